@@ -1,0 +1,123 @@
+"""Propagator, one time step and observables (oracle; test infrastructure).
+
+Paper passages followed:
+
+* Sec. II, Eq. 2: i hbar d(rho)/dt = [H, rho] + i L(rho), read with hbar = 1
+  as d(rho)/dt = -i [H, rho] + L(rho).
+* Sec. II, Eq. 3: L(rho) = sum_j gamma_j (A_j rho A_j^dag
+  - 1/2 {A_j^dag A_j, rho}); the printed anticommutator lacks its rho and is
+  read as {A_j^dag A_j, rho}.
+* Sec. IV.B and Table III: the solve has a "Taylor approximation" stage that
+  builds the propagator U = exp(-i H dt) once, and a "unitary evolution"
+  stage that applies U rho U^dag repeatedly.  The paper gives no time
+  discretisation for the dissipator; the reading used is one Lie-Trotter
+  step per iteration -- rotate with U, then an explicit-Euler dissipator step
+  on the rotated matrix:
+
+      rho_u      = U rho_k U^dag
+      rho_d      = rho_u + dt * sum_j gamma_j (A_j rho_u A_j^dag
+                                       - 1/2 (A_j^dag A_j rho_u + rho_u A_j^dag A_j))
+      sink      += dt * sum_j gamma_j [tr(A_j^dag A_j rho_u) - tr(A_j rho_u A_j^dag)]
+      rho_{k+1}  = Herm(rho_d) * (1 - sink) / tr Herm(rho_d),
+                   Herm(X) = (X + X^dag) / 2
+
+  The last two lines are identities in exact arithmetic: they book the
+  probability that a decoherence operator moves out of a truncated basis
+  (the "sink") and remove rounding drift of the trace and of Hermiticity.
+
+The oracle's propagator comes from an eigendecomposition of H, deliberately
+not the Taylor series the library uses.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import model
+
+
+class System:
+    """Everything the oracle needs about one workload, built from its dict."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        self.occ = model.basis(wl["atoms"], wl["photon_cap"],
+                               wl.get("exc_min", 0), wl.get("exc_max", -1))
+        self.n = self.occ.shape[0]
+        self.terms = model.hamiltonian_terms(wl, self.occ)
+        self.h = np.zeros((self.n, self.n))
+        for coef, _, w in self.terms:
+            self.h += coef * w.toarray()
+        self.jumps = model.jump_operators(wl, self.occ)
+        self.dt = float(wl["dt"])
+        self.u = propagator(self.h, self.dt)
+
+
+def propagator(h, dt):
+    """U = exp(-i H dt) for real symmetric H, via H = V diag(lam) V^T."""
+    lam, v = np.linalg.eigh(h)
+    return (v * np.exp(-1j * lam * dt)) @ v.T
+
+
+def dissipator(rho, jumps):
+    """D(rho) = sum_j gamma_j (A rho A^dag - 1/2 (A^dag A rho + rho A^dag A))."""
+    out = np.zeros_like(rho)
+    for gamma, a, ada in jumps:
+        out += gamma * (a @ (a @ rho.conj().T).conj().T
+                        - 0.5 * (ada @ rho + (ada @ rho.conj().T).conj().T))
+    return out
+
+
+def lost_rate(rho, jumps):
+    """sum_j gamma_j [tr(A^dag A rho) - tr(A rho A^dag)]: probability per unit
+    time that the decoherence operators move out of the basis."""
+    total = 0.0
+    for gamma, a, ada in jumps:
+        t_out = (ada @ rho).trace()
+        t_in = (a @ (a @ rho.conj().T).conj().T).trace()
+        total += gamma * (t_out - t_in).real
+    return total
+
+
+def step(rho, sink, u, jumps, dt):
+    """One time step (rotate, dissipate, book sink, symmetrise, renormalise).
+    Returns (rho_{k+1}, sink_{k+1})."""
+    rho_u = u @ rho @ u.conj().T
+    rho_d = rho_u + dt * dissipator(rho_u, jumps)
+    sink = sink + dt * lost_rate(rho_u, jumps)
+    herm = 0.5 * (rho_d + rho_d.conj().T)
+    rho_next = herm * ((1.0 - sink) / herm.trace().real)
+    return rho_next, sink
+
+
+def evolve(sysm: System, rho0, n_steps, sink0=0.0, record_every=0):
+    """n_steps time steps from rho0.  Returns (rho, sink[, records]) where
+    records holds (k, rho_k, sink_k) every record_every steps."""
+    rho, sink = rho0.astype(np.complex128), float(sink0)
+    rec = []
+    for k in range(1, n_steps + 1):
+        rho, sink = step(rho, sink, sysm.u, sysm.jumps, sysm.dt)
+        if record_every and k % record_every == 0:
+            rec.append((k, rho.copy(), sink))
+    return (rho, sink, rec) if record_every else (rho, sink)
+
+
+def observe(rho, sink):
+    """Populations Re rho_ss, trace and sink."""
+    pops = np.real(np.diag(rho)).copy()
+    return pops, float(pops.sum()), float(sink)
+
+
+def superoperator(sysm: System):
+    """Matrix M of the step map on row-major vec(rho), for tiny N:
+    M = (I + dt L_D) (U kron conj(U)), with L_D the dissipator's
+    superoperator.  Uses vec(A X B) = (A kron B^T) vec(X) (row-major)."""
+    n = sysm.n
+    eye = np.eye(n)
+    ld = np.zeros((n * n, n * n), dtype=np.complex128)
+    for gamma, a, ada in sysm.jumps:
+        ad = a.toarray().astype(np.complex128)
+        add = ada.toarray().astype(np.complex128)
+        ld += gamma * (np.kron(ad, ad.conj())
+                       - 0.5 * (np.kron(add, eye) + np.kron(eye, add.T)))
+    rot = np.kron(sysm.u, sysm.u.conj())
+    return (np.eye(n * n) + sysm.dt * ld) @ rot
