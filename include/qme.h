@@ -1,0 +1,220 @@
+/*
+ * qme.h -- C ABI of the MI355X quantum-master-equation solver.
+ *
+ * The library time-steps the density matrix rho of a finite-dimensional
+ * cavity-QED system (Jaynes-Cummings-Hubbard / Tavis-Cummings-Hubbard
+ * lattices of cavities with two-level atoms) under the quantum master
+ * equation of Sec. II, Eqs. 2-3 of Li, Miao, Ozhigov, "Supercomputer model of
+ * finite-dimensional quantum electrodynamics applications" (hbar = 1):
+ *
+ *     d rho / dt = -i [H, rho] + sum_j gamma_j (A_j rho A_j^dag
+ *                                 - 1/2 {A_j^dag A_j, rho}).
+ *
+ * The calls follow the paper's modelling scheme (Sec. II): fix the basis of
+ * "matter + field" states (qme_basis), build the Hamiltonian and the
+ * decoherence operators (qme_hamiltonian), solve the equation by repeated
+ * time steps (qme_step; the "Taylor approximation" stage builds the
+ * propagator once, the "unitary evolution" stage applies it, Sec. IV.B,
+ * Table III) and read out state probabilities (qme_observe; the quantities
+ * plotted in Figs. 4-8).
+ *
+ * One time step k -> k+1 (propagator U = exp(-i H dt), built once):
+ *     rho_u     = U rho_k U^dag
+ *     rho_d     = rho_u + dt * sum_j gamma_j (A_j rho_u A_j^dag
+ *                                   - 1/2 (A_j^dag A_j rho_u + rho_u A_j^dag A_j))
+ *     sink     += dt * sum_j gamma_j [tr(A_j^dag A_j rho_u) - tr(A_j rho_u A_j^dag)]
+ *     rho_{k+1} = Herm(rho_d) * (1 - sink) / tr Herm(rho_d)
+ * where "sink" is the probability that decoherence moved out of a truncated
+ * basis and Herm(X) is the Hermitian part of X.
+ *
+ * Conventions for every call:
+ *   - Return a qme_status; nothing aborts, throws or exits across the ABI.
+ *     On an error nothing the caller can observe has been modified and
+ *     qme_last_error() describes the failure (thread-local text).
+ *   - Arguments are validated before any device work is enqueued.
+ *   - Pointers named *_dev are device pointers (HIP); all others are host.
+ *     Input arrays are copied during the call; the caller keeps ownership.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *     qme_step and qme_batch_step only enqueue work; calls that return host
+ *     results (qme_observe, qme_get_state, qme_adjoint) synchronise the stream.
+ *   - A context is used by one host thread / stream at a time.
+ */
+#ifndef QME_H
+#define QME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QME_OK = 0,
+  QME_E_ARG = 1,          /* invalid argument (null pointer, bad index, NaN, ...) */
+  QME_E_SIZE = 2,         /* buffer too small or problem too large */
+  QME_E_DEVICE = 3,       /* a HIP runtime call failed */
+  QME_E_NUMERIC = 4,      /* non-finite values or trace <= 0 in the state */
+  QME_E_STATE = 5,        /* call not valid for this context / state */
+  QME_E_UNSUPPORTED = 6   /* precision or option not available */
+} qme_status;
+
+/* Arithmetic of the two dense complex products of each step. */
+typedef enum {
+  QME_FP64 = 0,    /* FP64 storage, FP64 MFMA products */
+  QME_FP32 = 1,    /* FP32 storage, FP32 MFMA products, FP64 dissipator/trace */
+  QME_BF16X3 = 2   /* FP32 storage, each FP32 operand split into three bf16
+                      planes, six bf16 MFMA cross products, FP32 accumulate */
+} qme_precision;
+
+/* Decoherence operators A_j (Sec. II, Eq. 3). */
+typedef enum {
+  QME_JUMP_PHOTON_LEAK = 0,   /* A = a_c, photon leaves cavity c */
+  QME_JUMP_ATOM_DECAY = 1,    /* A = sigma_ck = |g><e| of atom k of cavity c */
+  QME_JUMP_ATOM_DEPHASE = 2   /* A = sigma_ck^dag sigma_ck */
+} qme_jump_kind;
+
+/* Structure of the system.  Modes are ordered cavity by cavity: the photon
+ * mode of cavity c (levels 0..photon_cap[c]), then its atoms[c] two-level
+ * atoms.  The basis is every occupation tuple whose total excitation number
+ * lies in [exc_min, exc_max] (exc_max < 0: no upper bound), in ascending
+ * lexicographic order with mode 0 most significant (Kronecker order for a
+ * full tensor product).  This is the working-subspace selection of Sec. II
+ * (third point) and Sec. IV.B, Eqs. 10-11 (single-photon subspace). */
+typedef struct {
+  int32_t n_cavities;
+  const int32_t *atoms;        /* [n_cavities], >= 0 */
+  const int32_t *photon_cap;   /* [n_cavities], >= 0 */
+  int32_t exc_min;
+  int32_t exc_max;
+} qme_system;
+
+/* Photon hopping mu (a_a^dag a_b + a_b^dag a_a) between cavities a != b
+ * (Sec. IV.B, Eq. 12, tunnelling strength zeta). */
+typedef struct {
+  int32_t a, b;
+  double mu;
+} qme_hop;
+
+/* One decoherence channel: kind, cavity, atom index within the cavity
+ * (ignored for photon leak), rate gamma >= 0. */
+typedef struct {
+  int32_t kind, cavity, atom;
+  double gamma;
+} qme_jump;
+
+/* Hamiltonian (RWA, hbar = 1; Sec. IV.A Eq. 8b, Sec. IV.B Eq. 12):
+ *   H = sum_c omega_c a_c^dag a_c + sum_atoms omega_a sigma^dag sigma
+ *     + sum_atoms g (a_c^dag sigma + a_c sigma^dag)
+ *     + sum_hops mu (a_a^dag a_b + a_b^dag a_a)
+ * Atoms are numbered cavity-major. */
+typedef struct {
+  const double *omega_c;   /* [n_cavities] */
+  const double *omega_a;   /* [total atoms] */
+  const double *g;         /* [total atoms] */
+  int32_t n_hops;
+  const qme_hop *hops;     /* [n_hops] */
+  int32_t n_jumps;
+  const qme_jump *jumps;   /* [n_jumps] */
+  double dt;               /* time step, > 0 */
+} qme_params;
+
+typedef struct qme_ctx qme_ctx;
+
+/* ---------------------------------------------------------------- host only */
+
+/* Enumerate the basis.  Writes N to *n_states.  If occ is non-NULL and
+ * occ_rows >= N, also writes the occupation table, row-major N x n_modes
+ * (n_modes = n_cavities + total atoms).  occ == NULL is a size query
+ * (QME_OK); occ != NULL with occ_rows < N returns QME_E_SIZE (with *n_states
+ * set).  QME_E_SIZE also when N would exceed 2^20. */
+qme_status qme_basis(const qme_system *sys, int64_t *n_states, int32_t *occ,
+                     int64_t occ_rows);
+
+/* The Hamiltonian matrix restricted to the basis, as COO triplets sorted by
+ * (row, col) with duplicates summed.  Two-call pattern as for qme_basis:
+ * rows/cols/vals may be NULL for a size query; capacity < nnz gives
+ * QME_E_SIZE with *nnz set. */
+qme_status qme_hamiltonian_coo(const qme_system *sys, const qme_params *par,
+                               int64_t *nnz, int32_t *rows, int32_t *cols,
+                               double *vals, int64_t capacity);
+
+/* The propagator increment dU = exp(-i H dt) - I in FP64, computed on the
+ * host by the library's Taylor series (with scaling and squaring when
+ * |H dt|_1 > 1/2).  du_re / du_im: row-major n x n, n must equal N. */
+qme_status qme_propagator_host(const qme_system *sys, const qme_params *par,
+                               double *du_re, double *du_im, int64_t n);
+
+/* ------------------------------------------------------------- with a GPU */
+
+/* Build a context on the current HIP device: basis, Hamiltonian, FP64
+ * propagator (Taylor stage), decoherence tables, and the device copies of
+ * the propagator in the arithmetic of `precision`.  Synchronous. */
+qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
+                           int32_t precision, void *hip_stream, qme_ctx **out);
+
+/* Layout of a device state buffer: two planes (real, imaginary) of ld x ld
+ * elements each, row-major (ld >= n; rows and columns >= n are zero),
+ * elements FP64 for QME_FP64 and FP32 otherwise, followed by 64 bytes of
+ * FP64 scalars [sink, trace of the
+ * last rotated state, lost-probability rate of the last step, steps taken,
+ * last renormalisation factor, 0, 0, 0].  The caller allocates state_bytes
+ * of device memory (256-byte aligned) and owns it. */
+qme_status qme_state_layout(const qme_ctx *ctx, int64_t *n, int64_t *ld,
+                            int64_t *elem_bytes, size_t *state_bytes);
+
+/* Device workspace qme_step needs (caller-allocated, 256-byte aligned). */
+qme_status qme_workspace_size(const qme_ctx *ctx, size_t *bytes);
+
+/* Write a state: rho (host, row-major n x n FP64 planes, converted to the
+ * context precision, padding zeroed) and the sink scalar.  Synchronous. */
+qme_status qme_set_state(const qme_ctx *ctx, void *state_dev,
+                         const double *rho_re, const double *rho_im,
+                         double sink, void *hip_stream);
+
+/* Read a state back (row-major n x n FP64 planes; either may be NULL) and
+ * its sink (may be NULL).  Synchronous. */
+qme_status qme_get_state(const qme_ctx *ctx, const void *state_dev,
+                         double *rho_re, double *rho_im, double *sink,
+                         void *hip_stream);
+
+/* Advance the state by n_steps >= 0 time steps on hip_stream.  The state
+ * buffer holds rho_{k+n} afterwards (never a pending scale).  Asynchronous;
+ * the workspace must stay allocated until the stream reaches this point. */
+qme_status qme_step(qme_ctx *ctx, void *state_dev, int64_t n_steps,
+                    void *workspace_dev, void *hip_stream);
+
+/* Populations p_s = Re rho_ss (FP64, [N] or NULL), trace sum_s p_s and sink
+ * (each may be NULL).  Synchronous.  Returns QME_E_NUMERIC when a population
+ * is not finite or the trace is not positive (outputs still written). */
+qme_status qme_observe(const qme_ctx *ctx, const void *state_dev,
+                       double *populations, double *trace, double *sink,
+                       void *hip_stream);
+
+/* The planar complex product used by every step, exposed on its own:
+ *     C = alpha * A * op(M) + beta * X,   op(M) = M^H if conj_m else M^T,
+ * on ld x ld row-major planes in device memory (FP64 for QME_FP64, FP32 for
+ * QME_FP32; x_re / x_im may be NULL when beta == 0).  Both A and M are read
+ * by rows.  lower != 0 computes only the tile x tile blocks on or below the
+ * diagonal.  tile: 128 or 64 (FP32), 64 or 32 (FP64); ld must be a multiple
+ * of tile.  C must not overlap A, M or X.  Asynchronous on hip_stream. */
+qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
+                     const void *a_im_dev, const void *m_re_dev, const void *m_im_dev,
+                     const void *x_re_dev, const void *x_im_dev, void *c_re_dev,
+                     void *c_im_dev, double alpha, double beta, int32_t conj_m,
+                     int32_t lower, int32_t tile, void *hip_stream);
+
+/* Release a context and its device tables. NULL is ignored. */
+void qme_destroy(qme_ctx *ctx);
+
+/* Text of the last error on this thread ("" if none). */
+const char *qme_last_error(void);
+
+/* Library version string. */
+const char *qme_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QME_H */

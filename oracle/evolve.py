@@ -44,9 +44,10 @@ class System:
                                wl.get("exc_min", 0), wl.get("exc_max", -1))
         self.n = self.occ.shape[0]
         self.terms = model.hamiltonian_terms(wl, self.occ)
-        self.h = np.zeros((self.n, self.n))
+        h = None
         for coef, _, w in self.terms:
-            self.h += coef * w.toarray()
+            h = coef * w if h is None else h + coef * w
+        self.h = h.toarray()
         self.jumps = model.jump_operators(wl, self.occ)
         self.dt = float(wl["dt"])
         self.u = propagator(self.h, self.dt)
@@ -58,24 +59,54 @@ def propagator(h, dt):
     return (v * np.exp(-1j * lam * dt)) @ v.T
 
 
+def _sandwich(a, x):
+    """A x A^dag for a real sparse A (so A^dag = A^T): (A (A x)^T)^T."""
+    y = a @ x
+    return (a @ np.ascontiguousarray(y.T)).T
+
+
+def _right(m, x):
+    """x M for a real symmetric sparse M: (M x^T)^T."""
+    return (m @ np.ascontiguousarray(x.T)).T
+
+
+def _anticommutator_operator(jumps):
+    """K = sum_j gamma_j A_j^dag A_j (a sparse sum)."""
+    k = None
+    for gamma, _, ada in jumps:
+        k = gamma * ada if k is None else k + gamma * ada
+    return k
+
+
 def dissipator(rho, jumps):
-    """D(rho) = sum_j gamma_j (A rho A^dag - 1/2 (A^dag A rho + rho A^dag A))."""
+    """D(rho) = sum_j gamma_j A_j rho A_j^dag - 1/2 (K rho + rho K),
+    K = sum_j gamma_j A_j^dag A_j.
+
+    Every decoherence operator here has real matrix elements, so A^dag is A^T
+    and K is real symmetric.  A channel whose projected A_j has no non-zero
+    element (every arrival outside the basis) contributes no jump term."""
     out = np.zeros_like(rho)
-    for gamma, a, ada in jumps:
-        out += gamma * (a @ (a @ rho.conj().T).conj().T
-                        - 0.5 * (ada @ rho + (ada @ rho.conj().T).conj().T))
+    if not jumps:
+        return out
+    k = _anticommutator_operator(jumps)
+    out -= 0.5 * (k @ rho + _right(k, rho))
+    for gamma, a, _ in jumps:
+        if a.nnz:
+            out += gamma * _sandwich(a, rho)
     return out
 
 
 def lost_rate(rho, jumps):
     """sum_j gamma_j [tr(A^dag A rho) - tr(A rho A^dag)]: probability per unit
-    time that the decoherence operators move out of the basis."""
-    total = 0.0
-    for gamma, a, ada in jumps:
-        t_out = (ada @ rho).trace()
-        t_in = (a @ (a @ rho.conj().T).conj().T).trace()
-        total += gamma * (t_out - t_in).real
-    return total
+    time that the decoherence operators move out of the basis.  Uses
+    tr(M X) = sum_ij M_ij X_ji and tr(A X A^T) = sum_ij A_ij (A X)_ij."""
+    if not jumps:
+        return 0.0
+    total = _anticommutator_operator(jumps).multiply(rho.T).sum().real
+    for gamma, a, _ in jumps:
+        if a.nnz:
+            total -= gamma * a.multiply(a @ rho).sum().real
+    return float(total)
 
 
 def step(rho, sink, u, jumps, dt):

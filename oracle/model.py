@@ -224,11 +224,10 @@ def hamiltonian_terms(wl, occ):
 
 def hamiltonian(wl, occ) -> np.ndarray:
     """Dense real symmetric H (float64)."""
-    n = occ.shape[0]
-    h = np.zeros((n, n))
+    h = None
     for coef, _, w in hamiltonian_terms(wl, occ):
-        h += coef * w.toarray()
-    return h
+        h = coef * w if h is None else h + coef * w
+    return h.toarray()
 
 
 def jump_word(md: Modes, kind, cavity, atom_in_cavity):

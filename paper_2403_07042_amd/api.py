@@ -1,0 +1,161 @@
+"""Python front end of the solver: marshals a workload description into the
+C ABI structures and wraps a context.  PyTorch provides device memory and the
+stream; every step of the method runs in libqme.so."""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+from . import _lib as L
+
+
+class Marshal:
+    """C structures for one workload dict (keeps the arrays alive)."""
+
+    def __init__(self, wl: dict):
+        atoms = list(wl["atoms"])
+        nc = len(atoms)
+        self._atoms = (c_int32 * nc)(*atoms)
+        self._caps = (c_int32 * nc)(*wl["photon_cap"])
+        self.system = L.System(nc, self._atoms, self._caps, int(wl.get("exc_min", 0)),
+                               int(wl.get("exc_max", -1)))
+        na = int(sum(atoms))
+        self._oc = (c_double * nc)(*wl["omega_c"])
+        self._oa = (c_double * max(na, 1))(*(wl["omega_a"] or [0.0]))
+        self._g = (c_double * max(na, 1))(*(wl["g"] or [0.0]))
+        hops = wl.get("hops", [])
+        jumps = wl.get("jumps", [])
+        self._hops = (L.Hop * max(len(hops), 1))(*[L.Hop(int(a), int(b), float(m)) for a, b, m in hops])
+        self._jumps = (L.Jump * max(len(jumps), 1))(
+            *[L.Jump(int(k), int(c), int(a), float(gm)) for k, c, a, gm in jumps])
+        self.params = L.Params(self._oc, self._oa, self._g, len(hops), self._hops,
+                               len(jumps), self._jumps, float(wl["dt"]))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def basis(wl: dict) -> np.ndarray:
+    """Occupation table (N x n_modes, int32) of the workload's basis."""
+    lib = L.load()
+    m = Marshal(wl)
+    n = c_int64(0)
+    L.check(lib.qme_basis(byref(m.system), byref(n), None, 0))
+    n_modes = len(wl["atoms"]) + int(sum(wl["atoms"]))
+    occ = np.zeros((n.value, n_modes), dtype=np.int32)
+    L.check(lib.qme_basis(byref(m.system), byref(n), occ.ctypes.data_as(POINTER(c_int32)),
+                          n.value))
+    return occ
+
+
+def hamiltonian_coo(wl: dict):
+    """(rows, cols, vals) of H in the basis."""
+    lib = L.load()
+    m = Marshal(wl)
+    nnz = c_int64(0)
+    L.check(lib.qme_hamiltonian_coo(byref(m.system), byref(m.params), byref(nnz), None,
+                                    None, None, 0))
+    r = np.zeros(nnz.value, np.int32)
+    c = np.zeros(nnz.value, np.int32)
+    v = np.zeros(nnz.value, np.float64)
+    L.check(lib.qme_hamiltonian_coo(byref(m.system), byref(m.params), byref(nnz),
+                                    r.ctypes.data_as(POINTER(c_int32)),
+                                    c.ctypes.data_as(POINTER(c_int32)), _dptr(v), nnz.value))
+    return r, c, v
+
+
+def propagator_increment(wl: dict, n: int) -> np.ndarray:
+    """dU = exp(-i H dt) - I computed by the library's FP64 Taylor stage."""
+    lib = L.load()
+    m = Marshal(wl)
+    re = np.zeros((n, n))
+    im = np.zeros((n, n))
+    L.check(lib.qme_propagator_host(byref(m.system), byref(m.params), _dptr(re), _dptr(im), n))
+    return re + 1j * im
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a HIP device is required")
+    return torch
+
+
+class Solver:
+    """One context on the current HIP device plus a torch-owned state buffer
+    and workspace."""
+
+    def __init__(self, wl: dict, precision: str = "fp32", stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.lib = L.load()
+        self.wl = wl
+        self._m = Marshal(wl)
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = c_void_p()
+        L.check(self.lib.qme_hamiltonian(byref(self._m.system), byref(self._m.params),
+                                         L.PRECISIONS[precision], self._sptr(), byref(ctx)))
+        self.ctx = ctx
+        n, ld, eb, sb = c_int64(), c_int64(), c_int64(), c_size_t()
+        L.check(self.lib.qme_state_layout(ctx, byref(n), byref(ld), byref(eb), byref(sb)))
+        self.n, self.ld, self.elem, self.state_bytes = n.value, ld.value, eb.value, sb.value
+        ws = c_size_t()
+        L.check(self.lib.qme_workspace_size(ctx, byref(ws)))
+        self.workspace_bytes = ws.value
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.state = torch.zeros(self.state_bytes, dtype=torch.uint8, device=dev)
+        self.workspace = torch.zeros(max(self.workspace_bytes, 256), dtype=torch.uint8, device=dev)
+
+    def _sptr(self):
+        return c_void_p(self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.lib.qme_destroy(self.ctx)
+            self.ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_state(self):
+        """A fresh zeroed device state buffer of this context's layout."""
+        return self.torch.zeros(self.state_bytes, dtype=self.torch.uint8, device=self.state.device)
+
+    def set_rho(self, rho: np.ndarray, sink: float = 0.0, state=None):
+        rho = np.asarray(rho, dtype=np.complex128)
+        if rho.shape != (self.n, self.n):
+            raise ValueError("rho has the wrong shape")
+        re = np.ascontiguousarray(rho.real)
+        im = np.ascontiguousarray(rho.imag)
+        st = self.state if state is None else state
+        L.check(self.lib.qme_set_state(self.ctx, c_void_p(st.data_ptr()), _dptr(re), _dptr(im),
+                                       float(sink), self._sptr()))
+
+    def get_rho(self, state=None):
+        st = self.state if state is None else state
+        re = np.zeros((self.n, self.n))
+        im = np.zeros((self.n, self.n))
+        sink = c_double()
+        L.check(self.lib.qme_get_state(self.ctx, c_void_p(st.data_ptr()), _dptr(re), _dptr(im),
+                                       byref(sink), self._sptr()))
+        return re + 1j * im, sink.value
+
+    def step(self, n_steps: int, state=None):
+        st = self.state if state is None else state
+        L.check(self.lib.qme_step(self.ctx, c_void_p(st.data_ptr()), int(n_steps),
+                                  c_void_p(self.workspace.data_ptr()), self._sptr()))
+
+    def observe(self, state=None):
+        st = self.state if state is None else state
+        pops = np.zeros(self.n)
+        tr, sink = c_double(), c_double()
+        L.check(self.lib.qme_observe(self.ctx, c_void_p(st.data_ptr()), _dptr(pops),
+                                     byref(tr), byref(sink), self._sptr()))
+        return pops, tr.value, sink.value

@@ -1,0 +1,347 @@
+// Device-side entry points of the C ABI: context build (tables and the
+// propagator on the device), state layout and transfer, the time-step driver
+// and the observables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+#include "device.hpp"
+#include "model.hpp"
+#include "qme.h"
+
+using namespace qme;
+
+#define QME_GUARD_BEGIN try {
+#define QME_GUARD_END                                      \
+  }                                                        \
+  catch (const std::bad_alloc &) {                         \
+    set_error("out of host memory");                       \
+    return QME_E_SIZE;                                     \
+  }                                                        \
+  catch (const std::exception &e) {                        \
+    set_error(std::string("internal error: ") + e.what()); \
+    return QME_E_STATE;                                    \
+  }
+
+#define HIP_OK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));               \
+      return QME_E_DEVICE;                                                        \
+    }                                                                             \
+  } while (0)
+
+namespace qme {
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+void pick_tiles(qme_ctx *c) {
+  // Products on matrix cores want large tiles; the padded leading dimension
+  // must be a multiple of every tile used.
+  if (c->precision == QME_FP64) {
+    c->tile1 = c->n >= 256 ? 64 : 32;
+    c->tile2 = c->tile1;
+  } else {
+    c->tile1 = c->n >= 1024 ? 128 : 64;
+    c->tile2 = c->n >= 1024 ? 128 : 64;
+  }
+  c->ld = round_up(c->n, std::max(c->tile1, c->tile2));
+}
+
+size_t plane_elems(const qme_ctx *c) { return size_t(c->ld) * size_t(c->ld); }
+
+size_t state_bytes(const qme_ctx *c) { return 2 * plane_elems(c) * c->elem + 64; }
+
+qme_status check_device(const qme_ctx *c) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev != c->device) HIP_OK(hipSetDevice(c->device));
+  return QME_OK;
+}
+
+template <typename T>
+static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
+                            hipStream_t s) {
+  const size_t pe = plane_elems(c);
+  T *x_re = static_cast<T *>(state), *x_im = x_re + pe;
+  double *aux = reinterpret_cast<double *>(x_im + pe);
+  T *y_re = static_cast<T *>(ws), *y_im = y_re + pe;
+  T *z_re = y_im + pe, *z_im = z_re + pe;
+  const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
+
+  CgemmArgs<T> g1{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
+  CgemmArgs<T> g2{y_re, y_im, u_re, u_im, y_re, y_im, z_re, z_im, c->ld, T(1), T(1)};
+  DissArgs<T> da{z_re, z_im, x_re, x_im, c->ld, c->n, c->model.dt, c->d, c->leak,
+                 c->pi, c->cg, c->jt.n_gather, aux};
+  for (int64_t k = 0; k < n_steps; ++k) {
+    hipError_t e;
+    if constexpr (sizeof(T) == 4) {
+      e = launch_cgemm_f32(g1, c->tile1, true, false, s);
+      if (e == hipSuccess) e = launch_cgemm_f32(g2, c->tile2, true, true, s);
+    } else {
+      e = launch_cgemm_f64(g1, c->tile1, true, false, s);
+      if (e == hipSuccess) e = launch_cgemm_f64(g2, c->tile2, true, true, s);
+    }
+    if (e == hipSuccess) e = launch_trace<T>(da, s);
+    if (e == hipSuccess) e = launch_dissipate<T>(da, s);
+    if (e != hipSuccess) {
+      set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return QME_E_DEVICE;
+    }
+  }
+  return QME_OK;
+}
+
+}  // namespace qme
+
+extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
+                                      int32_t precision, void *hip_stream, qme_ctx **out) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!out) { set_error("out is NULL"); return QME_E_ARG; }
+  *out = nullptr;
+  if (!par) { set_error("params is NULL"); return QME_E_ARG; }
+  if (precision != QME_FP64 && precision != QME_FP32) {
+    if (precision == QME_BF16X3) { set_error("BF16X3 precision is not built"); return QME_E_UNSUPPORTED; }
+    set_error("unknown precision");
+    return QME_E_ARG;
+  }
+  auto c = std::make_unique<qme_ctx>();
+  std::string err;
+  if (!build_model(sys, par, c->model, err)) { set_error(err); return QME_E_ARG; }
+  if (!enumerate_basis(c->model, err)) { set_error(err); return QME_E_SIZE; }
+  c->precision = precision;
+  c->elem = precision == QME_FP64 ? 8 : 4;
+  c->n = c->model.n;
+  pick_tiles(c.get());
+  std::vector<int32_t> r, cc;
+  std::vector<double> v;
+  hamiltonian_coo(c->model, r, cc, v);
+  c->h = to_csr(c->n, r, cc, v);
+  if (!propagator_increment(c->model, c->h, c->du_re_host, c->du_im_host, err)) {
+    set_error(err);
+    return QME_E_NUMERIC;
+  }
+  c->jt = jump_tables(c->model);
+
+  HIP_OK(hipGetDevice(&c->device));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const size_t pe = plane_elems(c.get());
+  // propagator planes, padded with zeros, in the storage type
+  std::vector<char> buf(pe * c->elem);
+  for (int plane = 0; plane < 2; ++plane) {
+    const std::vector<double> &src = plane ? c->du_im_host : c->du_re_host;
+    std::memset(buf.data(), 0, buf.size());
+    for (int64_t i = 0; i < c->n; ++i)
+      for (int64_t j = 0; j < c->n; ++j) {
+        double x = src[size_t(i) * c->n + j];
+        size_t o = size_t(i) * c->ld + j;
+        if (c->elem == 8) reinterpret_cast<double *>(buf.data())[o] = x;
+        else reinterpret_cast<float *>(buf.data())[o] = float(x);
+      }
+    void **dst = plane ? &c->du_im : &c->du_re;
+    HIP_OK(hipMalloc(dst, buf.size()));
+    HIP_OK(hipMemcpyAsync(*dst, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  const int64_t n = c->n;
+  HIP_OK(hipMalloc(&c->d, sizeof(double) * n));
+  HIP_OK(hipMalloc(&c->leak, sizeof(double) * n));
+  HIP_OK(hipMalloc(&c->diag, sizeof(double) * (n + 8)));
+  HIP_OK(hipMemcpy(c->d, c->jt.d.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(c->leak, c->jt.leak.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  const size_t ng = size_t(std::max(1, c->jt.n_gather)) * n;
+  HIP_OK(hipMalloc(&c->pi, sizeof(int32_t) * ng));
+  HIP_OK(hipMalloc(&c->cg, sizeof(double) * ng));
+  if (c->jt.n_gather > 0) {
+    HIP_OK(hipMemcpy(c->pi, c->jt.pi.data(), sizeof(int32_t) * c->jt.pi.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->cg, c->jt.cg.data(), sizeof(double) * c->jt.cg.size(), hipMemcpyHostToDevice));
+  }
+  *out = c.release();
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_state_layout(const qme_ctx *c, int64_t *n, int64_t *ld,
+                                       int64_t *elem_bytes, size_t *bytes) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (n) *n = c->n;
+  if (ld) *ld = c->ld;
+  if (elem_bytes) *elem_bytes = c->elem;
+  if (bytes) *bytes = state_bytes(c);
+  return QME_OK;
+}
+
+extern "C" qme_status qme_workspace_size(const qme_ctx *c, size_t *bytes) {
+  set_error("");
+  if (!c || !bytes) { set_error("NULL argument"); return QME_E_ARG; }
+  *bytes = 4 * plane_elems(c) * c->elem;
+  return QME_OK;
+}
+
+extern "C" qme_status qme_set_state(const qme_ctx *c, void *state, const double *rho_re,
+                                    const double *rho_im, double sink, void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!c || !state || !rho_re || !rho_im) { set_error("NULL argument"); return QME_E_ARG; }
+  if (!std::isfinite(sink)) { set_error("sink is not finite"); return QME_E_ARG; }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  const size_t pe = plane_elems(c);
+  std::vector<char> buf(state_bytes(c), 0);
+  for (int64_t i = 0; i < c->n; ++i)
+    for (int64_t j = 0; j < c->n; ++j) {
+      size_t src = size_t(i) * c->n + j, o = size_t(i) * c->ld + j;
+      double xr = rho_re[src], xi = rho_im[src];
+      if (!std::isfinite(xr) || !std::isfinite(xi)) { set_error("rho is not finite"); return QME_E_ARG; }
+      if (c->elem == 8) {
+        reinterpret_cast<double *>(buf.data())[o] = xr;
+        reinterpret_cast<double *>(buf.data())[pe + o] = xi;
+      } else {
+        reinterpret_cast<float *>(buf.data())[o] = float(xr);
+        reinterpret_cast<float *>(buf.data())[pe + o] = float(xi);
+      }
+    }
+  double *aux = reinterpret_cast<double *>(buf.data() + 2 * pe * c->elem);
+  aux[0] = sink;
+  aux[4] = 1.0;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  HIP_OK(hipMemcpyAsync(state, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_get_state(const qme_ctx *c, const void *state, double *rho_re,
+                                    double *rho_im, double *sink, void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!c || !state) { set_error("NULL argument"); return QME_E_ARG; }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  const size_t pe = plane_elems(c);
+  std::vector<char> buf(state_bytes(c));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  HIP_OK(hipMemcpyAsync(buf.data(), state, buf.size(), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < c->n; ++i)
+    for (int64_t j = 0; j < c->n; ++j) {
+      size_t dst = size_t(i) * c->n + j, o = size_t(i) * c->ld + j;
+      double xr, xi;
+      if (c->elem == 8) {
+        xr = reinterpret_cast<double *>(buf.data())[o];
+        xi = reinterpret_cast<double *>(buf.data())[pe + o];
+      } else {
+        xr = reinterpret_cast<float *>(buf.data())[o];
+        xi = reinterpret_cast<float *>(buf.data())[pe + o];
+      }
+      if (rho_re) rho_re[dst] = xr;
+      if (rho_im) rho_im[dst] = xi;
+    }
+  if (sink) *sink = reinterpret_cast<double *>(buf.data() + 2 * pe * c->elem)[0];
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_step(qme_ctx *c, void *state, int64_t n_steps, void *ws,
+                               void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!c || !state || !ws) { set_error("NULL argument"); return QME_E_ARG; }
+  if (n_steps < 0) { set_error("n_steps < 0"); return QME_E_ARG; }
+  if ((reinterpret_cast<uintptr_t>(state) | reinterpret_cast<uintptr_t>(ws)) & 255) {
+    set_error("state and workspace must be 256-byte aligned");
+    return QME_E_ARG;
+  }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (c->elem == 8) return step_impl<double>(c, state, n_steps, ws, s);
+  return step_impl<float>(c, state, n_steps, ws, s);
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_observe(const qme_ctx *c, const void *state, double *pops,
+                                  double *trace, double *sink, void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!c || !state) { set_error("NULL argument"); return QME_E_ARG; }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const size_t pe = plane_elems(c);
+  hipError_t e;
+  if (c->elem == 8) e = launch_diag<double>(static_cast<const double *>(state), c->ld, c->n, c->diag, s);
+  else e = launch_diag<float>(static_cast<const float *>(state), c->ld, c->n, c->diag, s);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return QME_E_DEVICE; }
+  std::vector<double> host(c->n + 8);
+  const char *auxp = static_cast<const char *>(state) + 2 * pe * c->elem;
+  HIP_OK(hipMemcpyAsync(host.data(), c->diag, sizeof(double) * c->n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(host.data() + c->n, auxp, 64, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  double tr = 0.0;
+  bool finite = true;
+  for (int64_t u = 0; u < c->n; ++u) {
+    tr += host[u];
+    finite = finite && std::isfinite(host[u]);
+  }
+  if (pops) std::memcpy(pops, host.data(), sizeof(double) * c->n);
+  if (trace) *trace = tr;
+  if (sink) *sink = host[c->n];
+  if (!finite || !std::isfinite(host[c->n]) || !(tr > 0.0)) {
+    set_error("state is not finite or its trace is not positive");
+    return QME_E_NUMERIC;
+  }
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
+                                const void *a_im, const void *m_re, const void *m_im,
+                                const void *x_re, const void *x_im, void *c_re, void *c_im,
+                                double alpha, double beta, int32_t conj_m, int32_t lower,
+                                int32_t tile, void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!a_re || !a_im || !m_re || !m_im || !c_re || !c_im) { set_error("NULL operand"); return QME_E_ARG; }
+  if (beta != 0.0 && (!x_re || !x_im)) { set_error("beta != 0 needs X"); return QME_E_ARG; }
+  if (ld <= 0 || tile <= 0 || ld % tile != 0) { set_error("ld must be a positive multiple of tile"); return QME_E_ARG; }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if (precision == QME_FP32) {
+    if (tile != 128 && tile != 64) { set_error("FP32 tile must be 128 or 64"); return QME_E_ARG; }
+    CgemmArgs<float> g{static_cast<const float *>(a_re), static_cast<const float *>(a_im),
+                       static_cast<const float *>(m_re), static_cast<const float *>(m_im),
+                       static_cast<const float *>(x_re), static_cast<const float *>(x_im),
+                       static_cast<float *>(c_re), static_cast<float *>(c_im), ld,
+                       float(alpha), float(beta)};
+    e = launch_cgemm_f32(g, tile, conj_m != 0, lower != 0, s);
+  } else if (precision == QME_FP64) {
+    if (tile != 64 && tile != 32) { set_error("FP64 tile must be 64 or 32"); return QME_E_ARG; }
+    CgemmArgs<double> g{static_cast<const double *>(a_re), static_cast<const double *>(a_im),
+                        static_cast<const double *>(m_re), static_cast<const double *>(m_im),
+                        static_cast<const double *>(x_re), static_cast<const double *>(x_im),
+                        static_cast<double *>(c_re), static_cast<double *>(c_im), ld, alpha, beta};
+    e = launch_cgemm_f64(g, tile, conj_m != 0, lower != 0, s);
+  } else {
+    set_error("qme_cgemm supports QME_FP32 and QME_FP64");
+    return QME_E_UNSUPPORTED;
+  }
+  if (e != hipSuccess) { set_error(std::string("launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
+  return QME_OK;
+  QME_GUARD_END
+}
+
+qme_ctx::~qme_ctx() {
+  for (void *p : {du_re, du_im, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg})
+    if (p) (void)hipFree(p);
+}
+
+extern "C" void qme_destroy(qme_ctx *c) { delete c; }

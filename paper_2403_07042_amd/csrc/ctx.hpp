@@ -1,0 +1,37 @@
+// The opaque context behind qme_ctx (internal).
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "model.hpp"
+#include "qme.h"
+
+struct qme_ctx {
+  qme::Model model;
+  qme::Csr h;                         // Hamiltonian (host, FP64)
+  qme::JumpTables jt;
+  std::vector<double> du_re_host, du_im_host;   // dU = U - I, FP64, n x n
+  int precision = QME_FP32;
+  int64_t elem = 4;                   // storage bytes per real
+  int64_t n = 0, ld = 0;
+  int tile1 = 64, tile2 = 64;         // tiles of the two products of a step
+  int device = 0;
+  // device tables (owned)
+  void *du_re = nullptr, *du_im = nullptr;   // dU planes, ld x ld, storage type
+  double *d = nullptr, *leak = nullptr, *diag = nullptr;
+  int32_t *pi = nullptr;
+  double *cg = nullptr;
+
+  qme_ctx() = default;
+  qme_ctx(const qme_ctx &) = delete;
+  qme_ctx &operator=(const qme_ctx &) = delete;
+  ~qme_ctx();   // frees the device tables
+};
+
+namespace qme {
+int64_t round_up(int64_t x, int64_t m);
+size_t plane_elems(const qme_ctx *c);
+size_t state_bytes(const qme_ctx *c);
+}  // namespace qme

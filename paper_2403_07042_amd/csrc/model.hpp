@@ -1,0 +1,94 @@
+// Host-side model of a cavity-QED system: basis, Hamiltonian, decoherence
+// tables and the FP64 propagator (the "Taylor approximation" stage).
+//
+// Everything here runs on the CPU and is independent of HIP, so it can be
+// checked without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qme.h"
+
+namespace qme {
+
+// Copy of a validated system + parameters, with the mode layout derived.
+struct Model {
+  int n_cav = 0;
+  std::vector<int> atoms, cap;
+  int exc_lo = 0, exc_hi = 0;      // effective window
+  int n_modes = 0;
+  std::vector<int> photon_mode;     // per cavity
+  std::vector<int> atom_mode;       // per atom (cavity-major)
+  std::vector<int> atom_cavity;     // cavity of each atom
+  std::vector<int> mode_cap;
+  std::vector<int> first_atom;      // per cavity, index of its first atom
+
+  // parameters
+  std::vector<double> omega_c, omega_a, g;
+  std::vector<qme_hop> hops;
+  std::vector<qme_jump> jumps;
+  double dt = 0.0;
+  bool has_params = false;
+
+  // basis
+  int64_t n = 0;
+  std::vector<int32_t> occ;         // n x n_modes, lexicographic order
+  // cnt[m * (exc_hi + 1) + s]: completions of modes m.. given prefix sum s
+  // that land in the window; rank() sums it over the levels below a tuple's
+  std::vector<uint64_t> cnt;
+
+  int64_t rank(const int32_t *levels) const;   // index in basis or -1
+};
+
+// Sparse real matrix, CSR.
+struct Csr {
+  int64_t n = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+// Per-parameter derivative terms dH/dtheta_p (for gradients), as COO.
+struct TermCoo {
+  std::vector<int32_t> row, col;
+  std::vector<double> val;
+};
+
+// Decoherence tables in the gather form used by the dissipator:
+//   (A_j rho A_j^dag)[u,v] = c_j[u] c_j[v] rho[pi_j[u], pi_j[v]],
+// with pi_j[u] the basis state that A_j maps onto u (-1 if none).
+// Only channels with at least one arrival inside the basis are kept in
+// pi/cg ("gather channels").  cg = sqrt(gamma_j) c_j.
+struct JumpTables {
+  int n_gather = 0;
+  std::vector<int32_t> gather_channel;   // original jump index of each gather channel
+  std::vector<int32_t> pi;               // n_gather x n
+  std::vector<double> cg;                // n_gather x n
+  std::vector<double> d;                 // sum_j gamma_j (A_j^dag A_j)_uu
+  std::vector<double> leak;              // sum_j gamma_j |a_j(u)|^2 [A_j u leaves the basis]
+  // per original jump, unit-rate tables (for rate gradients)
+  std::vector<int32_t> unit_pi;          // n_jumps x n
+  std::vector<double> unit_c;            // n_jumps x n (c_j, not scaled)
+  std::vector<double> unit_ada;          // n_jumps x n diag of A^dag A
+};
+
+bool build_model(const qme_system *sys, const qme_params *par, Model &m,
+                 std::string &err);
+bool enumerate_basis(Model &m, std::string &err);
+void hamiltonian_coo(const Model &m, std::vector<int32_t> &r,
+                     std::vector<int32_t> &c, std::vector<double> &v);
+Csr to_csr(int64_t n, const std::vector<int32_t> &r,
+           const std::vector<int32_t> &c, const std::vector<double> &v);
+// dH/dtheta for each parameter in the gradient order (g per atom, mu per hop).
+std::vector<TermCoo> hamiltonian_terms(const Model &m);
+JumpTables jump_tables(const Model &m);
+// dU = exp(-i H dt) - I, row-major n x n planes; exactly symmetric.
+bool propagator_increment(const Model &m, const Csr &h, std::vector<double> &re,
+                          std::vector<double> &im, std::string &err);
+
+// Thread-local error text of the ABI.
+void set_error(const std::string &s);
+
+}  // namespace qme

@@ -1,0 +1,136 @@
+"""Parity of the full GPU time step (both MFMA products, decoherence,
+symmetrisation, renormalisation, sink) with the CPU oracle on the same seeded
+inputs, element by element, plus the invariants the method guarantees."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import closed_forms as cf
+from oracle import evolve as ev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2403_07042_amd")
+
+# tolerance on max_ab |rho_gpu - rho_oracle| (complex modulus)
+TOL = {"fp64": 1e-11, "fp32": 1e-5}
+TRACE_TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+def gpu_run(wl, precision, checkpoints):
+    """Run the workload on the GPU; returns {k: (rho, sink, trace)}."""
+    sol = P.Solver(wl, precision)
+    occ = P.basis(wl)
+    sol.set_rho(W.initial_rho(wl, occ))
+    out, done = {}, 0
+    for k in sorted(checkpoints):
+        print(f"{wl.get('name', 'wl')} {precision} -> step {k}", flush=True)
+        sol.step(k - done)
+        done = k
+        rho, sink = sol.get_rho()
+        _, trace, sink2 = sol.observe()
+        assert sink == sink2
+        out[k] = (rho, sink, trace)
+    sol.close()
+    return out
+
+
+def oracle_run(wl, checkpoints):
+    s = ev.System(wl)
+    rho, sink = W.initial_rho(wl, s.occ), 0.0
+    out, done = {}, 0
+    for k in sorted(checkpoints):
+        rho, sink = ev.evolve(s, rho, k - done, sink0=sink)
+        done = k
+        out[k] = (rho.copy(), sink)
+    return out
+
+
+def compare(wl, precision, checkpoints, tol=None, ref=None):
+    ref = ref or oracle_run(wl, checkpoints)
+    got = gpu_run(wl, precision, checkpoints)
+    tol = tol or TOL[precision]
+    for k in checkpoints:
+        rho, sink, trace = got[k]
+        rref, sref = ref[k]
+        err = np.abs(rho - rref).max()
+        assert err < tol, (k, err)
+        assert np.array_equal(rho, rho.conj().T)          # exactly Hermitian
+        assert np.all(np.imag(np.diag(rho)) == 0.0)
+        assert abs(sink - sref) < TRACE_TOL[precision]
+        assert abs(trace - (1.0 - sink)) < TRACE_TOL[precision]
+    return got
+
+
+def small_open_system(window=(0, -1)):
+    return {
+        "name": "small_open", "atoms": [1, 2], "photon_cap": [2, 1],
+        "exc_min": window[0], "exc_max": window[1],
+        "omega_c": [1.0, 1.1], "omega_a": [0.9, 1.0, 1.05], "g": [0.2, 0.15, 0.1],
+        "hops": [(0, 1, 0.07)],
+        "jumps": [(W.PHOTON_LEAK, 0, -1, 0.05), (W.PHOTON_LEAK, 1, -1, 0.02),
+                  (W.ATOM_DECAY, 1, 1, 0.04), (W.ATOM_DEPHASE, 0, 0, 0.03),
+                  (W.ATOM_DEPHASE, 1, 0, 0.01)],
+        "dt": 0.05, "steps": 300, "init": {"kind": "haar", "seed": 11},
+    }
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("window", [(0, -1), (1, 2)])
+def test_small_open_system_all_jump_kinds(precision, window):
+    compare(small_open_system(window), precision, [1, 7, 300])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_jaynes_cummings_n8(precision):
+    wl = W.jc_single()
+    got = compare(wl, precision, [1, 1000, 10000])
+    # closed form of the damped Jaynes-Cummings model at t = 100 (first-order
+    # splitting error ~3e-6, see the oracle pins)
+    rho = got[10000][0]
+    p1, p2, _ = cf.damped_jc(0.01, 0.001, 100.0)
+    assert abs(rho[2, 2].real - p1) < 5e-6 and abs(rho[1, 1].real - p2) < 5e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tch_n144(precision):
+    wl = W.tch_2x2()
+    compare(wl, precision, [1, 1000, 5000])
+
+
+def test_lattice_small_with_sink():
+    wl = W.photon_lattice(6, 5, mu=0.2, g=0.15, gamma=0.05, dt=0.1, start=(0, 2))
+    got = compare(wl, "fp32", [10, 200])
+    assert got[200][1] > 1e-3        # population really left through the boundary
+    compare(wl, "fp64", [10, 200])
+
+
+def test_lattice_2048_fp32_closed_form():
+    """Full-size 32 x 32 lattice (N = 2048), 1000 FP32 steps, against the
+    sine-mode closed form; the boundary leak moves less than 1e-20 of
+    probability by t = 10 for a photon started at the centre."""
+    wl = W.photon_lattice()
+    occ = P.basis(wl)
+    got = gpu_run(wl, "fp32", [1, 1000])
+    for k in (1, 1000):
+        ref = cf.lattice_rho(occ, 1, 32, 32, 0.01, 0.01, 1.0, k * wl["dt"], wl["centre_site"])
+        rho, sink, trace = got[k]
+        assert np.abs(rho - ref).max() < 1e-5
+        assert abs(trace - 1.0) < 1e-6 and sink < 1e-15
+
+
+def test_lattice_2048_fp64_against_oracle_steps():
+    wl = W.photon_lattice()
+    compare(wl, "fp64", [1, 3])
+
+
+def test_state_roundtrip_and_zero_steps():
+    wl = W.tch_2x2()
+    sol = P.Solver(wl, "fp64")
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    sol.set_rho(rho0, sink=0.25)
+    sol.step(0)
+    rho, sink = sol.get_rho()
+    assert np.array_equal(rho, rho0) and sink == 0.25
+    sol.close()
