@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the quantum-master-equation time step on one MI355X.
+
+Workload: 2D photon motion (Sec. IV.B) on a 32 x 32 lattice of cavities with
+one two-level atom each, single-excitation subspace (N = 2048), hopping
+mu = 0.01, coupling g = 0.01, photon leak 0.001 on the 124 boundary sites,
+dt = 0.01, photon started at site (16, 16).  One "step" is one full time step
+of the method: rho_u = U rho U^dag as two planar complex MFMA products, the
+FP64 trace/sink pass and the fused decoherence/symmetrisation/renormalisation
+pass.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line (rank 0, N = 1): value = FP32 time steps per second,
+plus the FP64 method's rate, per-kernel durations from HIP events recorded
+on the launch stream during the timed region, the roofline entry of the
+dominant kernel, and the CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QME steps/sec at N=2048 (FP32 MFMA vs FP64) + adjoint grad time/step"
+PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
+PEAK_FP64_MFMA = 78.6       # TFLOP/s, MI355X dense FP64 matrix
+PEAK_HBM = 8000.0           # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps timed for the CPU baseline (0: skip)")
+    ap.add_argument("--legs", default="fp32,fp64", help="comma list of fp32, fp64")
+    ap.add_argument("--tiles32", default="", help="tile1,tile2 override for the FP32 leg")
+    ap.add_argument("--tiles64", default="", help="tile1,tile2 override for the FP64 leg")
+    return ap.parse_args()
+
+
+def timed_leg(P, W, torch, wl, precision, steps, warmup, tiles=""):
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, precision)
+    if tiles:
+        sol.set_tiles(*[int(x) for x in tiles.split(",")])
+    sol.set_rho(rho0)
+    sol.step(warmup)
+    torch.cuda.synchronize()
+    sol.set_rho(rho0)
+    sol.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sol.profile_read()
+    sol.profile(False)
+    pops, trace, sink = sol.observe()
+    out = {
+        "seconds": t1 - t0,
+        "steps_per_s": steps / (t1 - t0),
+        "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "kernels_us": {k: (1e3 * ms / max(cnt, 1)) for k, (ms, cnt) in prof.items()},
+        "tiles": tiles or "default",
+        "pops": pops, "trace": trace, "sink": sink, "n": sol.n, "ld": sol.ld,
+    }
+    sol.close()
+    return out
+
+
+def cpu_baseline(W, wl, gpu_leg, steps):
+    """The CPU oracle (NumPy complex128) timed on the host cores on a bounded
+    sample of the same workload, plus the parity of the GPU run's final
+    populations with the lattice's closed form."""
+    from oracle import closed_forms as cf
+    from oracle import evolve as ev
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    s = ev.System(wl)
+    rho = W.initial_rho(wl, s.occ)
+    t0 = time.perf_counter()
+    sink = 0.0
+    for _ in range(steps):
+        rho, sink = ev.step(rho, sink, s.u, s.jumps, s.dt)
+    t1 = time.perf_counter()
+    base = {"value": steps / (t1 - t0), "unit": "steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{steps} time steps of the N=2048 lattice workload (NumPy complex128, "
+                      f"BLAS threads={threads}); propagator build excluded"}
+    parity = None
+    if gpu_leg is not None:
+        k = gpu_leg["k"]
+        ref = cf.lattice_rho(s.occ, 1, 32, 32, 0.01, 0.01, 1.0, k * wl["dt"], wl["centre_site"])
+        import numpy as np
+        dpop = float(np.abs(gpu_leg["pops"] - np.real(np.diag(ref))).max())
+        parity = {"after_steps": k, "max_abs_dpop_vs_closed_form": dpop,
+                  "trace_error": abs(gpu_leg["trace"] - (1.0 - gpu_leg["sink"]))}
+    return base, parity
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the solver is single-GPU); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2403_07042_amd as P
+    import workloads as W
+
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    wl = W.photon_lattice(steps=args.steps)
+    n = 2048
+    flops_product = 8.0 * n ** 3          # one complex N^3 product
+    flops_step = 2 * flops_product        # 16 N^3 per step (algorithmic)
+    res = {}
+    if "fp32" in legs:
+        res["fp32"] = timed_leg(P, W, torch, wl, "fp32", args.steps, args.warmup, args.tiles32)
+    if "fp64" in legs and args.fp64_steps > 0:
+        res["fp64"] = timed_leg(P, W, torch, wl, "fp64", args.fp64_steps, min(args.warmup, 5),
+                                args.tiles64)
+
+    main_leg = res.get("fp32") or res.get("fp64")
+    prec = "fp32" if "fp32" in res else "fp64"
+    peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_FP64_MFMA
+    avg_us = main_leg["kernels_us"]["product_full"]
+    achieved = flops_product / (avg_us * 1e-6) / 1e12
+    roofline = {"bound": "mfma", "kernel": f"cgemm_{prec} (first product, full tiles)",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "algorithmic_per_launch": f"8*N^3 = {flops_product:.4g} flop (N=2048)"}
+
+    cpu, parity = None, None
+    if args.cpu_steps > 0:
+        gl = {"k": args.steps, **main_leg} if prec == "fp32" else {"k": args.fp64_steps, **main_leg}
+        cpu, parity = cpu_baseline(W, wl, gl, args.cpu_steps)
+
+    line = {
+        "metric": METRIC,
+        "value": main_leg["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "jch_lattice_32x32_single_excitation_n2048", "N": n,
+                   "ld": main_leg["ld"], "dt": 0.01, "mu": 0.01, "g": 0.01,
+                   "boundary_leak": 0.001, "precision": prec},
+        "effective_tflops": flops_step * main_leg["steps_per_s"] / 1e12,
+        "effective_frac_of_peak": flops_step * main_leg["steps_per_s"] / 1e12 / peak,
+        "kernels_us": main_leg["kernels_us"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "adjoint_ms_per_step": None,
+    }
+    if "fp64" in res:
+        f = res["fp64"]
+        line["fp64"] = {"steps_per_s": f["steps_per_s"], "ms_per_step": f["ms_per_step"],
+                        "steps": args.fp64_steps, "kernels_us": f["kernels_us"],
+                        "effective_frac_of_fp64_peak":
+                            flops_step * f["steps_per_s"] / 1e12 / PEAK_FP64_MFMA}
+        if "fp32" in res:
+            line["fp32_speedup_over_fp64"] = res["fp32"]["steps_per_s"] / f["steps_per_s"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

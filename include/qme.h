@@ -204,6 +204,24 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
                      void *c_im_dev, double alpha, double beta, int32_t conj_m,
                      int32_t lower, int32_t tile, void *hip_stream);
 
+/* Tile edge of the two products of each step (the autotuner's knob):
+ * tile1 for T = rho + dU rho, tile2 for the lower-triangle product.
+ * FP32 tiles: 128 or 64; FP64 tiles: 64 or 32.  Each must divide the state's
+ * leading dimension ld (qme_state_layout), else QME_E_ARG. */
+qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
+
+/* Per-kernel timing of qme_step with HIP events recorded on the caller's
+ * stream around every launch (the tracing facility used by the benchmark).
+ * enable != 0 starts recording (and clears earlier records); 0 stops it. */
+qme_status qme_profile_enable(qme_ctx *ctx, int32_t enable);
+
+/* Synchronises on the recorded events and returns, per kernel kind, the
+ * summed duration in milliseconds and the number of launches since the last
+ * enable: kind 0 = first product (full), 1 = second product (lower tiles),
+ * 2 = trace/sink pass, 3 = decoherence pass.  Arrays of 4 (either may be
+ * NULL).  Recording stays enabled. */
+qme_status qme_profile_read(qme_ctx *ctx, double *total_ms, int64_t *launches);
+
 /* Release a context and its device tables. NULL is ignored. */
 void qme_destroy(qme_ctx *ctx);
 

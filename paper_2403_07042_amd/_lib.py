@@ -61,6 +61,9 @@ SIGNATURES = {
     "qme_cgemm": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32, c_int32,
                             c_int32, c_void_p]),
+    "qme_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
+    "qme_profile_enable": (c_int32, [c_void_p, c_int32]),
+    "qme_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "qme_destroy": (None, [c_void_p]),
     "qme_last_error": (c_char_p, []),
     "qme_version": (c_char_p, []),

@@ -159,3 +159,19 @@ class Solver:
         L.check(self.lib.qme_observe(self.ctx, c_void_p(st.data_ptr()), _dptr(pops),
                                      byref(tr), byref(sink), self._sptr()))
         return pops, tr.value, sink.value
+
+    def set_tiles(self, tile1: int, tile2: int):
+        L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
+
+    # ---------------------------------------------------------- profiling
+    KINDS = ("product_full", "product_lower", "trace", "dissipate")
+
+    def profile(self, enable: bool = True):
+        L.check(self.lib.qme_profile_enable(self.ctx, int(enable)))
+
+    def profile_read(self):
+        """{kind: (total_ms, launches)} since profiling was enabled."""
+        ms = (c_double * 4)()
+        cnt = (c_int64 * 4)()
+        L.check(self.lib.qme_profile_read(self.ctx, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KINDS)}

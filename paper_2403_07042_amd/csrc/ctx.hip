@@ -42,14 +42,14 @@ namespace qme {
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 void pick_tiles(qme_ctx *c) {
-  // Products on matrix cores want large tiles; the padded leading dimension
-  // must be a multiple of every tile used.
+  // Measured on MI355X at N = 2048: 64 x 64 FP32 tiles (4 workgroups per CU)
+  // beat 128 x 128 (one wave per SIMD) on both products, and 32 x 32 FP64
+  // tiles beat 64 x 64.  The padded leading dimension is a multiple of the
+  // tile; qme_set_tiles may pick a larger tile when it divides ld.
   if (c->precision == QME_FP64) {
-    c->tile1 = c->n >= 256 ? 64 : 32;
-    c->tile2 = c->tile1;
+    c->tile1 = c->tile2 = 32;
   } else {
-    c->tile1 = c->n >= 1024 ? 128 : 64;
-    c->tile2 = c->n >= 1024 ? 128 : 64;
+    c->tile1 = c->tile2 = 64;
   }
   c->ld = round_up(c->n, std::max(c->tile1, c->tile2));
 }
@@ -63,6 +63,21 @@ qme_status check_device(const qme_ctx *c) {
   HIP_OK(hipGetDevice(&dev));
   if (dev != c->device) HIP_OK(hipSetDevice(c->device));
   return QME_OK;
+}
+
+// Records an event on s after a launch of `kind` (-1 marks the start of a
+// sequence) when profiling is on.
+static hipError_t mark(qme_ctx *c, hipStream_t s, int kind) {
+  if (!c->profiling) return hipSuccess;
+  if (c->events_used == c->events.size()) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    c->events.push_back(e);
+    c->event_kind.push_back(-1);
+  }
+  c->event_kind[c->events_used] = kind;
+  return hipEventRecord(static_cast<hipEvent_t>(c->events[c->events_used++]), s);
 }
 
 template <typename T>
@@ -80,16 +95,21 @@ static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   DissArgs<T> da{z_re, z_im, x_re, x_im, c->ld, c->n, c->model.dt, c->d, c->leak,
                  c->pi, c->cg, c->jt.n_gather, aux};
   for (int64_t k = 0; k < n_steps; ++k) {
-    hipError_t e;
+    hipError_t e = mark(c, s, -1);
     if constexpr (sizeof(T) == 4) {
-      e = launch_cgemm_f32(g1, c->tile1, true, false, s);
+      if (e == hipSuccess) e = launch_cgemm_f32(g1, c->tile1, true, false, s);
+      if (e == hipSuccess) e = mark(c, s, 0);
       if (e == hipSuccess) e = launch_cgemm_f32(g2, c->tile2, true, true, s);
     } else {
-      e = launch_cgemm_f64(g1, c->tile1, true, false, s);
+      if (e == hipSuccess) e = launch_cgemm_f64(g1, c->tile1, true, false, s);
+      if (e == hipSuccess) e = mark(c, s, 0);
       if (e == hipSuccess) e = launch_cgemm_f64(g2, c->tile2, true, true, s);
     }
+    if (e == hipSuccess) e = mark(c, s, 1);
     if (e == hipSuccess) e = launch_trace<T>(da, s);
+    if (e == hipSuccess) e = mark(c, s, 2);
     if (e == hipSuccess) e = launch_dissipate<T>(da, s);
+    if (e == hipSuccess) e = mark(c, s, 3);
     if (e != hipSuccess) {
       set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
       return QME_E_DEVICE;
@@ -339,7 +359,57 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
   QME_GUARD_END
 }
 
+extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  auto ok = [&](int t) {
+    bool valid = c->precision == QME_FP64 ? (t == 64 || t == 32) : (t == 128 || t == 64);
+    return valid && c->ld % t == 0;
+  };
+  if (!ok(tile1) || !ok(tile2)) {
+    set_error("tile not supported for this precision or does not divide ld");
+    return QME_E_ARG;
+  }
+  c->tile1 = tile1;
+  c->tile2 = tile2;
+  return QME_OK;
+}
+
+extern "C" qme_status qme_profile_enable(qme_ctx *c, int32_t enable) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  c->profiling = enable != 0;
+  c->events_used = 0;
+  return QME_OK;
+}
+
+extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *launches) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  double ms[4] = {0, 0, 0, 0};
+  int64_t cnt[4] = {0, 0, 0, 0};
+  if (c->events_used > 0)
+    HIP_OK(hipEventSynchronize(static_cast<hipEvent_t>(c->events[c->events_used - 1])));
+  for (size_t i = 1; i < c->events_used; ++i) {
+    int k = c->event_kind[i];
+    if (k < 0 || k > 3) continue;
+    float t = 0.0f;
+    HIP_OK(hipEventElapsedTime(&t, static_cast<hipEvent_t>(c->events[i - 1]),
+                               static_cast<hipEvent_t>(c->events[i])));
+    ms[k] += t;
+    cnt[k] += 1;
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (total_ms) total_ms[k] = ms[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  return QME_OK;
+  QME_GUARD_END
+}
+
 qme_ctx::~qme_ctx() {
+  for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *p : {du_re, du_im, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg})
     if (p) (void)hipFree(p);
 }

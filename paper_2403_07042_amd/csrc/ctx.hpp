@@ -24,6 +24,12 @@ struct qme_ctx {
   int32_t *pi = nullptr;
   double *cg = nullptr;
 
+  // per-kernel timing (qme_profile_enable / qme_profile_read)
+  bool profiling = false;
+  std::vector<void *> events;          // hipEvent_t pool
+  size_t events_used = 0;
+  std::vector<int> event_kind;         // kind of the launch ending at event i (-1: start)
+
   qme_ctx() = default;
   qme_ctx(const qme_ctx &) = delete;
   qme_ctx &operator=(const qme_ctx &) = delete;
