@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--legs", default="fp32,fp64", help="comma list of fp32, fp64")
+    ap.add_argument("--adjoint-steps", type=int, default=200,
+                    help="steps of the timed FP32 adjoint (0: skip)")
+    ap.add_argument("--checkpoint-every", type=int, default=32)
     ap.add_argument("--tiles32", default="", help="tile1,tile2 override for the FP32 leg")
     ap.add_argument("--tiles64", default="", help="tile1,tile2 override for the FP64 leg")
     return ap.parse_args()
@@ -74,6 +77,30 @@ def timed_leg(P, W, torch, wl, precision, steps, warmup, tiles=""):
     }
     sol.close()
     return out
+
+
+def adjoint_leg(P, W, torch, wl, steps, every):
+    """Wall time of one qme_adjoint call (forward with checkpoints, segment
+    recompute, three adjoint products per step, FP64 finalisation) for the
+    centre photon population, per step; and the tied gradients it returns."""
+    import numpy as np
+    occ = P.basis(wl)
+    site = wl["centre_site"]
+    obs = np.zeros(occ.shape[0])
+    obs[int(np.nonzero(occ[:, 2 * site] == 1)[0][0])] = 1.0
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(W.initial_rho(wl, occ))
+    sol.adjoint(min(steps, 8), obs, every)      # warm-up (allocations, kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, g = sol.adjoint(steps, obs, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol.close()
+    maps = W.tied_parameter_maps(wl)
+    return {"ms_per_step": 1e3 * (t1 - t0) / steps, "steps": steps, "checkpoint_every": every,
+            "value": f, "dvalue_dmu": float(g[maps["mu"]].sum()),
+            "dvalue_dg": float(g[maps["g"]].sum())}
 
 
 def cpu_baseline(W, wl, gpu_leg, steps):
@@ -131,6 +158,10 @@ def main():
         res["fp64"] = timed_leg(P, W, torch, wl, "fp64", args.fp64_steps, min(args.warmup, 5),
                                 args.tiles64)
 
+    adj = None
+    if args.adjoint_steps > 0:
+        adj = adjoint_leg(P, W, torch, wl, args.adjoint_steps, args.checkpoint_every)
+
     main_leg = res.get("fp32") or res.get("fp64")
     prec = "fp32" if "fp32" in res else "fp64"
     peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_FP64_MFMA
@@ -168,7 +199,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
-        "adjoint_ms_per_step": None,
+        "adjoint_ms_per_step": adj["ms_per_step"] if adj else None,
+        "adjoint": adj,
     }
     if "fp64" in res:
         f = res["fp64"]

@@ -191,18 +191,43 @@ qme_status qme_observe(const qme_ctx *ctx, const void *state_dev,
                        double *populations, double *trace, double *sink,
                        void *hip_stream);
 
-/* The planar complex product used by every step, exposed on its own:
- *     C = alpha * A * op(M) + beta * X,   op(M) = M^H if conj_m else M^T,
+/* Gradients of a final diagonal observable f = sum_s obs[s] Re rho_K[s,s]
+ * (rho_K: the state after n_steps steps from state0) with respect to the
+ * Hamiltonian couplings and the decoherence rates, by the adjoint of the
+ * time step (the parameter fit of the paper's fourth modelling point,
+ * Sec. II, needs them).  The forward pass keeps a checkpoint every
+ * checkpoint_every steps and recomputes each segment backwards.  Outputs:
+ * *value = f (may be NULL) and grad[n_atoms + n_hops + n_jumps] in the order
+ * g per atom (cavity-major), mu per hop, gamma per jump.  The Frechet
+ * derivative of exp(-i H dt) is evaluated on the host in FP64.  state0 is
+ * not modified.  workspace: device memory of at least
+ * qme_adjoint_workspace_size bytes (256-byte aligned).  Synchronous. */
+qme_status qme_adjoint(qme_ctx *ctx, const void *state0_dev, int64_t n_steps,
+                       int32_t checkpoint_every, const double *obs, double *value,
+                       double *grad, void *workspace_dev, size_t workspace_bytes,
+                       void *hip_stream);
+
+/* Device workspace qme_adjoint needs for these arguments. */
+qme_status qme_adjoint_workspace_size(const qme_ctx *ctx, int64_t n_steps,
+                                      int32_t checkpoint_every, size_t *bytes);
+
+/* The planar complex product used by every step and by the adjoint:
+ *     C = alpha * opA(A) * opB(B) + beta * X
  * on ld x ld row-major planes in device memory (FP64 for QME_FP64, FP32 for
- * QME_FP32; x_re / x_im may be NULL when beta == 0).  Both A and M are read
- * by rows.  lower != 0 computes only the tile x tile blocks on or below the
+ * QME_FP32; x_re / x_im may be NULL when beta == 0).  opA(A) = conj(A) if
+ * conj_a else A.  With b_rows != 0 the second operand (m_*) is B itself,
+ * read row-major; otherwise it is M and B = M^T, i.e. the operand is read by
+ * rows j.  opB = conj(B) if conj_b else B (so b_rows = 0, conj_b = 1 gives
+ * M^H).  lower != 0 computes only the tile x tile blocks on or below the
  * diagonal.  tile: 128 or 64 (FP32), 64 or 32 (FP64); ld must be a multiple
- * of tile.  C must not overlap A, M or X.  Asynchronous on hip_stream. */
+ * of tile.  C must not overlap A or B; C may equal X (accumulation).
+ * Asynchronous on hip_stream. */
 qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
                      const void *a_im_dev, const void *m_re_dev, const void *m_im_dev,
                      const void *x_re_dev, const void *x_im_dev, void *c_re_dev,
-                     void *c_im_dev, double alpha, double beta, int32_t conj_m,
-                     int32_t lower, int32_t tile, void *hip_stream);
+                     void *c_im_dev, double alpha, double beta, int32_t conj_a,
+                     int32_t conj_b, int32_t b_rows, int32_t lower, int32_t tile,
+                     void *hip_stream);
 
 /* Tile edge of the two products of each step (the autotuner's knob):
  * tile1 for T = rho + dU rho, tile2 for the lower-triangle product.

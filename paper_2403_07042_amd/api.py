@@ -160,6 +160,27 @@ class Solver:
                                      byref(tr), byref(sink), self._sptr()))
         return pops, tr.value, sink.value
 
+    def adjoint(self, n_steps: int, obs, checkpoint_every: int = 32, state=None):
+        """(f, grad) for f = sum_s obs[s] Re rho_K[s,s] after n_steps from the
+        given state (default: this solver's state, left unchanged); grad is
+        ordered g per atom, mu per hop, gamma per jump."""
+        st = self.state if state is None else state
+        obs = np.ascontiguousarray(np.asarray(obs, dtype=np.float64))
+        if obs.shape != (self.n,):
+            raise ValueError("obs must have one weight per basis state")
+        ws = c_size_t()
+        L.check(self.lib.qme_adjoint_workspace_size(self.ctx, int(n_steps), int(checkpoint_every),
+                                                    byref(ws)))
+        buf = self.torch.empty(max(ws.value, 256), dtype=self.torch.uint8, device=st.device)
+        n_par = int(sum(self.wl["atoms"])) + len(self.wl.get("hops", [])) + len(self.wl.get("jumps", []))
+        grad = np.zeros(max(n_par, 1))
+        val = c_double()
+        L.check(self.lib.qme_adjoint(self.ctx, c_void_p(st.data_ptr()), int(n_steps),
+                                     int(checkpoint_every), _dptr(obs), byref(val), _dptr(grad),
+                                     c_void_p(buf.data_ptr()), ws.value, self._sptr()))
+        del buf
+        return val.value, grad[:n_par]
+
     def set_tiles(self, tile1: int, tile2: int):
         L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
 

@@ -1,21 +1,28 @@
 // Planar complex GEMM on CDNA4 matrix cores (gfx950).
 //
-//   C = alpha * A * op(M) + beta * X,   op(M) = M^H or M^T,
+//   C = alpha * opA(A) * opB(B) + beta * X
 //
-// the two dense products of every time step ("unitary evolution" stage,
-// Sec. IV.B / Table III):
-//   T   = rho + dU rho      (A = dU, M = rho, rho Hermitian => rho = rho^H)
-//   rho_u = T + T conj(dU)  (A = T,  M = dU,  dU symmetric => conj(dU) = dU^H)
-// with dU = U - I so that the identity part of U is added exactly.
+//   opA(A) = A or conj(A)                         (CONJ_A)
+//   B by rows of M ("NT"):  opB = M^T or M^H       (CONJ_B), B[k][j] = M[j][k]
+//   B row-major ("NN"):     opB = B or conj(B)     (CONJ_B), B[k][j] = B[k][j]
+//
+// The products of a time step ("unitary evolution" stage, Sec. IV.B /
+// Table III) and of its adjoint, with dU = U - I so the identity part of U
+// is added exactly through X:
+//   forward  T     = rho + dU rho           A = dU,  M = rho (rho = rho^H)   NT, M^H
+//            rho_u = T + T conj(dU)         A = T,   M = dU  (dU symmetric)  NT, M^H, lower
+//   adjoint  X     = mu + conj(dU) mu       A = dU conj, M = mu (Hermitian)  NT, M^H
+//            lam   = X + X dU               A = X,   M = dU                  NT, M^T, lower
+//            G    += rho X                  A = rho, B = X                   NN
 //
 // Design (one workgroup per BM x BM output tile, 4 waves in a 2 x 2 grid):
-//   * both operands are read by rows, k contiguous: float4 global loads,
-//     staged through double-buffered LDS tiles [row][KT + pad];
-//   * the k index inside a K tile is permuted per lane half so that each
-//     lane fetches its 8 (FP32) or 4 (FP64) k values with two ds_read_b128;
-//   * a complex multiply-add is four real MFMA products; the sign of the
-//     imaginary cross terms is applied by negating one register fragment;
-//   * 'lower' launches only the tiles on or below the diagonal (Hermitian
+//   * operands read by rows (k contiguous for A and NT-B, j contiguous for
+//     NN-B) with 16-byte global loads, staged through double-buffered LDS;
+//   * for A and NT-B the k index inside a K tile is permuted per lane group
+//     so each lane fetches its k values with two ds_read_b128;
+//   * a complex multiply-add is four real MFMA products; conjugations and
+//     the minus sign of Ai*Bi are applied by negating register fragments;
+//   * LOWER launches only the tiles on or below the diagonal (Hermitian
 //     output), enumerated triangularly.
 #include "device.hpp"
 
@@ -28,9 +35,11 @@ namespace qme {
 
 static constexpr int kThreads = 256;
 
-// Tile index -> (bi, bj).  Full grid: row-major tiles with the launch order
-// remapped so that the blocks an XCD receives (block b goes to XCD b % 8)
-// form compact groups of tile rows (L2 reuse of A rows and M rows).
+enum : int { kConjA = 1, kConjB = 2, kBRow = 4 };
+
+// Tile index -> (bi, bj).  Full grid: the launch order is remapped so that the
+// blocks one XCD receives (block b runs on XCD b % 8) form compact groups of
+// tile rows, which share A rows and B tiles in that XCD's L2.
 __device__ __forceinline__ void tile_coords(int t, int tiles, bool lower, int &bi, int &bj) {
   if (lower) {
     int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
@@ -53,20 +62,36 @@ __device__ __forceinline__ void tile_coords(int t, int tiles, bool lower, int &b
   bj = in / rows;
 }
 
+// The four real products of one complex multiply-add, signs folded into
+// fragment negations.  a*/b*: fragments; mfma(x, y, acc) accumulates x*y.
+//   Cr += Ar Br - sA sB Ai Bi,   Ci += sB Ar Bi + sA Ai Br
+template <int OPS, typename V, typename S, typename F>
+__device__ __forceinline__ void cmac(V &cr, V &ci, S ar, S ai, S br, S bi, F mfma) {
+  constexpr bool ca = OPS & kConjA, cb = OPS & kConjB;
+  cr = mfma(ar, br, cr);
+  ci = mfma(ca ? -ai : ai, br, ci);
+  cr = mfma((ca != cb) ? ai : -ai, bi, cr);
+  ci = mfma(ar, cb ? -bi : bi, ci);
+}
+
 // ----------------------------------------------------------------- FP32
 // v_mfma_f32_32x32x2_f32: A 32x2 (lane l: row l%32, k-slot l/32), B 2x32
 // (lane l: k-slot l/32, col l%32), D 32x32 in 16 registers (lane l: col l%32,
 // register r: row 8*(r/4) + 4*(l/32) + r%4).
 
-template <int BM, bool CONJ, bool LOWER>
+template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
+  constexpr bool BROW = OPS & kBRow;
   constexpr int KT = 16;
-  constexpr int LDK = KT + 4;          // padded LDS row (floats)
+  constexpr int LDK = KT + 4;          // padded LDS row of A / NT-B (floats)
+  constexpr int LDJ = BM + 4;          // padded LDS row of NN-B (floats)
   constexpr int WM = BM / 2;           // wave tile
   constexpr int F = WM / 32;           // 32x32 blocks per wave side
   constexpr int PASSES = BM / 64;      // 64 rows per load pass (4 float4 per row)
+  constexpr int BSZ = BROW ? KT * LDJ : BM * LDK;
+  constexpr int BPASS = BROW ? (KT * BM / 4) / kThreads : PASSES;
   __shared__ float sA[2][2][BM * LDK];
-  __shared__ float sM[2][2][BM * LDK];
+  __shared__ float sB[2][2][BSZ];
 
   const int tiles = int(p.ld / BM);
   int bi, bj;
@@ -80,18 +105,27 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
   const int lr = tid >> 2, lk = (tid & 3) * 4;
   const float *ga_re = p.a_re + (int64_t(bi) * BM + lr) * ld + lk;
   const float *ga_im = p.a_im + (int64_t(bi) * BM + lr) * ld + lk;
-  const float *gm_re = p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
-  const float *gm_im = p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
+  // NT: rows j of M;  NN: rows k of B, columns bj*BM + ...
+  const int br_k = tid / (BM / 4), br_j = (tid % (BM / 4)) * 4;
+  const float *gb_re = BROW ? p.m_re + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
+                            : p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
+  const float *gb_im = BROW ? p.m_im + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
+                            : p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
 
-  floatx4 ra[PASSES][2], rm[PASSES][2];
+  floatx4 ra[PASSES][2], rb[BPASS > 0 ? BPASS : 1][2];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < PASSES; ++q) {
       const int64_t off = int64_t(q) * 64 * ld + k0;
       ra[q][0] = *reinterpret_cast<const floatx4 *>(ga_re + off);
       ra[q][1] = *reinterpret_cast<const floatx4 *>(ga_im + off);
-      rm[q][0] = *reinterpret_cast<const floatx4 *>(gm_re + off);
-      rm[q][1] = *reinterpret_cast<const floatx4 *>(gm_im + off);
+    }
+#pragma unroll
+    for (int q = 0; q < BPASS; ++q) {
+      const int64_t off = BROW ? (int64_t(k0) + q * (kThreads / (BM / 4))) * ld
+                               : int64_t(q) * 64 * ld + k0;
+      rb[q][0] = *reinterpret_cast<const floatx4 *>(gb_re + off);
+      rb[q][1] = *reinterpret_cast<const floatx4 *>(gb_im + off);
     }
   };
   auto lstore = [&](int st) {
@@ -100,8 +134,13 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
       const int o = (q * 64 + lr) * LDK + lk;
       *reinterpret_cast<floatx4 *>(&sA[st][0][o]) = ra[q][0];
       *reinterpret_cast<floatx4 *>(&sA[st][1][o]) = ra[q][1];
-      *reinterpret_cast<floatx4 *>(&sM[st][0][o]) = rm[q][0];
-      *reinterpret_cast<floatx4 *>(&sM[st][1][o]) = rm[q][1];
+    }
+#pragma unroll
+    for (int q = 0; q < BPASS; ++q) {
+      const int o = BROW ? (br_k + q * (kThreads / (BM / 4))) * LDJ + br_j
+                         : (q * 64 + lr) * LDK + lk;
+      *reinterpret_cast<floatx4 *>(&sB[st][0][o]) = rb[q][0];
+      *reinterpret_cast<floatx4 *>(&sB[st][1][o]) = rb[q][1];
     }
   };
 
@@ -113,6 +152,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
 #pragma unroll
       for (int r = 0; r < 16; ++r) { cr[a][b][r] = 0.0f; ci[a][b][r] = 0.0f; }
 
+  auto mfma = [](float x, float y, floatx16 acc) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
+  };
+
   const int nk = int(ld / KT);
   gload(0);
   lstore(0);
@@ -120,47 +163,46 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
   for (int kt = 0; kt < nk; ++kt) {
     const int st = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * KT);
-    float ar[F][8], ai[F][8], mr[F][8], mi[F][8];
+    float ar[F][8], ai[F][8], br[F][8], bi_[F][8];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       const int oa = (wm * WM + f * 32 + li) * LDK + h * 8;
-      const int om = (wn * WM + f * 32 + li) * LDK + h * 8;
       floatx4 x0 = *reinterpret_cast<const floatx4 *>(&sA[st][0][oa]);
       floatx4 x1 = *reinterpret_cast<const floatx4 *>(&sA[st][0][oa + 4]);
       floatx4 y0 = *reinterpret_cast<const floatx4 *>(&sA[st][1][oa]);
       floatx4 y1 = *reinterpret_cast<const floatx4 *>(&sA[st][1][oa + 4]);
-      floatx4 z0 = *reinterpret_cast<const floatx4 *>(&sM[st][0][om]);
-      floatx4 z1 = *reinterpret_cast<const floatx4 *>(&sM[st][0][om + 4]);
-      floatx4 w0 = *reinterpret_cast<const floatx4 *>(&sM[st][1][om]);
-      floatx4 w1 = *reinterpret_cast<const floatx4 *>(&sM[st][1][om + 4]);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         ar[f][e] = x0[e]; ar[f][e + 4] = x1[e];
         ai[f][e] = y0[e]; ai[f][e + 4] = y1[e];
-        mr[f][e] = z0[e]; mr[f][e + 4] = z1[e];
-        mi[f][e] = w0[e]; mi[f][e + 4] = w1[e];
       }
-    }
+      if constexpr (BROW) {
+        const int col = wn * WM + f * 32 + li;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < 8; ++s) {
+          br[f][s] = sB[st][0][(h * 8 + s) * LDJ + col];
+          bi_[f][s] = sB[st][1][(h * 8 + s) * LDJ + col];
+        }
+      } else {
+        const int om = (wn * WM + f * 32 + li) * LDK + h * 8;
+        floatx4 z0 = *reinterpret_cast<const floatx4 *>(&sB[st][0][om]);
+        floatx4 z1 = *reinterpret_cast<const floatx4 *>(&sB[st][0][om + 4]);
+        floatx4 w0 = *reinterpret_cast<const floatx4 *>(&sB[st][1][om]);
+        floatx4 w1 = *reinterpret_cast<const floatx4 *>(&sB[st][1][om + 4]);
 #pragma unroll
-      for (int a = 0; a < F; ++a) {
-#pragma unroll
-        for (int b = 0; b < F; ++b) {
-          // op(M) = M^H: Cr += Ar Mr + Ai Mi, Ci += Ai Mr - Ar Mi
-          // op(M) = M^T: Cr += Ar Mr - Ai Mi, Ci += Ai Mr + Ar Mi
-          cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a][s], mr[b][s], cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a][s], mr[b][s], ci[a][b], 0, 0, 0);
-          if (CONJ) {
-            cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a][s], mi[b][s], cr[a][b], 0, 0, 0);
-            ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar[a][s], mi[b][s], ci[a][b], 0, 0, 0);
-          } else {
-            cr[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[a][s], mi[b][s], cr[a][b], 0, 0, 0);
-            ci[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a][s], mi[b][s], ci[a][b], 0, 0, 0);
-          }
+        for (int e = 0; e < 4; ++e) {
+          br[f][e] = z0[e]; br[f][e + 4] = z1[e];
+          bi_[f][e] = w0[e]; bi_[f][e + 4] = w1[e];
         }
       }
     }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int a = 0; a < F; ++a)
+#pragma unroll
+        for (int b = 0; b < F; ++b)
+          cmac<OPS>(cr[a][b], ci[a][b], ar[a][s], ai[a][s], br[b][s], bi_[b][s], mfma);
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
@@ -193,15 +235,19 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
 // (lane l: k-slot l/16, col l%16), D 16x16 in 4 doubles (lane l: col l%16,
 // register r: row l/16 + 4*r).
 
-template <int BM, bool CONJ, bool LOWER>
+template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p) {
+  constexpr bool BROW = OPS & kBRow;
   constexpr int KT = 16;
   constexpr int LDK = KT + 2;          // padded LDS row (doubles)
+  constexpr int LDJ = BM + 2;
   constexpr int WM = BM / 2;
   constexpr int F = WM / 16;           // 16x16 blocks per wave side
   constexpr int PASSES = BM / 32;      // 32 rows per pass (8 x doublex2 per row)
+  constexpr int BSZ = BROW ? KT * LDJ : BM * LDK;
+  constexpr int BPASS = BROW ? (KT * BM / 2) / kThreads : PASSES;
   __shared__ double sA[2][2][BM * LDK];
-  __shared__ double sM[2][2][BM * LDK];
+  __shared__ double sB[2][2][BSZ];
 
   const int tiles = int(p.ld / BM);
   int bi, bj;
@@ -215,18 +261,26 @@ __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p
   const int lr = tid >> 3, lk = (tid & 7) * 2;
   const double *ga_re = p.a_re + (int64_t(bi) * BM + lr) * ld + lk;
   const double *ga_im = p.a_im + (int64_t(bi) * BM + lr) * ld + lk;
-  const double *gm_re = p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
-  const double *gm_im = p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
+  const int br_k = tid / (BM / 2), br_j = (tid % (BM / 2)) * 2;
+  const double *gb_re = BROW ? p.m_re + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
+                             : p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
+  const double *gb_im = BROW ? p.m_im + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
+                             : p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
 
-  doublex2 ra[PASSES][2], rm[PASSES][2];
+  doublex2 ra[PASSES][2], rb[BPASS > 0 ? BPASS : 1][2];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < PASSES; ++q) {
       const int64_t off = int64_t(q) * 32 * ld + k0;
       ra[q][0] = *reinterpret_cast<const doublex2 *>(ga_re + off);
       ra[q][1] = *reinterpret_cast<const doublex2 *>(ga_im + off);
-      rm[q][0] = *reinterpret_cast<const doublex2 *>(gm_re + off);
-      rm[q][1] = *reinterpret_cast<const doublex2 *>(gm_im + off);
+    }
+#pragma unroll
+    for (int q = 0; q < BPASS; ++q) {
+      const int64_t off = BROW ? (int64_t(k0) + q * (kThreads / (BM / 2))) * ld
+                               : int64_t(q) * 32 * ld + k0;
+      rb[q][0] = *reinterpret_cast<const doublex2 *>(gb_re + off);
+      rb[q][1] = *reinterpret_cast<const doublex2 *>(gb_im + off);
     }
   };
   auto lstore = [&](int st) {
@@ -235,8 +289,13 @@ __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p
       const int o = (q * 32 + lr) * LDK + lk;
       *reinterpret_cast<doublex2 *>(&sA[st][0][o]) = ra[q][0];
       *reinterpret_cast<doublex2 *>(&sA[st][1][o]) = ra[q][1];
-      *reinterpret_cast<doublex2 *>(&sM[st][0][o]) = rm[q][0];
-      *reinterpret_cast<doublex2 *>(&sM[st][1][o]) = rm[q][1];
+    }
+#pragma unroll
+    for (int q = 0; q < BPASS; ++q) {
+      const int o = BROW ? (br_k + q * (kThreads / (BM / 2))) * LDJ + br_j
+                         : (q * 32 + lr) * LDK + lk;
+      *reinterpret_cast<doublex2 *>(&sB[st][0][o]) = rb[q][0];
+      *reinterpret_cast<doublex2 *>(&sB[st][1][o]) = rb[q][1];
     }
   };
 
@@ -248,6 +307,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p
 #pragma unroll
       for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0.0; ci[a][b][r] = 0.0; }
 
+  auto mfma = [](double x, double y, doublex4 acc) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+  };
+
   const int nk = int(ld / KT);
   gload(0);
   lstore(0);
@@ -255,42 +318,40 @@ __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p
   for (int kt = 0; kt < nk; ++kt) {
     const int st = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * KT);
-    double ar[F][4], ai[F][4], mr[F][4], mi[F][4];
+    double ar[F][4], ai[F][4], br[F][4], bi_[F][4];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       const int oa = (wm * WM + f * 16 + li) * LDK + h * 4;
-      const int om = (wn * WM + f * 16 + li) * LDK + h * 4;
       doublex2 x0 = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa]);
       doublex2 x1 = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa + 2]);
       doublex2 y0 = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa]);
       doublex2 y1 = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa + 2]);
-      doublex2 z0 = *reinterpret_cast<const doublex2 *>(&sM[st][0][om]);
-      doublex2 z1 = *reinterpret_cast<const doublex2 *>(&sM[st][0][om + 2]);
-      doublex2 w0 = *reinterpret_cast<const doublex2 *>(&sM[st][1][om]);
-      doublex2 w1 = *reinterpret_cast<const doublex2 *>(&sM[st][1][om + 2]);
       ar[f][0] = x0[0]; ar[f][1] = x0[1]; ar[f][2] = x1[0]; ar[f][3] = x1[1];
       ai[f][0] = y0[0]; ai[f][1] = y0[1]; ai[f][2] = y1[0]; ai[f][3] = y1[1];
-      mr[f][0] = z0[0]; mr[f][1] = z0[1]; mr[f][2] = z1[0]; mr[f][3] = z1[1];
-      mi[f][0] = w0[0]; mi[f][1] = w0[1]; mi[f][2] = w1[0]; mi[f][3] = w1[1];
-    }
+      if constexpr (BROW) {
+        const int col = wn * WM + f * 16 + li;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-#pragma unroll
-      for (int a = 0; a < F; ++a) {
-#pragma unroll
-        for (int b = 0; b < F; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a][s], mr[b][s], cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a][s], mr[b][s], ci[a][b], 0, 0, 0);
-          if (CONJ) {
-            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a][s], mi[b][s], cr[a][b], 0, 0, 0);
-            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[a][s], mi[b][s], ci[a][b], 0, 0, 0);
-          } else {
-            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a][s], mi[b][s], cr[a][b], 0, 0, 0);
-            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a][s], mi[b][s], ci[a][b], 0, 0, 0);
-          }
+        for (int s = 0; s < 4; ++s) {
+          br[f][s] = sB[st][0][(h * 4 + s) * LDJ + col];
+          bi_[f][s] = sB[st][1][(h * 4 + s) * LDJ + col];
         }
+      } else {
+        const int om = (wn * WM + f * 16 + li) * LDK + h * 4;
+        doublex2 z0 = *reinterpret_cast<const doublex2 *>(&sB[st][0][om]);
+        doublex2 z1 = *reinterpret_cast<const doublex2 *>(&sB[st][0][om + 2]);
+        doublex2 w0 = *reinterpret_cast<const doublex2 *>(&sB[st][1][om]);
+        doublex2 w1 = *reinterpret_cast<const doublex2 *>(&sB[st][1][om + 2]);
+        br[f][0] = z0[0]; br[f][1] = z0[1]; br[f][2] = z1[0]; br[f][3] = z1[1];
+        bi_[f][0] = w0[0]; bi_[f][1] = w0[1]; bi_[f][2] = w1[0]; bi_[f][3] = w1[1];
       }
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int a = 0; a < F; ++a)
+#pragma unroll
+        for (int b = 0; b < F; ++b)
+          cmac<OPS>(cr[a][b], ci[a][b], ar[a][s], ai[a][s], br[b][s], bi_[b][s], mfma);
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
@@ -328,35 +389,49 @@ static hipError_t launch(K kernel, const Args &a, int tile, bool lower, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, bool conj_m, bool lower,
-                            hipStream_t s) {
-  if (a.ld % tile != 0) return hipErrorInvalidValue;
-#define QME_F32(BM)                                                                     \
-  if (tile == BM) {                                                                     \
-    if (conj_m) return lower ? launch(cgemm_f32_kernel<BM, true, true>, a, BM, true, s)  \
-                             : launch(cgemm_f32_kernel<BM, true, false>, a, BM, false, s); \
-    return lower ? launch(cgemm_f32_kernel<BM, false, true>, a, BM, true, s)             \
-                 : launch(cgemm_f32_kernel<BM, false, false>, a, BM, false, s);          \
+#define QME_KERNEL_TABLE(NAME, ARGS)                                                          \
+  template <int BM>                                                                           \
+  static hipError_t NAME##_dispatch(const ARGS &a, int ops, bool lower, hipStream_t s) {      \
+    switch (ops * 2 + (lower ? 1 : 0)) {                                                      \
+      case 0: return launch(NAME<BM, 0, false>, a, BM, false, s);                             \
+      case 1: return launch(NAME<BM, 0, true>, a, BM, true, s);                               \
+      case 2: return launch(NAME<BM, 1, false>, a, BM, false, s);                             \
+      case 3: return launch(NAME<BM, 1, true>, a, BM, true, s);                               \
+      case 4: return launch(NAME<BM, 2, false>, a, BM, false, s);                             \
+      case 5: return launch(NAME<BM, 2, true>, a, BM, true, s);                               \
+      case 6: return launch(NAME<BM, 3, false>, a, BM, false, s);                             \
+      case 7: return launch(NAME<BM, 3, true>, a, BM, true, s);                               \
+      case 8: return launch(NAME<BM, 4, false>, a, BM, false, s);                             \
+      case 9: return launch(NAME<BM, 4, true>, a, BM, true, s);                               \
+      case 10: return launch(NAME<BM, 5, false>, a, BM, false, s);                            \
+      case 11: return launch(NAME<BM, 5, true>, a, BM, true, s);                              \
+      case 12: return launch(NAME<BM, 6, false>, a, BM, false, s);                            \
+      case 13: return launch(NAME<BM, 6, true>, a, BM, true, s);                              \
+      case 14: return launch(NAME<BM, 7, false>, a, BM, false, s);                            \
+      case 15: return launch(NAME<BM, 7, true>, a, BM, true, s);                              \
+    }                                                                                         \
+    return hipErrorInvalidValue;                                                              \
   }
-  QME_F32(128)
-  QME_F32(64)
-#undef QME_F32
+
+QME_KERNEL_TABLE(cgemm_f32_kernel, CgemmArgs<float>)
+QME_KERNEL_TABLE(cgemm_f64_kernel, CgemmArgs<double>)
+#undef QME_KERNEL_TABLE
+
+static int ops_of(const GemmOps &o) {
+  return (o.conj_a ? kConjA : 0) | (o.conj_b ? kConjB : 0) | (o.b_rows ? kBRow : 0);
+}
+
+hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o, hipStream_t s) {
+  if (a.ld % tile != 0) return hipErrorInvalidValue;
+  if (tile == 128) return cgemm_f32_kernel_dispatch<128>(a, ops_of(o), o.lower, s);
+  if (tile == 64) return cgemm_f32_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, bool conj_m, bool lower,
-                            hipStream_t s) {
+hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, const GemmOps &o, hipStream_t s) {
   if (a.ld % tile != 0) return hipErrorInvalidValue;
-#define QME_F64(BM)                                                                     \
-  if (tile == BM) {                                                                     \
-    if (conj_m) return lower ? launch(cgemm_f64_kernel<BM, true, true>, a, BM, true, s)  \
-                             : launch(cgemm_f64_kernel<BM, true, false>, a, BM, false, s); \
-    return lower ? launch(cgemm_f64_kernel<BM, false, true>, a, BM, true, s)             \
-                 : launch(cgemm_f64_kernel<BM, false, false>, a, BM, false, s);          \
-  }
-  QME_F64(64)
-  QME_F64(32)
-#undef QME_F64
+  if (tile == 64) return cgemm_f64_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
+  if (tile == 32) return cgemm_f64_kernel_dispatch<32>(a, ops_of(o), o.lower, s);
   return hipErrorInvalidValue;
 }
 

@@ -81,35 +81,52 @@ static hipError_t mark(qme_ctx *c, hipStream_t s, int kind) {
 }
 
 template <typename T>
-static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
-                            hipStream_t s) {
+hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s) {
   const size_t pe = plane_elems(c);
-  T *x_re = static_cast<T *>(state), *x_im = x_re + pe;
-  double *aux = reinterpret_cast<double *>(x_im + pe);
-  T *y_re = static_cast<T *>(ws), *y_im = y_re + pe;
-  T *z_re = y_im + pe, *z_im = z_re + pe;
+  const T *x_re = static_cast<const T *>(in), *x_im = x_re + pe;
+  const double *aux_in = reinterpret_cast<const double *>(x_im + pe);
+  T *o_re = static_cast<T *>(out), *o_im = o_re + pe;
+  double *aux_out = reinterpret_cast<double *>(o_im + pe);
+  T *y_re = static_cast<T *>(y), *y_im = y_re + pe;
+  T *z_re = static_cast<T *>(z), *z_im = z_re + pe;
   const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
 
   CgemmArgs<T> g1{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
   CgemmArgs<T> g2{y_re, y_im, u_re, u_im, y_re, y_im, z_re, z_im, c->ld, T(1), T(1)};
-  DissArgs<T> da{z_re, z_im, x_re, x_im, c->ld, c->n, c->model.dt, c->d, c->leak,
-                 c->pi, c->cg, c->jt.n_gather, aux};
+  DissArgs<T> da{z_re, z_im, o_re, o_im, c->ld, c->n, c->model.dt, c->d, c->leak,
+                 c->pi, c->cg, c->jt.n_gather, aux_in, aux_out};
+  GemmOps o1, o2;
+  o1.conj_b = o2.conj_b = true;
+  o2.lower = true;
+  hipError_t e = mark(c, s, -1);
+  if constexpr (sizeof(T) == 4) {
+    if (e == hipSuccess) e = launch_cgemm_f32(g1, c->tile1, o1, s);
+    if (e == hipSuccess) e = mark(c, s, 0);
+    if (e == hipSuccess) e = launch_cgemm_f32(g2, c->tile2, o2, s);
+  } else {
+    if (e == hipSuccess) e = launch_cgemm_f64(g1, c->tile1, o1, s);
+    if (e == hipSuccess) e = mark(c, s, 0);
+    if (e == hipSuccess) e = launch_cgemm_f64(g2, c->tile2, o2, s);
+  }
+  if (e == hipSuccess) e = mark(c, s, 1);
+  if (e == hipSuccess) e = launch_trace<T>(da, s);
+  if (e == hipSuccess) e = mark(c, s, 2);
+  if (e == hipSuccess) e = launch_dissipate<T>(da, s);
+  if (e == hipSuccess) e = mark(c, s, 3);
+  return e;
+}
+
+template hipError_t step_once<float>(qme_ctx *, const void *, void *, void *, void *, hipStream_t);
+template hipError_t step_once<double>(qme_ctx *, const void *, void *, void *, void *, hipStream_t);
+
+template <typename T>
+static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
+                            hipStream_t s) {
+  const size_t pe = plane_elems(c);
+  T *y = static_cast<T *>(ws);
+  T *z = y + 2 * pe;
   for (int64_t k = 0; k < n_steps; ++k) {
-    hipError_t e = mark(c, s, -1);
-    if constexpr (sizeof(T) == 4) {
-      if (e == hipSuccess) e = launch_cgemm_f32(g1, c->tile1, true, false, s);
-      if (e == hipSuccess) e = mark(c, s, 0);
-      if (e == hipSuccess) e = launch_cgemm_f32(g2, c->tile2, true, true, s);
-    } else {
-      if (e == hipSuccess) e = launch_cgemm_f64(g1, c->tile1, true, false, s);
-      if (e == hipSuccess) e = mark(c, s, 0);
-      if (e == hipSuccess) e = launch_cgemm_f64(g2, c->tile2, true, true, s);
-    }
-    if (e == hipSuccess) e = mark(c, s, 1);
-    if (e == hipSuccess) e = launch_trace<T>(da, s);
-    if (e == hipSuccess) e = mark(c, s, 2);
-    if (e == hipSuccess) e = launch_dissipate<T>(da, s);
-    if (e == hipSuccess) e = mark(c, s, 3);
+    hipError_t e = step_once<T>(c, state, state, y, z, s);
     if (e != hipSuccess) {
       set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
       return QME_E_DEVICE;
@@ -182,6 +199,37 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   if (c->jt.n_gather > 0) {
     HIP_OK(hipMemcpy(c->pi, c->jt.pi.data(), sizeof(int32_t) * c->jt.pi.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->cg, c->jt.cg.data(), sizeof(double) * c->jt.cg.size(), hipMemcpyHostToDevice));
+  }
+  // adjoint tables
+  const int nj = int(c->model.jumps.size());
+  c->n_arrival = int(c->jt.arrival_channel.size());
+  const size_t ntau = size_t(std::max(1, c->jt.n_gather)) * n;
+  HIP_OK(hipMalloc(&c->tau, sizeof(int32_t) * ntau));
+  HIP_OK(hipMalloc(&c->ca, sizeof(double) * ntau));
+  if (c->jt.n_gather > 0) {
+    HIP_OK(hipMemcpy(c->tau, c->jt.tau.data(), sizeof(int32_t) * c->jt.tau.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->ca, c->jt.ca.data(), sizeof(double) * c->jt.ca.size(), hipMemcpyHostToDevice));
+  }
+  const size_t nup = size_t(std::max(1, c->n_arrival)) * n;
+  HIP_OK(hipMalloc(&c->upi, sizeof(int32_t) * nup));
+  HIP_OK(hipMalloc(&c->uc, sizeof(double) * nup));
+  {
+    std::vector<int32_t> upi;
+    std::vector<double> uc;
+    for (int32_t j : c->jt.arrival_channel) {
+      upi.insert(upi.end(), c->jt.unit_pi.begin() + size_t(j) * n, c->jt.unit_pi.begin() + size_t(j + 1) * n);
+      uc.insert(uc.end(), c->jt.unit_c.begin() + size_t(j) * n, c->jt.unit_c.begin() + size_t(j + 1) * n);
+    }
+    if (!upi.empty()) {
+      HIP_OK(hipMemcpy(c->upi, upi.data(), sizeof(int32_t) * upi.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(c->uc, uc.data(), sizeof(double) * uc.size(), hipMemcpyHostToDevice));
+    }
+  }
+  HIP_OK(hipMalloc(&c->ada, sizeof(double) * size_t(std::max(1, nj)) * n));
+  HIP_OK(hipMalloc(&c->arrival_of, sizeof(int32_t) * size_t(std::max(1, nj))));
+  if (nj > 0) {
+    HIP_OK(hipMemcpy(c->ada, c->jt.unit_ada.data(), sizeof(double) * c->jt.unit_ada.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->arrival_of, c->jt.arrival_of.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice));
   }
   *out = c.release();
   return QME_OK;
@@ -326,8 +374,8 @@ extern "C" qme_status qme_observe(const qme_ctx *c, const void *state, double *p
 extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
                                 const void *a_im, const void *m_re, const void *m_im,
                                 const void *x_re, const void *x_im, void *c_re, void *c_im,
-                                double alpha, double beta, int32_t conj_m, int32_t lower,
-                                int32_t tile, void *hip_stream) {
+                                double alpha, double beta, int32_t conj_a, int32_t conj_b,
+                                int32_t b_rows, int32_t lower, int32_t tile, void *hip_stream) {
   QME_GUARD_BEGIN
   set_error("");
   if (!a_re || !a_im || !m_re || !m_im || !c_re || !c_im) { set_error("NULL operand"); return QME_E_ARG; }
@@ -335,6 +383,11 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
   if (ld <= 0 || tile <= 0 || ld % tile != 0) { set_error("ld must be a positive multiple of tile"); return QME_E_ARG; }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipError_t e;
+  GemmOps o;
+  o.conj_a = conj_a != 0;
+  o.conj_b = conj_b != 0;
+  o.b_rows = b_rows != 0;
+  o.lower = lower != 0;
   if (precision == QME_FP32) {
     if (tile != 128 && tile != 64) { set_error("FP32 tile must be 128 or 64"); return QME_E_ARG; }
     CgemmArgs<float> g{static_cast<const float *>(a_re), static_cast<const float *>(a_im),
@@ -342,14 +395,14 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
                        static_cast<const float *>(x_re), static_cast<const float *>(x_im),
                        static_cast<float *>(c_re), static_cast<float *>(c_im), ld,
                        float(alpha), float(beta)};
-    e = launch_cgemm_f32(g, tile, conj_m != 0, lower != 0, s);
+    e = launch_cgemm_f32(g, tile, o, s);
   } else if (precision == QME_FP64) {
     if (tile != 64 && tile != 32) { set_error("FP64 tile must be 64 or 32"); return QME_E_ARG; }
     CgemmArgs<double> g{static_cast<const double *>(a_re), static_cast<const double *>(a_im),
                         static_cast<const double *>(m_re), static_cast<const double *>(m_im),
                         static_cast<const double *>(x_re), static_cast<const double *>(x_im),
                         static_cast<double *>(c_re), static_cast<double *>(c_im), ld, alpha, beta};
-    e = launch_cgemm_f64(g, tile, conj_m != 0, lower != 0, s);
+    e = launch_cgemm_f64(g, tile, o, s);
   } else {
     set_error("qme_cgemm supports QME_FP32 and QME_FP64");
     return QME_E_UNSUPPORTED;
@@ -410,7 +463,8 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
 
 qme_ctx::~qme_ctx() {
   for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
-  for (void *p : {du_re, du_im, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg})
+  for (void *p : {du_re, du_im, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
+                  (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of})
     if (p) (void)hipFree(p);
 }
 

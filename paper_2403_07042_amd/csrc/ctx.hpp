@@ -5,6 +5,8 @@
 #include <memory>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "model.hpp"
 #include "qme.h"
 
@@ -23,6 +25,14 @@ struct qme_ctx {
   double *d = nullptr, *leak = nullptr, *diag = nullptr;
   int32_t *pi = nullptr;
   double *cg = nullptr;
+  // adjoint tables (owned)
+  int32_t *tau = nullptr;     // [n_gather x n]
+  double *ca = nullptr;
+  int32_t *upi = nullptr;     // [n_arrival x n]
+  double *uc = nullptr;
+  double *ada = nullptr;      // [n_jumps x n]
+  int32_t *arrival_of = nullptr;   // [n_jumps]
+  int n_arrival = 0;
 
   // per-kernel timing (qme_profile_enable / qme_profile_read)
   bool profiling = false;
@@ -40,4 +50,9 @@ namespace qme {
 int64_t round_up(int64_t x, int64_t m);
 size_t plane_elems(const qme_ctx *c);
 size_t state_bytes(const qme_ctx *c);
+qme_status check_device(const qme_ctx *c);
+// One time step from state `in` to state `out` (may alias) with the two
+// workspace plane pairs y (product T) and z (rotated state, lower tiles).
+template <typename T>
+hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s);
 }  // namespace qme

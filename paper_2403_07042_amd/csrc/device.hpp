@@ -7,11 +7,15 @@
 
 namespace qme {
 
-// Planar complex GEMM  C = alpha * A * op(M) + beta * X  on N x N matrices
-// stored row-major with leading dimension ld (padding rows/columns zero):
-//   op(M) = M^H (conj_m) or M^T.
-// Both A and M are read by rows, so both operands stream contiguous k.
-// lower: compute only the tiles on or below the diagonal (for Hermitian C).
+// Planar complex GEMM  C = alpha * opA(A) * opB(B) + beta * X  on ld x ld
+// row-major matrices (padding rows/columns zero).  The second operand is
+// passed as m_re/m_im: with b_rows it is B itself (row-major [k][j]),
+// otherwise it is M with B = M^T (B[k][j] = M[j][k]).  conj_a / conj_b
+// conjugate A / B.  lower: only the tiles on or below the diagonal.
+struct GemmOps {
+  bool conj_a = false, conj_b = false, b_rows = false, lower = false;
+};
+
 template <typename T>
 struct CgemmArgs {
   const T *a_re, *a_im;
@@ -22,9 +26,9 @@ struct CgemmArgs {
   T alpha, beta;
 };
 
-hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, bool conj_m, bool lower,
+hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o,
                             hipStream_t s);
-hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, bool conj_m, bool lower,
+hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, const GemmOps &o,
                             hipStream_t s);
 
 // Fused decoherence step on the rotated state Z (lower triangle valid):
@@ -42,7 +46,8 @@ struct DissArgs {
   const int32_t *pi;     // [n_gather * n]
   const double *cg;      // [n_gather * n]
   int n_gather;
-  double *aux;           // state scalars (see qme_state_layout)
+  const double *aux_in;  // scalars of the input state (sink)
+  double *aux_out;       // scalars of the output state (see qme_state_layout)
 };
 
 template <typename T>
@@ -51,5 +56,48 @@ template <typename T>
 hipError_t launch_dissipate(const DissArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_diag(const T *x_re, int64_t ld, int64_t n, double *out, hipStream_t s);
+
+// Adjoint of one step's decoherence, fused with the rate-gradient partials.
+//   mu = lam + dt * sum_j gamma_j (A_j^dag lam A_j - 1/2 {A_j^dag A_j, lam})
+// from the lower triangle of the Hermitian lam (written in full), and, with
+// Z = rho_u of the same step,
+//   e(u,v) = Re(Z[u,v] lam[v,u]) summed per row / column of each tile, and
+//   sum_{u,v} c_a[u] c_a[v] Re(lam[v,u] Z[pi_a[u], pi_a[v]]) per block for
+//   every channel a with arrivals inside the basis (unit rate).
+template <typename T>
+struct AdjArgs {
+  const T *l_re, *l_im;
+  T *mu_re, *mu_im;
+  const T *z_re, *z_im;
+  int64_t ld, n;
+  double dt;
+  const double *d;
+  const int32_t *tau;    // [n_gather * n]
+  const double *ca;      // [n_gather * n]
+  int n_gather;
+  const int32_t *upi;    // [n_arrival * n]
+  const double *uc;      // [n_arrival * n]
+  int n_arrival;
+  double *rowbuf;        // [tiles * n]
+  double *colbuf;        // [tiles * n]
+  double *gbuf;          // [blocks * n_arrival]
+};
+
+constexpr int kAdjTile = 64;
+constexpr int kMaxArrival = 16;
+
+template <typename T>
+hipError_t launch_adj_dissipate(const AdjArgs<T> &a, hipStream_t s);
+// q[u] = sum of the row / column partials of e(u, .) (all tiles of u)
+hipError_t launch_q_reduce(const double *rowbuf, const double *colbuf, int64_t n, double *q,
+                           hipStream_t s);
+// grad[j] += dt * (sum_b gbuf[b][arrival_of[j]] - sum_u ada[j][u] q[u])
+hipError_t launch_gamma_reduce(const double *gbuf, int blocks, int n_arrival,
+                               const int32_t *arrival_of, const double *ada, const double *q,
+                               int64_t n, int n_jumps, double dt, double *grad, hipStream_t s);
+// X = 0 except X[u][u] = o[u]
+template <typename T>
+hipError_t launch_set_diag(T *x_re, T *x_im, int64_t ld, int64_t n, const double *o,
+                           hipStream_t s);
 
 }  // namespace qme

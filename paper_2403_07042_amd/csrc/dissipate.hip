@@ -65,12 +65,13 @@ __global__ __launch_bounds__(kTraceThreads) void trace_kernel(DissArgs<T> p) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double sink = p.aux[0] + p.dt * s_lost[0];
-    p.aux[0] = sink;
-    p.aux[1] = s_rot[0];
-    p.aux[2] = s_lost[0];
-    p.aux[3] = p.aux[3] + 1.0;
-    p.aux[4] = (1.0 - sink) / s_tr[0];
+    const double sink = p.aux_in[0] + p.dt * s_lost[0];
+    const double steps = p.aux_in[3] + 1.0;
+    p.aux_out[0] = sink;
+    p.aux_out[1] = s_rot[0];
+    p.aux_out[2] = s_lost[0];
+    p.aux_out[3] = steps;
+    p.aux_out[4] = (1.0 - sink) / s_tr[0];
   }
 }
 
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kDissThreads) void dissipate_kernel(DissArgs<T> p) 
   while (bi * (bi + 1) / 2 > t) --bi;
   const int bj = t - bi * (bi + 1) / 2;
   const bool diag_tile = bi == bj;
-  const double scale = p.aux[4];
+  const double scale = p.aux_out[4];
   const double dt = p.dt;
   const int c = threadIdx.x & (TD - 1);
   const int r0 = threadIdx.x / TD;

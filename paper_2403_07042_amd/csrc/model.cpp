@@ -329,13 +329,25 @@ JumpTables jump_tables(const Model &m) {
       }
     }
   }
+  jt.arrival_of.assign(nj, -1);
   for (int j = 0; j < nj; ++j) {
-    if (!has_arrival[j] || m.jumps[j].gamma == 0.0) continue;
+    if (!has_arrival[j]) continue;
+    jt.arrival_of[j] = int(jt.arrival_channel.size());
+    jt.arrival_channel.push_back(j);
+    if (m.jumps[j].gamma == 0.0) continue;
     jt.gather_channel.push_back(j);
     double sg = std::sqrt(m.jumps[j].gamma);
+    size_t base = jt.tau.size();
+    jt.tau.resize(base + n, -1);
+    jt.ca.resize(base + n, 0.0);
     for (int64_t u = 0; u < n; ++u) {
-      jt.pi.push_back(jt.unit_pi[size_t(j) * n + u]);
+      int32_t w = jt.unit_pi[size_t(j) * n + u];
+      jt.pi.push_back(w);
       jt.cg.push_back(sg * jt.unit_c[size_t(j) * n + u]);
+      if (w >= 0) {   // A_j maps w onto u
+        jt.tau[base + w] = int32_t(u);
+        jt.ca[base + w] = sg * jt.unit_c[size_t(j) * n + u];
+      }
     }
   }
   jt.n_gather = int(jt.gather_channel.size());
@@ -400,7 +412,8 @@ static void zgemm_host(int64_t n, const std::vector<double> &ar, const std::vect
 }
 
 bool propagator_increment(const Model &m, const Csr &h, std::vector<double> &re,
-                          std::vector<double> &im, std::string &err) {
+                          std::vector<double> &im, std::string &err,
+                          std::vector<std::vector<double>> *levels, int *nsq) {
   const int64_t n = m.n;
   // theta = |H dt|_1 (largest absolute column sum; H is symmetric, so rows)
   double norm1 = 0.0;
@@ -432,8 +445,15 @@ bool propagator_increment(const Model &m, const Csr &h, std::vector<double> &re,
     if (mx < 1e-18 && double(k) > theta) break;
     if (k == 60) { err = "Taylor series did not converge"; return false; }
   }
+  if (nsq) *nsq = squarings;
+  if (levels) levels->clear();
   // squaring in increment form: (I + D)^2 - I = 2 D + D D
   for (int s = 0; s < squarings; ++s) {
+    if (levels) {   // V_{squarings - s} - I, stored re plane then im plane
+      std::vector<double> lv(re);
+      lv.insert(lv.end(), im.begin(), im.end());
+      levels->push_back(std::move(lv));
+    }
     std::vector<double> cr, ci;
     zgemm_host(n, re, im, re, im, cr, ci);
     for (size_t e = 0; e < re.size(); ++e) {
@@ -450,6 +470,110 @@ bool propagator_increment(const Model &m, const Csr &h, std::vector<double> &re,
       re[a] = re[b] = r;
       im[a] = im[b] = x;
     }
+  }
+  return true;
+}
+
+// ------------------------------------------------------------ Frechet
+
+// y = (-i tau H) x for complex planar dense x (rows), H sparse real symmetric.
+static void apply_left(const Csr &h, double tau, const std::vector<double> &xr,
+                       const std::vector<double> &xi, std::vector<double> &yr,
+                       std::vector<double> &yi) {
+  // (-i tau) (H xr + i H xi) = tau H xi - i tau H xr
+  spmm(h, xi, yr, tau);
+  spmm(h, xr, yi, -tau);
+}
+
+// y = x (-i tau H) = (-i tau) (x H); with H symmetric, (x H)^T = H x^T.
+static void apply_right(const Csr &h, double tau, const std::vector<double> &xr,
+                        const std::vector<double> &xi, std::vector<double> &yr,
+                        std::vector<double> &yi) {
+  const int64_t n = h.n;
+  std::vector<double> tr(size_t(n) * n), ti(size_t(n) * n), ur, ui;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      tr[size_t(j) * n + i] = xr[size_t(i) * n + j];
+      ti[size_t(j) * n + i] = xi[size_t(i) * n + j];
+    }
+  ur.resize(tr.size());
+  ui.resize(ti.size());
+  apply_left(h, tau, tr, ti, ur, ui);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      yr[size_t(i) * n + j] = ur[size_t(j) * n + i];
+      yi[size_t(i) * n + j] = ui[size_t(j) * n + i];
+    }
+}
+
+// L(B, G) for B = -i tau H by its power series
+//   L(B, G) = sum_{k>=1} (1/k!) sum_{j=0}^{k-1} B^j G B^{k-1-j},
+// accumulated with M_1 = G, R_1 = G B, M_{k+1} = (B M_k + R_k) / (k+1),
+// R_{k+1} = R_k B / (k+1); every product is sparse x dense.
+static bool frechet_series(const Csr &h, double tau, const std::vector<double> &g_re,
+                           const std::vector<double> &g_im, std::vector<double> &w_re,
+                           std::vector<double> &w_im, std::string &err) {
+  const size_t nn = g_re.size();
+  std::vector<double> mr(g_re), mi(g_im), rr(nn), ri(nn), tr(nn), ti(nn);
+  apply_right(h, tau, g_re, g_im, rr, ri);
+  w_re = mr;
+  w_im = mi;
+  double gmax = 0.0;
+  for (size_t e = 0; e < nn; ++e) gmax = std::max(gmax, std::fabs(g_re[e]) + std::fabs(g_im[e]));
+  if (gmax == 0.0) return true;
+  for (int k = 1; k < 80; ++k) {
+    apply_left(h, tau, mr, mi, tr, ti);
+    double mx = 0.0;
+    for (size_t e = 0; e < nn; ++e) {
+      mr[e] = (tr[e] + rr[e]) / double(k + 1);
+      mi[e] = (ti[e] + ri[e]) / double(k + 1);
+      w_re[e] += mr[e];
+      w_im[e] += mi[e];
+      mx = std::max(mx, std::fabs(mr[e]) + std::fabs(mi[e]));
+    }
+    if (mx < 1e-18 * gmax) return true;
+    apply_right(h, tau, rr, ri, tr, ti);
+    for (size_t e = 0; e < nn; ++e) {
+      rr[e] = tr[e] / double(k + 1);
+      ri[e] = ti[e] / double(k + 1);
+    }
+  }
+  err = "Frechet series did not converge";
+  return false;
+}
+
+bool frechet_adjoint(const Model &m, const Csr &h, const std::vector<double> &g_re,
+                     const std::vector<double> &g_im, std::vector<double> &w_re,
+                     std::vector<double> &w_im, std::string &err) {
+  // Undo the squarings: L(2B, G) = L(B, G V + V G) / 2 with V = exp(B), so
+  // L(A, G) = 2^{-s} L(A / 2^s, G_s),  G_i = G_{i-1} V_i + V_i G_{i-1},
+  // V_i = exp(A / 2^i), i = 1..s.
+  std::vector<double> re, im;
+  std::vector<std::vector<double>> levels;
+  int s = 0;
+  if (!propagator_increment(m, h, re, im, err, &levels, &s)) return false;
+  const int64_t n = m.n;
+  const size_t nn = size_t(n) * n;
+  std::vector<double> gr(g_re), gi(g_im);
+  for (int i = 1; i <= s; ++i) {
+    // levels[s - i] holds V_i - I (the squaring loop stores V_s first)
+    const std::vector<double> &lv = levels[size_t(s - i)];
+    std::vector<double> vr(lv.begin(), lv.begin() + nn), vi(lv.begin() + nn, lv.end());
+    for (int64_t d = 0; d < n; ++d) vr[size_t(d) * n + d] += 1.0;
+    std::vector<double> ar, ai, br, bi;
+    zgemm_host(n, gr, gi, vr, vi, ar, ai);
+    zgemm_host(n, vr, vi, gr, gi, br, bi);
+    for (size_t e = 0; e < nn; ++e) {
+      gr[e] = ar[e] + br[e];
+      gi[e] = ai[e] + bi[e];
+    }
+  }
+  const double tau = m.dt / std::ldexp(1.0, s);
+  if (!frechet_series(h, tau, gr, gi, w_re, w_im, err)) return false;
+  const double f = std::ldexp(1.0, -s);
+  for (size_t e = 0; e < nn; ++e) {
+    w_re[e] *= f;
+    w_im[e] *= f;
   }
   return true;
 }

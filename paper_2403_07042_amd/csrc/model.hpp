@@ -68,10 +68,18 @@ struct JumpTables {
   std::vector<double> cg;                // n_gather x n
   std::vector<double> d;                 // sum_j gamma_j (A_j^dag A_j)_uu
   std::vector<double> leak;              // sum_j gamma_j |a_j(u)|^2 [A_j u leaves the basis]
+  // forward maps of the gather channels (adjoint decoherence):
+  //   (A_j^dag L A_j)[u,v] = a_j[u] a_j[v] L[tau_j[u], tau_j[v]],
+  // tau_j[u] = basis index of A_j u (-1 if zero or outside), ca = sqrt(gamma) a
+  std::vector<int32_t> tau;              // n_gather x n
+  std::vector<double> ca;                // n_gather x n
   // per original jump, unit-rate tables (for rate gradients)
   std::vector<int32_t> unit_pi;          // n_jumps x n
   std::vector<double> unit_c;            // n_jumps x n (c_j, not scaled)
   std::vector<double> unit_ada;          // n_jumps x n diag of A^dag A
+  // channels with an arrival inside the basis, whatever their rate
+  std::vector<int32_t> arrival_channel;  // original jump index
+  std::vector<int32_t> arrival_of;       // per jump: index into arrival_channel or -1
 };
 
 bool build_model(const qme_system *sys, const qme_params *par, Model &m,
@@ -85,8 +93,20 @@ Csr to_csr(int64_t n, const std::vector<int32_t> &r,
 std::vector<TermCoo> hamiltonian_terms(const Model &m);
 JumpTables jump_tables(const Model &m);
 // dU = exp(-i H dt) - I, row-major n x n planes; exactly symmetric.
+// When scaling and squaring was needed, levels receives the increments
+// V_i - I of V_i = exp(-i H dt / 2^i) for i = 1..s (level i-1 in the vector)
+// so that the adjoint can undo the squarings.
 bool propagator_increment(const Model &m, const Csr &h, std::vector<double> &re,
-                          std::vector<double> &im, std::string &err);
+                          std::vector<double> &im, std::string &err,
+                          std::vector<std::vector<double>> *levels = nullptr,
+                          int *squarings = nullptr);
+
+// W = L(A, G), the Frechet derivative of exp at A = -i H dt applied to G
+// in its adjoint form tr(G L(A, E)) = tr(L(A, G) E); G and W are complex
+// planar n x n (FP64, row-major).
+bool frechet_adjoint(const Model &m, const Csr &h, const std::vector<double> &g_re,
+                     const std::vector<double> &g_im, std::vector<double> &w_re,
+                     std::vector<double> &w_im, std::string &err);
 
 // Thread-local error text of the ABI.
 void set_error(const std::string &s);

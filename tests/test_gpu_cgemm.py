@@ -26,7 +26,7 @@ def planes(rng, ld, n, dtype):
     return re, im
 
 
-def run(prec, ld, n, tile, conj_m, lower, alpha, beta, seed=0):
+def run(prec, ld, n, tile, conj_m, lower, alpha, beta, seed=0, conj_a=False, b_rows=False):
     dtype = np.float32 if prec == L.FP32 else np.float64
     rng = np.random.default_rng(seed)
     ar, ai = planes(rng, ld, n, dtype)
@@ -38,15 +38,20 @@ def run(prec, ld, n, tile, conj_m, lower, alpha, beta, seed=0):
     t = [dev(v, dtype) for v in (ar, ai, mr, mi, xr, xi, cr, ci)]
     p = [ctypes.c_void_p(v.data_ptr()) for v in t]
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    print(f"cgemm prec={prec} ld={ld} n={n} tile={tile} conj={conj_m} lower={lower}", flush=True)
-    L.check(L.load().qme_cgemm(prec, ld, *p, alpha, beta, int(conj_m), int(lower), tile, s))
+    print(f"cgemm prec={prec} ld={ld} n={n} tile={tile} conj_a={conj_a} conj_b={conj_m} "
+          f"b_rows={b_rows} lower={lower}", flush=True)
+    L.check(L.load().qme_cgemm(prec, ld, *p, alpha, beta, int(conj_a), int(conj_m), int(b_rows),
+                               int(lower), tile, s))
     torch.cuda.synchronize()
     got = t[6].cpu().numpy().astype(np.float64) + 1j * t[7].cpu().numpy().astype(np.float64)
     a = ar.astype(np.float64) + 1j * ai
     m = mr.astype(np.float64) + 1j * mi
     x = xr.astype(np.float64) + 1j * xi
-    opm = m.conj().T if conj_m else m.T
-    ref = alpha * (a @ opm) + beta * x
+    opa = a.conj() if conj_a else a
+    opb = m if b_rows else m.T
+    if conj_m:
+        opb = opb.conj()
+    ref = alpha * (opa @ opb) + beta * x
     mask = np.ones((ld, ld), bool)
     if lower:
         bi = np.arange(ld)[:, None] // tile
@@ -83,3 +88,35 @@ def test_cgemm_alpha_beta():
     assert err < 1e-13 * scale
     err, scale = run(L.FP32, 128, 100, 64, False, False, 3.0, 0.0)
     assert err < 3.0 * (1e-6 * 100 + 1e-5)
+
+
+@pytest.mark.parametrize("prec,ld,n,tile", [(L.FP32, 192, 150, 64), (L.FP32, 256, 256, 128),
+                                            (L.FP64, 96, 70, 32), (L.FP64, 128, 128, 64)])
+@pytest.mark.parametrize("conj_a,conj_b,b_rows", [(True, True, False), (False, False, True),
+                                                  (True, False, True), (False, True, True)])
+def test_cgemm_operand_forms(prec, ld, n, tile, conj_a, conj_b, b_rows):
+    err, scale = run(prec, ld, n, tile, conj_b, False, 1.0, 1.0, conj_a=conj_a, b_rows=b_rows)
+    if prec == L.FP32:
+        assert err < 1e-6 * n + 1e-5
+    else:
+        assert err < 1e-13 * scale
+
+
+def test_cgemm_accumulate_in_place():
+    """C = A B + C (the adjoint's G accumulation): X and C are one buffer."""
+    rng = np.random.default_rng(4)
+    ld, n = 128, 100
+    ar, ai = planes(rng, ld, n, np.float32)
+    br, bi = planes(rng, ld, n, np.float32)
+    cr, ci = planes(rng, ld, n, np.float32)
+    t = [dev(v, np.float32) for v in (ar, ai, br, bi, cr, ci)]
+    p = [ctypes.c_void_p(v.data_ptr()) for v in t]
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L.check(L.load().qme_cgemm(L.FP32, ld, p[0], p[1], p[2], p[3], p[4], p[5], p[4], p[5],
+                               1.0, 1.0, 0, 0, 1, 0, 64, s))
+    torch.cuda.synchronize()
+    got = t[4].cpu().numpy() + 1j * t[5].cpu().numpy()
+    a = ar + 1j * ai.astype(np.float64)
+    b = br + 1j * bi.astype(np.float64)
+    ref = a @ b + (cr + 1j * ci.astype(np.float64))
+    assert np.abs(got - ref).max() < 1e-6 * n + 1e-5
