@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps timed for the CPU baseline (0: skip)")
-    ap.add_argument("--legs", default="fp32,fp64", help="comma list of fp32, fp64")
+    ap.add_argument("--legs", default="fp32,fp64,bf16x3", help="comma list of fp32, fp64, bf16x3")
+    ap.add_argument("--bf16x3-steps", type=int, default=1000)
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="steps of the timed FP32 adjoint (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
@@ -154,6 +155,8 @@ def main():
     res = {}
     if "fp32" in legs:
         res["fp32"] = timed_leg(P, W, torch, wl, "fp32", args.steps, args.warmup, args.tiles32)
+    if "bf16x3" in legs and args.bf16x3_steps > 0:
+        res["bf16x3"] = timed_leg(P, W, torch, wl, "bf16x3", args.bf16x3_steps, args.warmup)
     if "fp64" in legs and args.fp64_steps > 0:
         res["fp64"] = timed_leg(P, W, torch, wl, "fp64", args.fp64_steps, min(args.warmup, 5),
                                 args.tiles64)
@@ -202,6 +205,14 @@ def main():
         "adjoint_ms_per_step": adj["ms_per_step"] if adj else None,
         "adjoint": adj,
     }
+    if "bf16x3" in res:
+        b = res["bf16x3"]
+        line["bf16x3"] = {"steps_per_s": b["steps_per_s"], "ms_per_step": b["ms_per_step"],
+                          "steps": args.bf16x3_steps, "kernels_us": b["kernels_us"],
+                          "effective_frac_of_fp32_peak":
+                              flops_step * b["steps_per_s"] / 1e12 / PEAK_FP32_MFMA,
+                          "bf16_mfma_tflops_first_product":
+                              6 * flops_product / (b["kernels_us"]["product_full"] * 1e-6) / 1e12}
     if "fp64" in res:
         f = res["fp64"]
         line["fp64"] = {"steps_per_s": f["steps_per_s"], "ms_per_step": f["ms_per_step"],

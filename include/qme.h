@@ -199,7 +199,9 @@ qme_status qme_observe(const qme_ctx *ctx, const void *state_dev,
  * checkpoint_every steps and recomputes each segment backwards.  Outputs:
  * *value = f (may be NULL) and grad[n_atoms + n_hops + n_jumps] in the order
  * g per atom (cavity-major), mu per hop, gamma per jump.  The Frechet
- * derivative of exp(-i H dt) is evaluated on the host in FP64.  state0 is
+ * derivative of exp(-i H dt) is evaluated on the host in FP64; the adjoint
+ * products run in the context's storage arithmetic (FP32 for QME_BF16X3,
+ * whose forward recomputation still uses the split-bf16 products).  state0 is
  * not modified.  workspace: device memory of at least
  * qme_adjoint_workspace_size bytes (256-byte aligned).  Synchronous. */
 qme_status qme_adjoint(qme_ctx *ctx, const void *state0_dev, int64_t n_steps,
@@ -219,8 +221,9 @@ qme_status qme_adjoint_workspace_size(const qme_ctx *ctx, int64_t n_steps,
  * read row-major; otherwise it is M and B = M^T, i.e. the operand is read by
  * rows j.  opB = conj(B) if conj_b else B (so b_rows = 0, conj_b = 1 gives
  * M^H).  lower != 0 computes only the tile x tile blocks on or below the
- * diagonal.  tile: 128 or 64 (FP32), 64 or 32 (FP64); ld must be a multiple
- * of tile.  C must not overlap A or B; C may equal X (accumulation).
+ * diagonal.  tile: 128 or 64 (FP32), 64 or 32 (FP64), 64 (QME_BF16X3: FP32
+ * planes, split-bf16 products, b_rows must be 0); ld must be a multiple of
+ * tile.  C must not overlap A or B; C may equal X (accumulation).
  * Asynchronous on hip_stream. */
 qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
                      const void *a_im_dev, const void *m_re_dev, const void *m_im_dev,
@@ -231,7 +234,7 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
 
 /* Tile edge of the two products of each step (the autotuner's knob):
  * tile1 for T = rho + dU rho, tile2 for the lower-triangle product.
- * FP32 tiles: 128 or 64; FP64 tiles: 64 or 32.  Each must divide the state's
+ * FP32 tiles: 128 or 64; FP64 tiles: 64 or 32; BF16X3: 64.  Each must divide the state's
  * leading dimension ld (qme_state_layout), else QME_E_ARG. */
 qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
 

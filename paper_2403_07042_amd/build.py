@@ -27,7 +27,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-munsafe-fp-atomics"]
 
-SOURCES = ["model.cpp", "abi_host.cpp", "ctx.hip", "cgemm.hip", "dissipate.hip", "adjoint.hip"]
+SOURCES = ["model.cpp", "abi_host.cpp", "ctx.hip", "cgemm.hip", "dissipate.hip", "adjoint.hip",
+           "cgemm_bf16x3.hip"]
 
 
 def _compile(src: str) -> str:

@@ -1,0 +1,210 @@
+// Split-BF16x3 planar complex GEMM on CDNA4 matrix cores (gfx950).
+//
+//   C = alpha * opA(A) * opB(M^T) + beta * X     (FP32 in, FP32 out; "NT")
+//
+// Each FP32 value x is split, while its tile is staged into LDS, into three
+// bf16 values x = hi + mid + lo + r with |r| <= 2^-24 |x| (round to nearest
+// even at each stage).  A real product x*y is accumulated in FP32 from the
+// six significant cross products
+//   mid*mid, lo*hi, hi*lo, mid*hi, hi*mid, hi*hi      (smallest first);
+// the dropped terms (mid*lo, lo*mid, lo*lo) are below 2^-24 |x y|.
+// v_mfma_f32_32x32x16_bf16 does 16 k-terms per instruction, so the six
+// products cost less than one FP32 MFMA sequence over the same k.
+//
+// Used for both products of a time step, in the same NT forms as the FP32
+// kernel (A rows and M rows stream contiguous k; see cgemm.hip).
+#include "device.hpp"
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+namespace qme {
+
+static constexpr int kThreads3 = 256;
+
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = __bf16(x);
+  const float r1 = x - float(h);
+  m = __bf16(r1);
+  const float r2 = r1 - float(m);
+  l = __bf16(r2);
+}
+
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+  bf16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = -v[e];
+  return o;
+}
+
+// acc += x * y over the six significant split products; x[3], y[3] = hi, mid, lo
+__device__ __forceinline__ floatx16 mac3(const bf16x8 *x, const bf16x8 *y, floatx16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[2], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[0], acc, 0, 0, 0);
+  return acc;
+}
+
+// One workgroup per 64 x 64 output tile, 4 waves (2 x 2), each a 32 x 32
+// block.  K tile 32 (two MFMA k-steps of 16).  LDS holds six bf16 planes
+// (re/im x hi/mid/lo) per operand, single-buffered; the next K tile is
+// prefetched into registers during the products.
+// v_mfma_f32_32x32x16_bf16: A 32x16 (lane l: row l%32, k 8*(l/32)..+7),
+// B 16x32 (lane l: k 8*(l/32)..+7, col l%32), D as for the FP32 32x32 MFMA.
+template <bool CONJA, bool CONJB, bool LOWER>
+__global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float> p) {
+  constexpr int BM = 64;
+  constexpr int KT = 32;
+  constexpr int LDK = KT + 8;   // padded LDS row (bf16)
+  __shared__ __bf16 sA[6][BM * LDK];
+  __shared__ __bf16 sB[6][BM * LDK];
+
+  const int tiles = int(p.ld / BM);
+  int bi, bj;
+  {
+    const int t = blockIdx.x;
+    if (LOWER) {
+      int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
+      while ((r + 1) * (r + 2) / 2 <= t) ++r;
+      while (r * (r + 1) / 2 > t) --r;
+      bi = r;
+      bj = t - r * (r + 1) / 2;
+    } else {
+      const int nb = tiles * tiles;
+      int tt = t;
+      if ((nb & 7) == 0) tt = (t & 7) * (nb >> 3) + (t >> 3);
+      const int group = 4, gsz = group * tiles;
+      const int g = tt / gsz, first = g * group;
+      const int rows = min(group, tiles - first);
+      const int in = tt - g * gsz;
+      bi = first + in % rows;
+      bj = in / rows;
+    }
+  }
+  const int64_t ld = p.ld;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 31, h = lane >> 5;
+
+  // loads: 64 rows x 32 k per plane = 512 float4, two per thread
+  const int lr = tid >> 3, lk = (tid & 7) * 4;
+  const float *src[4] = {p.a_re + (int64_t(bi) * BM + lr) * ld + lk,
+                         p.a_im + (int64_t(bi) * BM + lr) * ld + lk,
+                         p.m_re + (int64_t(bj) * BM + lr) * ld + lk,
+                         p.m_im + (int64_t(bj) * BM + lr) * ld + lk};
+  floatx4 reg[4][2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        reg[o][q] = *reinterpret_cast<const floatx4 *>(src[o] + int64_t(q) * 32 * ld + k0);
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      __bf16 *base = (o < 2) ? &sA[(o & 1) * 3][0] : &sB[(o & 1) * 3][0];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        bf16x4 vh, vm, vl;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          __bf16 a, b, c;
+          split3(reg[o][q][e], a, b, c);
+          vh[e] = a; vm[e] = b; vl[e] = c;
+        }
+        const int off = (q * 32 + lr) * LDK + lk;
+        *reinterpret_cast<bf16x4 *>(base + 0 * BM * LDK + off) = vh;
+        *reinterpret_cast<bf16x4 *>(base + 1 * BM * LDK + off) = vm;
+        *reinterpret_cast<bf16x4 *>(base + 2 * BM * LDK + off) = vl;
+      }
+    }
+  };
+
+  floatx16 cr, ci;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) { cr[r] = 0.0f; ci[r] = 0.0f; }
+
+  const int nk = int(ld / KT);
+  gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();             // previous tile's fragments consumed
+    lstore();
+    __syncthreads();
+    if (kt + 1 < nk) gload((kt + 1) * KT);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 ar[3], ai[3], br[3], bim[3];
+      const int oa = (wm * 32 + li) * LDK + s * 16 + h * 8;
+      const int ob = (wn * 32 + li) * LDK + s * 16 + h * 8;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        ar[t] = *reinterpret_cast<const bf16x8 *>(&sA[t][oa]);
+        ai[t] = *reinterpret_cast<const bf16x8 *>(&sA[3 + t][oa]);
+        br[t] = *reinterpret_cast<const bf16x8 *>(&sB[t][ob]);
+        bim[t] = *reinterpret_cast<const bf16x8 *>(&sB[3 + t][ob]);
+      }
+      // (Ar + i sA Ai)(Br + i sB Bi):
+      //   Cr += Ar Br - sA sB Ai Bi,  Ci += sB Ar Bi + sA Ai Br
+      bf16x8 t1[3], t2[3], t3[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        t1[t] = CONJA ? neg8(ai[t]) : ai[t];                      // sA Ai
+        t2[t] = (CONJA != CONJB) ? ai[t] : neg8(ai[t]);           // -sA sB Ai
+        t3[t] = CONJB ? neg8(ar[t]) : ar[t];                      // sB Ar
+      }
+      cr = mac3(ar, br, cr);
+      ci = mac3(t1, br, ci);
+      cr = mac3(t2, bim, cr);
+      ci = mac3(t3, bim, ci);
+    }
+  }
+
+  const bool has_x = p.beta != 0.0f;
+  const int64_t col = int64_t(bj) * BM + wn * 32 + li;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = int64_t(bi) * BM + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+    const int64_t o = row * ld + col;
+    float vr = p.alpha * cr[r], vi = p.alpha * ci[r];
+    if (has_x) {
+      vr += p.beta * p.x_re[o];
+      vi += p.beta * p.x_im[o];
+    }
+    p.c_re[o] = vr;
+    p.c_im[o] = vi;
+  }
+}
+
+template <typename K>
+static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipStream_t s) {
+  const int tiles = int(a.ld / 64);
+  const int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s) {
+  if (a.ld % 64 != 0 || o.b_rows) return hipErrorInvalidValue;
+  const int code = (o.conj_a ? 4 : 0) | (o.conj_b ? 2 : 0) | (o.lower ? 1 : 0);
+  switch (code) {
+    case 0: return launch3(cgemm_bf16x3_kernel<false, false, false>, a, false, s);
+    case 1: return launch3(cgemm_bf16x3_kernel<false, false, true>, a, true, s);
+    case 2: return launch3(cgemm_bf16x3_kernel<false, true, false>, a, false, s);
+    case 3: return launch3(cgemm_bf16x3_kernel<false, true, true>, a, true, s);
+    case 4: return launch3(cgemm_bf16x3_kernel<true, false, false>, a, false, s);
+    case 5: return launch3(cgemm_bf16x3_kernel<true, false, true>, a, true, s);
+    case 6: return launch3(cgemm_bf16x3_kernel<true, true, false>, a, false, s);
+    case 7: return launch3(cgemm_bf16x3_kernel<true, true, true>, a, true, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace qme

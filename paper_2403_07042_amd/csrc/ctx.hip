@@ -100,9 +100,15 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   o2.lower = true;
   hipError_t e = mark(c, s, -1);
   if constexpr (sizeof(T) == 4) {
-    if (e == hipSuccess) e = launch_cgemm_f32(g1, c->tile1, o1, s);
-    if (e == hipSuccess) e = mark(c, s, 0);
-    if (e == hipSuccess) e = launch_cgemm_f32(g2, c->tile2, o2, s);
+    if (c->precision == QME_BF16X3) {
+      if (e == hipSuccess) e = launch_cgemm_bf16x3(g1, o1, s);
+      if (e == hipSuccess) e = mark(c, s, 0);
+      if (e == hipSuccess) e = launch_cgemm_bf16x3(g2, o2, s);
+    } else {
+      if (e == hipSuccess) e = launch_cgemm_f32(g1, c->tile1, o1, s);
+      if (e == hipSuccess) e = mark(c, s, 0);
+      if (e == hipSuccess) e = launch_cgemm_f32(g2, c->tile2, o2, s);
+    }
   } else {
     if (e == hipSuccess) e = launch_cgemm_f64(g1, c->tile1, o1, s);
     if (e == hipSuccess) e = mark(c, s, 0);
@@ -144,8 +150,7 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   if (!out) { set_error("out is NULL"); return QME_E_ARG; }
   *out = nullptr;
   if (!par) { set_error("params is NULL"); return QME_E_ARG; }
-  if (precision != QME_FP64 && precision != QME_FP32) {
-    if (precision == QME_BF16X3) { set_error("BF16X3 precision is not built"); return QME_E_UNSUPPORTED; }
+  if (precision != QME_FP64 && precision != QME_FP32 && precision != QME_BF16X3) {
     set_error("unknown precision");
     return QME_E_ARG;
   }
@@ -403,9 +408,17 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
                         static_cast<const double *>(x_re), static_cast<const double *>(x_im),
                         static_cast<double *>(c_re), static_cast<double *>(c_im), ld, alpha, beta};
     e = launch_cgemm_f64(g, tile, o, s);
+  } else if (precision == QME_BF16X3) {
+    if (tile != 64 || o.b_rows) { set_error("BF16X3 products use tile 64 and the M^T / M^H forms"); return QME_E_ARG; }
+    CgemmArgs<float> g{static_cast<const float *>(a_re), static_cast<const float *>(a_im),
+                       static_cast<const float *>(m_re), static_cast<const float *>(m_im),
+                       static_cast<const float *>(x_re), static_cast<const float *>(x_im),
+                       static_cast<float *>(c_re), static_cast<float *>(c_im), ld,
+                       float(alpha), float(beta)};
+    e = launch_cgemm_bf16x3(g, o, s);
   } else {
-    set_error("qme_cgemm supports QME_FP32 and QME_FP64");
-    return QME_E_UNSUPPORTED;
+    set_error("unknown precision");
+    return QME_E_ARG;
   }
   if (e != hipSuccess) { set_error(std::string("launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
   return QME_OK;
@@ -416,7 +429,9 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   auto ok = [&](int t) {
-    bool valid = c->precision == QME_FP64 ? (t == 64 || t == 32) : (t == 128 || t == 64);
+    bool valid = c->precision == QME_FP64   ? (t == 64 || t == 32)
+                 : c->precision == QME_FP32 ? (t == 128 || t == 64)
+                                            : t == 64;
     return valid && c->ld % t == 0;
   };
   if (!ok(tile1) || !ok(tile2)) {

@@ -30,6 +30,8 @@ hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &
                             hipStream_t s);
 hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, const GemmOps &o,
                             hipStream_t s);
+// Split-BF16x3 products on FP32 planes (tile 64, NT forms only).
+hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s);
 
 // Fused decoherence step on the rotated state Z (lower triangle valid):
 //   X = scale * Herm(Z + dt * D(Z)),  D(Z)[u,v] = sum_j cg_j[u] cg_j[v]

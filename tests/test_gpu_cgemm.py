@@ -27,7 +27,7 @@ def planes(rng, ld, n, dtype):
 
 
 def run(prec, ld, n, tile, conj_m, lower, alpha, beta, seed=0, conj_a=False, b_rows=False):
-    dtype = np.float32 if prec == L.FP32 else np.float64
+    dtype = np.float64 if prec == L.FP64 else np.float32
     rng = np.random.default_rng(seed)
     ar, ai = planes(rng, ld, n, dtype)
     mr, mi = planes(rng, ld, n, dtype)
@@ -120,3 +120,13 @@ def test_cgemm_accumulate_in_place():
     b = br + 1j * bi.astype(np.float64)
     ref = a @ b + (cr + 1j * ci.astype(np.float64))
     assert np.abs(got - ref).max() < 1e-6 * n + 1e-5
+
+
+@pytest.mark.parametrize("ld,n", [(64, 64), (192, 150), (512, 500)])
+@pytest.mark.parametrize("conj_a,conj_b,lower", [(False, True, False), (False, True, True),
+                                                 (True, True, False), (False, False, True),
+                                                 (True, False, False)])
+def test_cgemm_bf16x3(ld, n, conj_a, conj_b, lower):
+    """Split-bf16 products of FP32 operands: accurate to FP32 rounding."""
+    err, scale = run(L.BF16X3, ld, n, 64, conj_b, lower, 1.0, 1.0, conj_a=conj_a)
+    assert err < 1e-6 * n + 1e-5
