@@ -207,6 +207,72 @@ __global__ void set_diag_kernel(T *x_re, T *x_im, int64_t ld, int64_t n, const d
   x_im[e] = T(0);
 }
 
+// ---------------------------------------------- Frechet finalisation (FP64)
+// W = L(B, G) for B = -i tau H by the series of the adjoint of the Frechet
+// derivative of exp: M_1 = G, R_1 = G B, M_{k+1} = (B M_k + R_k) / (k+1),
+// R_{k+1} = R_k B / (k+1), W = sum_k M_k.  H is sparse (CSR, symmetric), so
+// every product is a sparse-times-dense pass.
+
+template <typename T>
+__global__ void widen_kernel(const T *gr, const T *gi, double *dr, double *di, int64_t total) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < total) {
+    dr[e] = double(gr[e]);
+    di[e] = double(gi[e]);
+  }
+}
+
+// out = inv (B X + R), W += out      (row i of B X uses row i of H)
+__global__ void frechet_left_kernel(const int64_t *ptr, const int32_t *col, const double *val,
+                                    double tau, const double *xr, const double *xi,
+                                    const double *rr, const double *ri, double *outr,
+                                    double *outi, double *wr, double *wi, int64_t n, int64_t ld,
+                                    double inv) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) {
+    const int64_t o = int64_t(col[q]) * ld + j;
+    ar += val[q] * xr[o];
+    ai += val[q] * xi[o];
+  }
+  const int64_t o = i * ld + j;
+  // B X = -i tau (H X): real part tau Im(HX), imaginary part -tau Re(HX)
+  const double vr = inv * (tau * ai + rr[o]);
+  const double vi = inv * (-tau * ar + ri[o]);
+  outr[o] = vr;
+  outi[o] = vi;
+  wr[o] += vr;
+  wi[o] += vi;
+}
+
+// out = inv X B                      ((X H)[i][j] = sum over row j of H)
+__global__ void frechet_right_kernel(const int64_t *ptr, const int32_t *col, const double *val,
+                                     double tau, const double *xr, const double *xi,
+                                     double *outr, double *outi, int64_t n, int64_t ld,
+                                     double inv) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t q = ptr[j]; q < ptr[j + 1]; ++q) {
+    const int64_t o = i * ld + col[q];
+    ar += val[q] * xr[o];
+    ai += val[q] * xi[o];
+  }
+  const int64_t o = i * ld + j;
+  outr[o] = inv * tau * ai;
+  outi[o] = -inv * tau * ar;
+}
+
+// out[e] = Im W[col_e][row_e] * val_e  (tr(W H_p) gathers W transposed)
+__global__ void term_gather_kernel(const double *wi, const int32_t *trow, const int32_t *tcol,
+                                   const double *tval, int64_t ne, int64_t ld, double *out) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < ne) out[e] = wi[int64_t(tcol[e]) * ld + trow[e]] * tval[e];
+}
+
 template <typename T>
 hipError_t launch_adj_dissipate(const AdjArgs<T> &a, hipStream_t s) {
   const int tiles = int((a.n + kAdjTile - 1) / kAdjTile);
@@ -268,6 +334,7 @@ struct AdjLayout {
   int64_t nseg = 0, seg = 0;
   size_t S = 0, cp = 0, R = 0, Zs = 0, Y = 0, lam = 0, mu = 0, X = 0, G = 0;
   size_t rowbuf = 0, colbuf = 0, gbuf = 0, q = 0, o = 0, grad = 0, diag = 0, total = 0;
+  size_t fw = 0, fm = 0, fm2 = 0, fr = 0, fr2 = 0, fterm = 0;
   int tiles = 0, blocks = 0;
 };
 
@@ -300,6 +367,13 @@ static AdjLayout adj_layout(const qme_ctx *c, int64_t n_steps, int32_t every) {
   L.o = take(sizeof(double) * n);
   L.grad = take(sizeof(double) * std::max<size_t>(1, c->model.jumps.size()));
   L.diag = take(sizeof(double) * n);
+  const size_t p2d = 2 * plane_elems(c) * sizeof(double);
+  L.fw = take(p2d);
+  L.fm = take(p2d);
+  L.fm2 = take(p2d);
+  L.fr = take(p2d);
+  L.fr2 = take(p2d);
+  L.fterm = take(sizeof(double) * std::max<size_t>(1, size_t(c->term_offset.back())));
   L.total = off;
   return L;
 }
@@ -405,33 +479,94 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
     }
   }
 
-  // finalisation on the host in FP64
-  std::vector<T> gh(2 * pe);
   std::vector<double> gam(std::max(1, nj));
-  ADJ_OK(hipMemcpyAsync(gh.data(), g_re, sizeof(T) * 2 * pe, hipMemcpyDeviceToHost, s));
   ADJ_OK(hipMemcpyAsync(gam.data(), ggam, sizeof(double) * gam.size(), hipMemcpyDeviceToHost, s));
-  ADJ_OK(hipStreamSynchronize(s));
-  std::vector<double> gr(size_t(n) * n), gi(size_t(n) * n), wr, wi;
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t j = 0; j < n; ++j) {
-      gr[size_t(i) * n + j] = double(gh[size_t(i) * c->ld + j]);
-      gi[size_t(i) * n + j] = double(gh[pe + size_t(i) * c->ld + j]);
-    }
-  std::string err;
-  if (!frechet_adjoint(c->model, c->h, gr, gi, wr, wi, err)) {
-    set_error(err);
-    return QME_E_NUMERIC;
-  }
-  const std::vector<TermCoo> terms = hamiltonian_terms(c->model);
+  const size_t n_terms = c->term_offset.size() - 1;
   const double dt = c->model.dt;
-  for (size_t p = 0; p < terms.size(); ++p) {
-    // tr(W H_p) = sum_{(r,c)} W[c][r] H_p[r][c]; only its imaginary part is used
-    double im = 0.0;
-    for (size_t e = 0; e < terms[p].val.size(); ++e)
-      im += wi[size_t(terms[p].col[e]) * n + terms[p].row[e]] * terms[p].val[e];
-    grad[p] = 2.0 * dt * im;
+  if (c->squarings == 0) {
+    // finalisation on the device in FP64
+    const int64_t ld = c->ld;
+    auto dpl = [&](size_t off) {
+      double *re = reinterpret_cast<double *>(ws + off);
+      return std::make_pair(re, re + pe);
+    };
+    auto [w_re, w_im] = dpl(L.fw);
+    auto [m_re, m_im] = dpl(L.fm);
+    auto [m2_re, m2_im] = dpl(L.fm2);
+    auto [r_re, r_im] = dpl(L.fr);
+    auto [r2_re, r2_im] = dpl(L.fr2);
+    const int64_t total = int64_t(pe);
+    const dim3 eb(256), eg(unsigned((total + 255) / 256));
+    hipLaunchKernelGGL(widen_kernel<T>, eg, eb, 0, s, g_re, g_im, m_re, m_im, total);
+    ADJ_OK(hipGetLastError());
+    hipLaunchKernelGGL(widen_kernel<T>, eg, eb, 0, s, g_re, g_im, w_re, w_im, total);
+    ADJ_OK(hipGetLastError());
+    const double tau = dt;
+    const dim3 sg(unsigned((n + 255) / 256), unsigned(n));
+    hipLaunchKernelGGL(frechet_right_kernel, sg, eb, 0, s, c->h_ptr, c->h_col, c->h_val, tau,
+                       m_re, m_im, r_re, r_im, n, ld, 1.0);
+    ADJ_OK(hipGetLastError());
+    // number of terms: theta^k / k! below 1e-18 with theta = tau |H|_1
+    const double theta = tau * c->h_norm1;
+    int kmax = 1;
+    for (double term = theta; kmax < 60 && (term > 1e-18 || double(kmax) < theta);) {
+      ++kmax;
+      term *= theta / double(kmax);
+    }
+    for (int k = 1; k <= kmax; ++k) {
+      const double inv = 1.0 / double(k + 1);
+      hipLaunchKernelGGL(frechet_left_kernel, sg, eb, 0, s, c->h_ptr, c->h_col, c->h_val, tau,
+                         m_re, m_im, r_re, r_im, m2_re, m2_im, w_re, w_im, n, ld, inv);
+      ADJ_OK(hipGetLastError());
+      hipLaunchKernelGGL(frechet_right_kernel, sg, eb, 0, s, c->h_ptr, c->h_col, c->h_val, tau,
+                         r_re, r_im, r2_re, r2_im, n, ld, inv);
+      ADJ_OK(hipGetLastError());
+      std::swap(m_re, m2_re);
+      std::swap(m_im, m2_im);
+      std::swap(r_re, r2_re);
+      std::swap(r_im, r2_im);
+    }
+    const int64_t ne = c->term_offset.back();
+    std::vector<double> te(std::max<int64_t>(1, ne));
+    double *fterm = reinterpret_cast<double *>(ws + L.fterm);
+    if (ne > 0) {
+      hipLaunchKernelGGL(term_gather_kernel, dim3(unsigned((ne + 255) / 256)), eb, 0, s, w_im,
+                         c->t_row, c->t_col, c->t_val, ne, ld, fterm);
+      ADJ_OK(hipGetLastError());
+      ADJ_OK(hipMemcpyAsync(te.data(), fterm, sizeof(double) * ne, hipMemcpyDeviceToHost, s));
+    }
+    ADJ_OK(hipStreamSynchronize(s));
+    for (size_t p = 0; p < n_terms; ++p) {
+      double im = 0.0;
+      for (int64_t e = c->term_offset[p]; e < c->term_offset[p + 1]; ++e) im += te[e];
+      grad[p] = 2.0 * dt * im;
+    }
+  } else {
+    // scaling and squaring was needed: finalise on the host in FP64
+    std::vector<T> gh(2 * pe);
+    ADJ_OK(hipMemcpyAsync(gh.data(), g_re, sizeof(T) * 2 * pe, hipMemcpyDeviceToHost, s));
+    ADJ_OK(hipStreamSynchronize(s));
+    std::vector<double> gr(size_t(n) * n), gi(size_t(n) * n), wr, wi;
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < n; ++j) {
+        gr[size_t(i) * n + j] = double(gh[size_t(i) * c->ld + j]);
+        gi[size_t(i) * n + j] = double(gh[pe + size_t(i) * c->ld + j]);
+      }
+    std::string err;
+    if (!frechet_adjoint(c->model, c->h, gr, gi, wr, wi, err)) {
+      set_error(err);
+      return QME_E_NUMERIC;
+    }
+    const std::vector<TermCoo> terms = hamiltonian_terms(c->model);
+    for (size_t p = 0; p < terms.size(); ++p) {
+      // tr(W H_p) = sum_{(r,c)} W[c][r] H_p[r][c]; only its imaginary part is used
+      double im = 0.0;
+      for (size_t e = 0; e < terms[p].val.size(); ++e)
+        im += wi[size_t(terms[p].col[e]) * n + terms[p].row[e]] * terms[p].val[e];
+      grad[p] = 2.0 * dt * im;
+    }
   }
-  for (int j = 0; j < nj; ++j) grad[terms.size() + j] = gam[j];
+  for (int j = 0; j < nj; ++j) grad[n_terms + j] = gam[j];
   return QME_OK;
 }
 

@@ -166,7 +166,8 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   std::vector<double> v;
   hamiltonian_coo(c->model, r, cc, v);
   c->h = to_csr(c->n, r, cc, v);
-  if (!propagator_increment(c->model, c->h, c->du_re_host, c->du_im_host, err)) {
+  if (!propagator_increment(c->model, c->h, c->du_re_host, c->du_im_host, err, nullptr,
+                            &c->squarings)) {
     set_error(err);
     return QME_E_NUMERIC;
   }
@@ -235,6 +236,42 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   if (nj > 0) {
     HIP_OK(hipMemcpy(c->ada, c->jt.unit_ada.data(), sizeof(double) * c->jt.unit_ada.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->arrival_of, c->jt.arrival_of.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice));
+  }
+  // Hamiltonian CSR and the parameter terms (device Frechet finalisation)
+  for (int64_t i = 0; i < n; ++i) {
+    double rs = 0.0;
+    for (int64_t q = c->h.ptr[i]; q < c->h.ptr[i + 1]; ++q) rs += std::fabs(c->h.val[q]);
+    c->h_norm1 = std::max(c->h_norm1, rs);
+  }
+  const size_t nnz = std::max<size_t>(1, c->h.val.size());
+  HIP_OK(hipMalloc(&c->h_ptr, sizeof(int64_t) * (n + 1)));
+  HIP_OK(hipMalloc(&c->h_col, sizeof(int32_t) * nnz));
+  HIP_OK(hipMalloc(&c->h_val, sizeof(double) * nnz));
+  HIP_OK(hipMemcpy(c->h_ptr, c->h.ptr.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+  if (!c->h.val.empty()) {
+    HIP_OK(hipMemcpy(c->h_col, c->h.col.data(), sizeof(int32_t) * c->h.col.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->h_val, c->h.val.data(), sizeof(double) * c->h.val.size(), hipMemcpyHostToDevice));
+  }
+  {
+    const std::vector<TermCoo> terms = hamiltonian_terms(c->model);
+    std::vector<int32_t> tr, tc;
+    std::vector<double> tv;
+    c->term_offset.assign(1, 0);
+    for (const TermCoo &t : terms) {
+      tr.insert(tr.end(), t.row.begin(), t.row.end());
+      tc.insert(tc.end(), t.col.begin(), t.col.end());
+      tv.insert(tv.end(), t.val.begin(), t.val.end());
+      c->term_offset.push_back(int64_t(tv.size()));
+    }
+    const size_t ne = std::max<size_t>(1, tv.size());
+    HIP_OK(hipMalloc(&c->t_row, sizeof(int32_t) * ne));
+    HIP_OK(hipMalloc(&c->t_col, sizeof(int32_t) * ne));
+    HIP_OK(hipMalloc(&c->t_val, sizeof(double) * ne));
+    if (!tv.empty()) {
+      HIP_OK(hipMemcpy(c->t_row, tr.data(), sizeof(int32_t) * tr.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(c->t_col, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(c->t_val, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice));
+    }
   }
   *out = c.release();
   return QME_OK;
@@ -479,7 +516,9 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
 qme_ctx::~qme_ctx() {
   for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *p : {du_re, du_im, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
-                  (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of})
+                  (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,
+                  (void *)h_ptr, (void *)h_col, (void *)h_val, (void *)t_row, (void *)t_col,
+                  (void *)t_val})
     if (p) (void)hipFree(p);
 }
 

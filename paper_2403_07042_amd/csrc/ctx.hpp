@@ -33,6 +33,16 @@ struct qme_ctx {
   double *ada = nullptr;      // [n_jumps x n]
   int32_t *arrival_of = nullptr;   // [n_jumps]
   int n_arrival = 0;
+  // Hamiltonian (CSR, FP64) and the per-parameter term entries, for the
+  // device-side Frechet finalisation of the adjoint
+  int64_t *h_ptr = nullptr;
+  int32_t *h_col = nullptr;
+  double *h_val = nullptr;
+  int32_t *t_row = nullptr, *t_col = nullptr;
+  double *t_val = nullptr;
+  std::vector<int64_t> term_offset;   // host: entries of term p are [off[p], off[p+1])
+  int squarings = 0;                  // of the propagator build
+  double h_norm1 = 0.0;               // |H|_1
 
   // per-kernel timing (qme_profile_enable / qme_profile_read)
   bool profiling = false;

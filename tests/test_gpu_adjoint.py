@@ -132,3 +132,19 @@ def test_autograd_function():
     f_ref, g_ref = gr.gradient(s, rho0, 40, obs)
     assert abs(f.item() - f_ref) < 1e-12
     assert rel(theta.grad.numpy(), g_ref) < 1e-9
+
+
+def test_adjoint_with_scaling_and_squaring_fp64():
+    """|H dt| > 1/2: the propagator needs squarings and the Frechet
+    finalisation undoes them (host FP64 path)."""
+    wl = dict(small_open(), dt=1.3, steps=12)
+    s = ev.System(wl)
+    rho0 = W.initial_rho(wl, s.occ)
+    obs = md.photon_number(wl, s.occ).astype(float)
+    f_ref, g_ref = gr.gradient(s, rho0, 12, obs)
+    sol = P.Solver(wl, "fp64")
+    sol.set_rho(rho0)
+    f, g = sol.adjoint(12, obs, checkpoint_every=5)
+    sol.close()
+    assert abs(f - f_ref) < 1e-11
+    assert rel(g, g_ref) < 1e-9
