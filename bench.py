@@ -30,6 +30,22 @@ PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6       # TFLOP/s, MI355X dense FP64 matrix
 PEAK_HBM = 8000.0           # GB/s
 
+# HBM bytes per launch of the first FP32 product, from the FETCH_SIZE /
+# WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
+# profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
+# cgemm.hip; reported as null once the kernel source differs.
+TRAFFIC_FP32_PRODUCT = {"bytes": (393453.6 + 32768.0) * 1024,
+                        "sha256": "a7fb55ff7ad60e4082c180b44be803bf8e0d848a96b0235ef0b5ca7d4c703844",
+                        "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2403_07042_amd", "csrc", "cgemm.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    return TRAFFIC_FP32_PRODUCT["bytes"] if digest == TRAFFIC_FP32_PRODUCT["sha256"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -44,6 +60,10 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="steps of the timed FP32 adjoint (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
+    ap.add_argument("--adjoint-all-resident", type=int, default=1,
+                    help="also time the adjoint with every state kept in HBM (no recompute)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB moved by one plain device copy after the legs (counter calibration)")
     ap.add_argument("--tiles32", default="", help="tile1,tile2 override for the FP32 leg")
     ap.add_argument("--tiles64", default="", help="tile1,tile2 override for the FP64 leg")
     return ap.parse_args()
@@ -161,10 +181,26 @@ def main():
         res["fp64"] = timed_leg(P, W, torch, wl, "fp64", args.fp64_steps, min(args.warmup, 5),
                                 args.tiles64)
 
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     adj = None
     if args.adjoint_steps > 0:
         adj = adjoint_leg(P, W, torch, wl, args.adjoint_steps, args.checkpoint_every)
+        if args.adjoint_all_resident:
+            full = adjoint_leg(P, W, torch, wl, args.adjoint_steps, args.adjoint_steps)
+            adj["all_resident_ms_per_step"] = full["ms_per_step"]
+            adj["all_resident_matches"] = (full["dvalue_dmu"] == adj["dvalue_dmu"]
+                                           and full["dvalue_dg"] == adj["dvalue_dg"])
 
+    if not res:
+        print(json.dumps({"metric": METRIC, "value": None, "note": "no timed leg selected"}))
+        return
     main_leg = res.get("fp32") or res.get("fp64")
     prec = "fp32" if "fp32" in res else "fp64"
     peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_FP64_MFMA
@@ -172,8 +208,12 @@ def main():
     achieved = flops_product / (avg_us * 1e-6) / 1e12
     roofline = {"bound": "mfma", "kernel": f"cgemm_{prec} (first product, full tiles)",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "algorithmic_per_launch": f"8*N^3 = {flops_product:.4g} flop (N=2048)"}
+                "frac": achieved / peak,
+                "traffic": measured_traffic() if prec == "fp32" else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "copy-calibrated; " + TRAFFIC_FP32_PRODUCT["source"] + ")",
+                "algorithmic_per_launch": f"8*N^3 = {flops_product:.4g} flop (N=2048); "
+                                          f"operand bytes 3*8*N^2 = {24.0 * n * n:.4g}"}
 
     cpu, parity = None, None
     if args.cpu_steps > 0:

@@ -417,12 +417,27 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
   auto [g_re, g_im] = planes(L.G);
   const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
 
-  // forward pass with checkpoints
+  // forward pass with checkpoints; the last segment is run straight into the
+  // recompute buffers R / Zs, so it is not recomputed in the backward pass
+  char *R = ws + L.R;
+  // the decoherence passes write rows/columns < n only: the padding of the
+  // recomputed states must be zero for the products that read them
+  ADJ_OK(hipMemsetAsync(R, 0, sba * size_t(L.seg + 1), s));
   ADJ_OK(hipMemcpyAsync(S, state0, sb, hipMemcpyDeviceToDevice, s));
   for (int64_t g = 0; g < L.nseg; ++g) {
     ADJ_OK(hipMemcpyAsync(ws + L.cp + size_t(g) * sba, S, sb, hipMemcpyDeviceToDevice, s));
     const int64_t len = std::min<int64_t>(L.seg, n_steps - g * L.seg);
-    for (int64_t i = 0; i < len; ++i) ADJ_OK(step_once<T>(c, S, S, ws + L.Y, ws + L.Zs, s));
+    if (g + 1 < L.nseg) {
+      for (int64_t i = 0; i < len; ++i) ADJ_OK(step_once<T>(c, S, S, ws + L.Y, ws + L.Zs, s));
+    } else {
+      ADJ_OK(hipMemcpyAsync(R, S, sb, hipMemcpyDeviceToDevice, s));
+      for (int64_t i = 0; i < len; ++i)
+        ADJ_OK(step_once<T>(c, R + size_t(i) * sba, R + size_t(i + 1) * sba, ws + L.Y,
+                            ws + L.Zs + size_t(i) * p2, s));
+      const int64_t last = n_steps - g * L.seg;
+      if (last != len) { set_error("internal: segment length mismatch"); return QME_E_STATE; }
+      ADJ_OK(hipMemcpyAsync(S, R + size_t(len) * sba, sb, hipMemcpyDeviceToDevice, s));
+    }
   }
   // objective
   double *diag = reinterpret_cast<double *>(ws + L.diag);
@@ -440,10 +455,9 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
   ADJ_OK(hipMemcpyAsync(o_dev, obs, sizeof(double) * n, hipMemcpyHostToDevice, s));
   ADJ_OK(launch_set_diag<T>(lam_re, lam_im, c->ld, n, o_dev, s));
   ADJ_OK(hipMemsetAsync(ws + L.G, 0, p2, s));
-  // the decoherence passes write rows/columns < n only: the padding of mu and
-  // of the recomputed states must be zero for the products that read them
+  // the adjoint decoherence pass writes rows/columns < n only: the padding
+  // of mu must be zero for the products that read it
   ADJ_OK(hipMemsetAsync(ws + L.mu, 0, p2, s));
-  ADJ_OK(hipMemsetAsync(ws + L.R, 0, sba * size_t(L.seg + 1), s));
   ADJ_OK(hipMemsetAsync(ggam, 0, sizeof(double) * std::max(1, nj), s));
 
   AdjArgs<T> aa{lam_re, lam_im, mu_re, mu_im, nullptr, nullptr, c->ld, n, c->model.dt, c->d,
@@ -459,11 +473,12 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
 
   for (int64_t g = L.nseg - 1; g >= 0; --g) {
     const int64_t len = std::min<int64_t>(L.seg, n_steps - g * L.seg);
-    char *R = ws + L.R;
-    ADJ_OK(hipMemcpyAsync(R, ws + L.cp + size_t(g) * sba, sb, hipMemcpyDeviceToDevice, s));
-    for (int64_t i = 0; i < len; ++i)
-      ADJ_OK(step_once<T>(c, R + size_t(i) * sba, R + size_t(i + 1) * sba, ws + L.Y,
-                          ws + L.Zs + size_t(i) * p2, s));
+    if (g + 1 < L.nseg) {   // recompute the segment from its checkpoint
+      ADJ_OK(hipMemcpyAsync(R, ws + L.cp + size_t(g) * sba, sb, hipMemcpyDeviceToDevice, s));
+      for (int64_t i = 0; i < len; ++i)
+        ADJ_OK(step_once<T>(c, R + size_t(i) * sba, R + size_t(i + 1) * sba, ws + L.Y,
+                            ws + L.Zs + size_t(i) * p2, s));
+    }
     for (int64_t i = len - 1; i >= 0; --i) {
       auto [z_re, z_im] = planes(L.Zs + size_t(i) * p2);
       aa.z_re = z_re;
