@@ -213,6 +213,37 @@ qme_status qme_adjoint(qme_ctx *ctx, const void *state0_dev, int64_t n_steps,
 qme_status qme_adjoint_workspace_size(const qme_ctx *ctx, int64_t n_steps,
                                       int32_t checkpoint_every, size_t *bytes);
 
+/* ------------------------------------------------------- batched instances */
+
+typedef struct qme_batch qme_batch;
+
+/* Bind `count` FP32 contexts and their device state buffers (one each,
+ * layouts from qme_state_layout, 256-byte aligned) into a batch.  Each step
+ * of the batch is one launch per phase (first product, lower-triangle
+ * product, trace/sink pass, decoherence pass) covering the tiles of every
+ * instance, largest instances first; a run of n steps is captured once into
+ * a hipGraph and replayed.  Each instance advances exactly as under qme_step
+ * (the same tile arithmetic: bitwise-identical results).  The contexts and
+ * states must outlive the batch. */
+qme_status qme_batch_create(qme_ctx *const *ctxs, void *const *states_dev, int32_t count,
+                            qme_batch **out);
+
+/* Device workspace of a batch (the products' scratch planes of every
+ * instance). */
+qme_status qme_batch_workspace_size(const qme_batch *batch, size_t *bytes);
+
+/* Whether runs are captured into (and replayed from) a hipGraph per
+ * (n_steps, workspace), and whether larger instances come first in each
+ * phase launch.  Synchronises the device. */
+qme_status qme_batch_config(qme_batch *batch, int32_t use_graph, int32_t largest_first);
+
+/* Advance every instance by n_steps on hip_stream (asynchronous). */
+qme_status qme_batch_step(qme_batch *batch, int64_t n_steps, void *workspace_dev,
+                          size_t workspace_bytes, void *hip_stream);
+
+/* Release a batch (not its contexts or states). NULL is ignored. */
+void qme_batch_destroy(qme_batch *batch);
+
 /* The planar complex product used by every step and by the adjoint:
  *     C = alpha * opA(A) * opB(B) + beta * X
  * on ld x ld row-major planes in device memory (FP64 for QME_FP64, FP32 for

@@ -196,3 +196,46 @@ class Solver:
         cnt = (c_int64 * 4)()
         L.check(self.lib.qme_profile_read(self.ctx, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KINDS)}
+
+
+class Batch:
+    """Many FP32 solvers stepped together: one launch per phase covers every
+    instance's tiles; a run of steps is replayed from one captured hipGraph."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        if not self.solvers:
+            raise ValueError("empty batch")
+        self.lib = L.load()
+        self.torch = self.solvers[0].torch
+        n = len(self.solvers)
+        ctxs = (c_void_p * n)(*[s.ctx.value for s in self.solvers])
+        states = (c_void_p * n)(*[s.state.data_ptr() for s in self.solvers])
+        b = c_void_p()
+        L.check(self.lib.qme_batch_create(ctxs, states, n, byref(b)))
+        self.handle = b
+        ws = c_size_t()
+        L.check(self.lib.qme_batch_workspace_size(b, byref(ws)))
+        self.workspace_bytes = ws.value
+        self.workspace = self.torch.zeros(max(ws.value, 256), dtype=self.torch.uint8,
+                                          device=self.solvers[0].state.device)
+        self.stream = self.solvers[0].stream
+
+    def config(self, use_graph=True, largest_first=True):
+        L.check(self.lib.qme_batch_config(self.handle, int(use_graph), int(largest_first)))
+
+    def step(self, n_steps: int):
+        L.check(self.lib.qme_batch_step(self.handle, int(n_steps),
+                                        c_void_p(self.workspace.data_ptr()),
+                                        self.workspace_bytes, c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.qme_batch_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

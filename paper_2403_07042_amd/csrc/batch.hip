@@ -1,0 +1,348 @@
+// Batched time steps of many independent instances of uneven size.
+//
+// Every instance's step is the same four phases as the per-instance path
+// (product T = rho + dU rho, lower-triangle product rho_u, FP64 trace/sink
+// pass, decoherence pass; Sec. II Eqs. 2-3 and the "unitary evolution" stage
+// of Sec. IV.B).  One launch per phase covers that phase's tiles of EVERY
+// instance (instances ordered largest first; a block finds its instance and
+// tile by a binary search over per-instance item offsets), so the grid stays
+// full even when single instances are small.  Phases are ordered by the
+// stream, never by waits between workgroups.  A run of n steps (4 n
+// launches) is captured once into a hipGraph and replayed with one launch.
+// The tile arithmetic is the per-instance kernels' own, so every instance
+// advances bitwise as under qme_step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cgemm_tile.hpp"
+#include "ctx.hpp"
+#include "device.hpp"
+#include "dissipate_tile.hpp"
+#include "qme.h"
+
+namespace qme {
+
+struct BatchInstance {
+  float *x_re, *x_im;
+  double *aux;
+  float *y_re, *y_im, *z_re, *z_im;
+  const float *u_re, *u_im;
+  const double *d, *leak, *cg;
+  const int32_t *pi;
+  int64_t n, ld;
+  double dt;
+  int32_t tiles, n_gather;
+  uint32_t items[4];   // per phase: tiles^2, lower tiles, 1, lower tiles (decoherence)
+};
+
+struct BatchPhase {
+  const BatchInstance *inst;
+  const int32_t *order;        // queue position -> instance
+  const int64_t *off;          // [count + 1] item prefix of this phase per queue position
+  int32_t count;
+};
+
+static constexpr int kBatchThreads = 256;
+
+__device__ __forceinline__ void tri_coords(int t, int &bi, int &bj) {
+  int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  bi = r;
+  bj = t - r * (r + 1) / 2;
+}
+
+template <int PHASE>
+__global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p) {
+  constexpr int kSmemFloats = PHASE <= 1 ? cgemm_f32_smem<64, kConjB>()
+                              : PHASE == 2 ? 3 * kBatchThreads * 2
+                                           : 2 * TD * (TD + 1);
+  __shared__ float smem[kSmemFloats];
+  const int64_t r = blockIdx.x;
+  int lo = 0, hi = p.count;   // largest position with off[pos] <= r
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (p.off[mid] <= r) lo = mid; else hi = mid;
+  }
+  const BatchInstance &in = p.inst[p.order[lo]];
+  const int tile = int(r - p.off[lo]);
+  if constexpr (PHASE == 0) {
+    const CgemmArgs<float> g{in.u_re, in.u_im, in.x_re, in.x_im, in.x_re, in.x_im,
+                             in.y_re, in.y_im, in.ld, 1.0f, 1.0f};
+    cgemm_f32_tile<64, kConjB>(g, tile / in.tiles, tile % in.tiles, smem);
+  } else if constexpr (PHASE == 1) {
+    int bi, bj;
+    tri_coords(tile, bi, bj);
+    const CgemmArgs<float> g{in.y_re, in.y_im, in.u_re, in.u_im, in.y_re, in.y_im,
+                             in.z_re, in.z_im, in.ld, 1.0f, 1.0f};
+    cgemm_f32_tile<64, kConjB>(g, bi, bj, smem);
+  } else {
+    const DissArgs<float> da{in.z_re, in.z_im, in.x_re, in.x_im, in.ld, in.n, in.dt, in.d,
+                             in.leak, in.pi, in.cg, in.n_gather, in.aux, in.aux};
+    if constexpr (PHASE == 2) {
+      double *sd = reinterpret_cast<double *>(smem);
+      trace_body<float, kBatchThreads>(da, sd, sd + kBatchThreads, sd + 2 * kBatchThreads);
+    } else {
+      float (*sr)[TD + 1] = reinterpret_cast<float (*)[TD + 1]>(smem);
+      float (*si)[TD + 1] = reinterpret_cast<float (*)[TD + 1]>(smem + TD * (TD + 1));
+      dissipate_tile<float>(da, tile, sr, si);
+    }
+  }
+}
+
+}  // namespace qme
+
+using namespace qme;
+
+struct qme_batch {
+  std::vector<qme_ctx *> ctxs;
+  std::vector<void *> states;
+  int device = 0;
+  int32_t count = 0;
+  bool use_graph = true;
+  bool lpt = true;
+  // device tables (owned)
+  BatchInstance *inst = nullptr;
+  int32_t *order = nullptr;
+  int64_t *phase_off = nullptr;   // [4][count + 1]
+  int64_t phase_items[4] = {0, 0, 0, 0};
+  size_t ws_bytes = 0;
+  std::vector<size_t> ws_off;      // per instance: Y planes offset (Z follows)
+  hipStream_t capture_stream = nullptr;
+  std::map<std::pair<int64_t, void *>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+  void *last_ws = nullptr;
+
+  void drop_graphs() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    for (hipGraph_t g : graph_defs) (void)hipGraphDestroy(g);
+    graph_defs.clear();
+  }
+  void drop_tables() {
+    for (void *p : {(void *)inst, (void *)order, (void *)phase_off})
+      if (p) (void)hipFree(p);
+    inst = nullptr;
+    order = nullptr;
+    phase_off = nullptr;
+    last_ws = nullptr;
+  }
+  ~qme_batch() {
+    drop_graphs();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    drop_tables();
+  }
+};
+
+#define B_OK(call)                                                               \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));              \
+      return QME_E_DEVICE;                                                       \
+    }                                                                            \
+  } while (0)
+
+static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+
+static qme_status build_tables(qme_batch *b) {
+  const int nb = b->count;
+  std::vector<int32_t> ord(nb);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (b->lpt)
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int x, int y) { return b->ctxs[x]->n > b->ctxs[y]->n; });
+  std::vector<BatchInstance> tab(nb);
+  b->ws_off.assign(nb, 0);
+  size_t off = 0;
+  for (int i = 0; i < nb; ++i) {
+    qme_ctx *c = b->ctxs[i];
+    const size_t pe = plane_elems(c);
+    BatchInstance &t = tab[i];
+    t.x_re = static_cast<float *>(b->states[i]);
+    t.x_im = t.x_re + pe;
+    t.aux = reinterpret_cast<double *>(t.x_im + pe);
+    b->ws_off[i] = off;
+    off += a256(4 * pe * sizeof(float));
+    t.y_re = t.y_im = t.z_re = t.z_im = nullptr;   // bound per workspace
+    t.u_re = static_cast<const float *>(c->du_re);
+    t.u_im = static_cast<const float *>(c->du_im);
+    t.d = c->d;
+    t.leak = c->leak;
+    t.cg = c->cg;
+    t.pi = c->pi;
+    t.n = c->n;
+    t.ld = c->ld;
+    t.dt = c->model.dt;
+    t.tiles = int32_t(c->ld / 64);
+    t.n_gather = c->jt.n_gather;
+    const int td = int((c->n + TD - 1) / TD);
+    t.items[0] = uint32_t(t.tiles) * uint32_t(t.tiles);
+    t.items[1] = uint32_t(t.tiles) * uint32_t(t.tiles + 1) / 2;
+    t.items[2] = 1;
+    t.items[3] = uint32_t(td) * uint32_t(td + 1) / 2;
+  }
+  b->ws_bytes = std::max<size_t>(off, 256);
+  std::vector<int64_t> po(4 * (nb + 1), 0);
+  for (int ph = 0; ph < 4; ++ph) {
+    int64_t acc = 0;
+    for (int k = 0; k < nb; ++k) {
+      po[ph * (nb + 1) + k] = acc;
+      acc += tab[ord[k]].items[ph];
+    }
+    po[ph * (nb + 1) + nb] = acc;
+    b->phase_items[ph] = acc;
+  }
+  B_OK(hipMalloc(&b->inst, sizeof(BatchInstance) * nb));
+  B_OK(hipMalloc(&b->order, sizeof(int32_t) * nb));
+  B_OK(hipMalloc(&b->phase_off, sizeof(int64_t) * po.size()));
+  B_OK(hipMemcpy(b->inst, tab.data(), sizeof(BatchInstance) * nb, hipMemcpyHostToDevice));
+  B_OK(hipMemcpy(b->order, ord.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice));
+  B_OK(hipMemcpy(b->phase_off, po.data(), sizeof(int64_t) * po.size(), hipMemcpyHostToDevice));
+  return QME_OK;
+}
+
+// Points the instance table at a workspace (Y / Z planes); synchronous.
+static qme_status bind_workspace(qme_batch *b, char *ws) {
+  if (ws == b->last_ws) return QME_OK;
+  B_OK(hipDeviceSynchronize());   // an earlier launch may still read the table
+  std::vector<BatchInstance> tab(b->count);
+  B_OK(hipMemcpy(tab.data(), b->inst, sizeof(BatchInstance) * b->count, hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->count; ++i) {
+    const size_t pe = plane_elems(b->ctxs[i]);
+    float *y = reinterpret_cast<float *>(ws + b->ws_off[i]);
+    tab[i].y_re = y;
+    tab[i].y_im = y + pe;
+    tab[i].z_re = y + 2 * pe;
+    tab[i].z_im = y + 3 * pe;
+  }
+  B_OK(hipMemcpy(b->inst, tab.data(), sizeof(BatchInstance) * b->count, hipMemcpyHostToDevice));
+  b->last_ws = ws;
+  return QME_OK;
+}
+
+static hipError_t enqueue(qme_batch *b, int64_t n_steps, hipStream_t s) {
+  for (int64_t k = 0; k < n_steps; ++k) {
+    for (int ph = 0; ph < 4; ++ph) {
+      const BatchPhase p{b->inst, b->order, b->phase_off + ph * (b->count + 1), b->count};
+      const dim3 grid(unsigned(b->phase_items[ph])), block(kBatchThreads);
+      switch (ph) {
+        case 0: hipLaunchKernelGGL(batch_phase_kernel<0>, grid, block, 0, s, p); break;
+        case 1: hipLaunchKernelGGL(batch_phase_kernel<1>, grid, block, 0, s, p); break;
+        case 2: hipLaunchKernelGGL(batch_phase_kernel<2>, grid, block, 0, s, p); break;
+        default: hipLaunchKernelGGL(batch_phase_kernel<3>, grid, block, 0, s, p); break;
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+extern "C" qme_status qme_batch_create(qme_ctx *const *ctxs, void *const *states, int32_t count,
+                                       qme_batch **out) {
+  try {
+    set_error("");
+    if (!ctxs || !states || !out || count < 1) { set_error("bad arguments"); return QME_E_ARG; }
+    *out = nullptr;
+    auto b = std::make_unique<qme_batch>();
+    b->count = count;
+    for (int i = 0; i < count; ++i) {
+      qme_ctx *c = ctxs[i];
+      if (!c || !states[i]) { set_error("NULL context or state"); return QME_E_ARG; }
+      if (c->precision != QME_FP32 || c->ld % 64 != 0) {
+        set_error("batched steps need FP32 contexts (leading dimension a multiple of 64)");
+        return QME_E_UNSUPPORTED;
+      }
+      if (reinterpret_cast<uintptr_t>(states[i]) & 255) { set_error("states must be 256-byte aligned"); return QME_E_ARG; }
+      if (i > 0 && c->device != ctxs[0]->device) { set_error("contexts on different devices"); return QME_E_ARG; }
+      b->ctxs.push_back(c);
+      b->states.push_back(states[i]);
+    }
+    b->device = ctxs[0]->device;
+    qme_status st = check_device(ctxs[0]);
+    if (st != QME_OK) return st;
+    st = build_tables(b.get());
+    if (st != QME_OK) return st;
+    *out = b.release();
+    return QME_OK;
+  } catch (const std::exception &e) {
+    set_error(std::string("internal error: ") + e.what());
+    return QME_E_STATE;
+  }
+}
+
+extern "C" qme_status qme_batch_workspace_size(const qme_batch *b, size_t *bytes) {
+  set_error("");
+  if (!b || !bytes) { set_error("NULL argument"); return QME_E_ARG; }
+  *bytes = b->ws_bytes;
+  return QME_OK;
+}
+
+extern "C" qme_status qme_batch_config(qme_batch *b, int32_t use_graph, int32_t largest_first) {
+  set_error("");
+  if (!b) { set_error("NULL batch"); return QME_E_ARG; }
+  qme_status st = check_device(b->ctxs[0]);
+  if (st != QME_OK) return st;
+  B_OK(hipDeviceSynchronize());   // no launch may still use the old graphs or tables
+  b->drop_graphs();
+  b->use_graph = use_graph != 0;
+  if ((largest_first != 0) != b->lpt) {
+    b->lpt = largest_first != 0;
+    b->drop_tables();
+    return build_tables(b);
+  }
+  return QME_OK;
+}
+
+extern "C" qme_status qme_batch_step(qme_batch *b, int64_t n_steps, void *ws, size_t ws_bytes,
+                                     void *hip_stream) {
+  try {
+    set_error("");
+    if (!b || !ws) { set_error("NULL argument"); return QME_E_ARG; }
+    if (n_steps < 0) { set_error("n_steps < 0"); return QME_E_ARG; }
+    if (ws_bytes < b->ws_bytes) { set_error("batch workspace too small"); return QME_E_SIZE; }
+    if (reinterpret_cast<uintptr_t>(ws) & 255) { set_error("workspace must be 256-byte aligned"); return QME_E_ARG; }
+    qme_status st = check_device(b->ctxs[0]);
+    if (st != QME_OK) return st;
+    if (n_steps == 0) return QME_OK;
+    st = bind_workspace(b, static_cast<char *>(ws));
+    if (st != QME_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (!b->use_graph) {
+      B_OK(enqueue(b, n_steps, s));
+      return QME_OK;
+    }
+    auto key = std::make_pair(n_steps, ws);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+      if (!b->capture_stream) B_OK(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      B_OK(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue(b, n_steps, b->capture_stream);
+      hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        set_error(std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        return QME_E_DEVICE;
+      }
+      hipGraphExec_t ex = nullptr;
+      B_OK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      b->graph_defs.push_back(g);
+      it = b->graphs.emplace(key, ex).first;
+    }
+    B_OK(hipGraphLaunch(it->second, s));
+    return QME_OK;
+  } catch (const std::exception &e) {
+    set_error(std::string("internal error: ") + e.what());
+    return QME_E_STATE;
+  }
+}
+
+extern "C" void qme_batch_destroy(qme_batch *b) { delete b; }

@@ -24,358 +24,24 @@
 //     the minus sign of Ai*Bi are applied by negating register fragments;
 //   * LOWER launches only the tiles on or below the diagonal (Hermitian
 //     output), enumerated triangularly.
-#include "device.hpp"
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-typedef double doublex2 __attribute__((ext_vector_type(2)));
+#include "cgemm_tile.hpp"
 
 namespace qme {
 
-static constexpr int kThreads = 256;
-
-enum : int { kConjA = 1, kConjB = 2, kBRow = 4 };
-
-// Tile index -> (bi, bj).  Full grid: the launch order is remapped so that the
-// blocks one XCD receives (block b runs on XCD b % 8) form compact groups of
-// tile rows, which share A rows and B tiles in that XCD's L2.
-__device__ __forceinline__ void tile_coords(int t, int tiles, bool lower, int &bi, int &bj) {
-  if (lower) {
-    int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
-    while ((r + 1) * (r + 2) / 2 <= t) ++r;
-    while (r * (r + 1) / 2 > t) --r;
-    bi = r;
-    bj = t - r * (r + 1) / 2;
-    return;
-  }
-  int nb = tiles * tiles;
-  int tt = t;
-  if ((nb & 7) == 0) tt = (t & 7) * (nb >> 3) + (t >> 3);
-  const int group = 4;
-  int gsz = group * tiles;
-  int g = tt / gsz;
-  int first = g * group;
-  int rows = min(group, tiles - first);
-  int in = tt - g * gsz;
-  bi = first + in % rows;
-  bj = in / rows;
-}
-
-// The four real products of one complex multiply-add, signs folded into
-// fragment negations.  a*/b*: fragments; mfma(x, y, acc) accumulates x*y.
-//   Cr += Ar Br - sA sB Ai Bi,   Ci += sB Ar Bi + sA Ai Br
-template <int OPS, typename V, typename S, typename F>
-__device__ __forceinline__ void cmac(V &cr, V &ci, S ar, S ai, S br, S bi, F mfma) {
-  constexpr bool ca = OPS & kConjA, cb = OPS & kConjB;
-  cr = mfma(ar, br, cr);
-  ci = mfma(ca ? -ai : ai, br, ci);
-  cr = mfma((ca != cb) ? ai : -ai, bi, cr);
-  ci = mfma(ar, cb ? -bi : bi, ci);
-}
-
-// ----------------------------------------------------------------- FP32
-// v_mfma_f32_32x32x2_f32: A 32x2 (lane l: row l%32, k-slot l/32), B 2x32
-// (lane l: k-slot l/32, col l%32), D 32x32 in 16 registers (lane l: col l%32,
-// register r: row 8*(r/4) + 4*(l/32) + r%4).
-
 template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
-  constexpr bool BROW = OPS & kBRow;
-  constexpr int KT = 16;
-  constexpr int LDK = KT + 4;          // padded LDS row of A / NT-B (floats)
-  constexpr int LDJ = BM + 4;          // padded LDS row of NN-B (floats)
-  constexpr int WM = BM / 2;           // wave tile
-  constexpr int F = WM / 32;           // 32x32 blocks per wave side
-  constexpr int PASSES = BM / 64;      // 64 rows per load pass (4 float4 per row)
-  constexpr int BSZ = BROW ? KT * LDJ : BM * LDK;
-  constexpr int BPASS = BROW ? (KT * BM / 4) / kThreads : PASSES;
-  __shared__ float sA[2][2][BM * LDK];
-  __shared__ float sB[2][2][BSZ];
-
-  const int tiles = int(p.ld / BM);
+  __shared__ float smem[cgemm_f32_smem<BM, OPS>()];
   int bi, bj;
-  tile_coords(blockIdx.x, tiles, LOWER, bi, bj);
-  const int64_t ld = p.ld;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int li = lane & 31, h = lane >> 5;
-
-  const int lr = tid >> 2, lk = (tid & 3) * 4;
-  const float *ga_re = p.a_re + (int64_t(bi) * BM + lr) * ld + lk;
-  const float *ga_im = p.a_im + (int64_t(bi) * BM + lr) * ld + lk;
-  // NT: rows j of M;  NN: rows k of B, columns bj*BM + ...
-  const int br_k = tid / (BM / 4), br_j = (tid % (BM / 4)) * 4;
-  const float *gb_re = BROW ? p.m_re + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
-                            : p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
-  const float *gb_im = BROW ? p.m_im + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
-                            : p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
-
-  floatx4 ra[PASSES][2], rb[BPASS > 0 ? BPASS : 1][2];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < PASSES; ++q) {
-      const int64_t off = int64_t(q) * 64 * ld + k0;
-      ra[q][0] = *reinterpret_cast<const floatx4 *>(ga_re + off);
-      ra[q][1] = *reinterpret_cast<const floatx4 *>(ga_im + off);
-    }
-#pragma unroll
-    for (int q = 0; q < BPASS; ++q) {
-      const int64_t off = BROW ? (int64_t(k0) + q * (kThreads / (BM / 4))) * ld
-                               : int64_t(q) * 64 * ld + k0;
-      rb[q][0] = *reinterpret_cast<const floatx4 *>(gb_re + off);
-      rb[q][1] = *reinterpret_cast<const floatx4 *>(gb_im + off);
-    }
-  };
-  auto lstore = [&](int st) {
-#pragma unroll
-    for (int q = 0; q < PASSES; ++q) {
-      const int o = (q * 64 + lr) * LDK + lk;
-      *reinterpret_cast<floatx4 *>(&sA[st][0][o]) = ra[q][0];
-      *reinterpret_cast<floatx4 *>(&sA[st][1][o]) = ra[q][1];
-    }
-#pragma unroll
-    for (int q = 0; q < BPASS; ++q) {
-      const int o = BROW ? (br_k + q * (kThreads / (BM / 4))) * LDJ + br_j
-                         : (q * 64 + lr) * LDK + lk;
-      *reinterpret_cast<floatx4 *>(&sB[st][0][o]) = rb[q][0];
-      *reinterpret_cast<floatx4 *>(&sB[st][1][o]) = rb[q][1];
-    }
-  };
-
-  floatx16 cr[F][F], ci[F][F];
-#pragma unroll
-  for (int a = 0; a < F; ++a)
-#pragma unroll
-    for (int b = 0; b < F; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) { cr[a][b][r] = 0.0f; ci[a][b][r] = 0.0f; }
-
-  auto mfma = [](float x, float y, floatx16 acc) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
-  };
-
-  const int nk = int(ld / KT);
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * KT);
-    float ar[F][8], ai[F][8], br[F][8], bi_[F][8];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const int oa = (wm * WM + f * 32 + li) * LDK + h * 8;
-      floatx4 x0 = *reinterpret_cast<const floatx4 *>(&sA[st][0][oa]);
-      floatx4 x1 = *reinterpret_cast<const floatx4 *>(&sA[st][0][oa + 4]);
-      floatx4 y0 = *reinterpret_cast<const floatx4 *>(&sA[st][1][oa]);
-      floatx4 y1 = *reinterpret_cast<const floatx4 *>(&sA[st][1][oa + 4]);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        ar[f][e] = x0[e]; ar[f][e + 4] = x1[e];
-        ai[f][e] = y0[e]; ai[f][e + 4] = y1[e];
-      }
-      if constexpr (BROW) {
-        const int col = wn * WM + f * 32 + li;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          br[f][s] = sB[st][0][(h * 8 + s) * LDJ + col];
-          bi_[f][s] = sB[st][1][(h * 8 + s) * LDJ + col];
-        }
-      } else {
-        const int om = (wn * WM + f * 32 + li) * LDK + h * 8;
-        floatx4 z0 = *reinterpret_cast<const floatx4 *>(&sB[st][0][om]);
-        floatx4 z1 = *reinterpret_cast<const floatx4 *>(&sB[st][0][om + 4]);
-        floatx4 w0 = *reinterpret_cast<const floatx4 *>(&sB[st][1][om]);
-        floatx4 w1 = *reinterpret_cast<const floatx4 *>(&sB[st][1][om + 4]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          br[f][e] = z0[e]; br[f][e + 4] = z1[e];
-          bi_[f][e] = w0[e]; bi_[f][e + 4] = w1[e];
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-      for (int a = 0; a < F; ++a)
-#pragma unroll
-        for (int b = 0; b < F; ++b)
-          cmac<OPS>(cr[a][b], ci[a][b], ar[a][s], ai[a][s], br[b][s], bi_[b][s], mfma);
-    if (kt + 1 < nk) lstore(st ^ 1);
-    __syncthreads();
-  }
-
-  // epilogue: C = alpha * acc + beta * X
-  const bool has_x = p.beta != 0.0f;
-#pragma unroll
-  for (int a = 0; a < F; ++a) {
-#pragma unroll
-    for (int b = 0; b < F; ++b) {
-      const int64_t col = int64_t(bj) * BM + wn * WM + b * 32 + li;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = int64_t(bi) * BM + wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const int64_t o = row * ld + col;
-        float vr = p.alpha * cr[a][b][r], vi = p.alpha * ci[a][b][r];
-        if (has_x) {
-          vr += p.beta * p.x_re[o];
-          vi += p.beta * p.x_im[o];
-        }
-        p.c_re[o] = vr;
-        p.c_im[o] = vi;
-      }
-    }
-  }
+  tile_coords(blockIdx.x, int(p.ld / BM), LOWER, bi, bj);
+  cgemm_f32_tile<BM, OPS>(p, bi, bj, smem);
 }
-
-// ----------------------------------------------------------------- FP64
-// v_mfma_f64_16x16x4_f64: A 16x4 (lane l: row l%16, k-slot l/16), B 4x16
-// (lane l: k-slot l/16, col l%16), D 16x16 in 4 doubles (lane l: col l%16,
-// register r: row l/16 + 4*r).
 
 template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p) {
-  constexpr bool BROW = OPS & kBRow;
-  constexpr int KT = 16;
-  constexpr int LDK = KT + 2;          // padded LDS row (doubles)
-  constexpr int LDJ = BM + 2;
-  constexpr int WM = BM / 2;
-  constexpr int F = WM / 16;           // 16x16 blocks per wave side
-  constexpr int PASSES = BM / 32;      // 32 rows per pass (8 x doublex2 per row)
-  constexpr int BSZ = BROW ? KT * LDJ : BM * LDK;
-  constexpr int BPASS = BROW ? (KT * BM / 2) / kThreads : PASSES;
-  __shared__ double sA[2][2][BM * LDK];
-  __shared__ double sB[2][2][BSZ];
-
-  const int tiles = int(p.ld / BM);
+  __shared__ double smem[cgemm_f64_smem<BM, OPS>()];
   int bi, bj;
-  tile_coords(blockIdx.x, tiles, LOWER, bi, bj);
-  const int64_t ld = p.ld;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int li = lane & 15, h = lane >> 4;
-
-  const int lr = tid >> 3, lk = (tid & 7) * 2;
-  const double *ga_re = p.a_re + (int64_t(bi) * BM + lr) * ld + lk;
-  const double *ga_im = p.a_im + (int64_t(bi) * BM + lr) * ld + lk;
-  const int br_k = tid / (BM / 2), br_j = (tid % (BM / 2)) * 2;
-  const double *gb_re = BROW ? p.m_re + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
-                             : p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
-  const double *gb_im = BROW ? p.m_im + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
-                             : p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
-
-  doublex2 ra[PASSES][2], rb[BPASS > 0 ? BPASS : 1][2];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < PASSES; ++q) {
-      const int64_t off = int64_t(q) * 32 * ld + k0;
-      ra[q][0] = *reinterpret_cast<const doublex2 *>(ga_re + off);
-      ra[q][1] = *reinterpret_cast<const doublex2 *>(ga_im + off);
-    }
-#pragma unroll
-    for (int q = 0; q < BPASS; ++q) {
-      const int64_t off = BROW ? (int64_t(k0) + q * (kThreads / (BM / 2))) * ld
-                               : int64_t(q) * 32 * ld + k0;
-      rb[q][0] = *reinterpret_cast<const doublex2 *>(gb_re + off);
-      rb[q][1] = *reinterpret_cast<const doublex2 *>(gb_im + off);
-    }
-  };
-  auto lstore = [&](int st) {
-#pragma unroll
-    for (int q = 0; q < PASSES; ++q) {
-      const int o = (q * 32 + lr) * LDK + lk;
-      *reinterpret_cast<doublex2 *>(&sA[st][0][o]) = ra[q][0];
-      *reinterpret_cast<doublex2 *>(&sA[st][1][o]) = ra[q][1];
-    }
-#pragma unroll
-    for (int q = 0; q < BPASS; ++q) {
-      const int o = BROW ? (br_k + q * (kThreads / (BM / 2))) * LDJ + br_j
-                         : (q * 32 + lr) * LDK + lk;
-      *reinterpret_cast<doublex2 *>(&sB[st][0][o]) = rb[q][0];
-      *reinterpret_cast<doublex2 *>(&sB[st][1][o]) = rb[q][1];
-    }
-  };
-
-  doublex4 cr[F][F], ci[F][F];
-#pragma unroll
-  for (int a = 0; a < F; ++a)
-#pragma unroll
-    for (int b = 0; b < F; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0.0; ci[a][b][r] = 0.0; }
-
-  auto mfma = [](double x, double y, doublex4 acc) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
-  };
-
-  const int nk = int(ld / KT);
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * KT);
-    double ar[F][4], ai[F][4], br[F][4], bi_[F][4];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const int oa = (wm * WM + f * 16 + li) * LDK + h * 4;
-      doublex2 x0 = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa]);
-      doublex2 x1 = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa + 2]);
-      doublex2 y0 = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa]);
-      doublex2 y1 = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa + 2]);
-      ar[f][0] = x0[0]; ar[f][1] = x0[1]; ar[f][2] = x1[0]; ar[f][3] = x1[1];
-      ai[f][0] = y0[0]; ai[f][1] = y0[1]; ai[f][2] = y1[0]; ai[f][3] = y1[1];
-      if constexpr (BROW) {
-        const int col = wn * WM + f * 16 + li;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          br[f][s] = sB[st][0][(h * 4 + s) * LDJ + col];
-          bi_[f][s] = sB[st][1][(h * 4 + s) * LDJ + col];
-        }
-      } else {
-        const int om = (wn * WM + f * 16 + li) * LDK + h * 4;
-        doublex2 z0 = *reinterpret_cast<const doublex2 *>(&sB[st][0][om]);
-        doublex2 z1 = *reinterpret_cast<const doublex2 *>(&sB[st][0][om + 2]);
-        doublex2 w0 = *reinterpret_cast<const doublex2 *>(&sB[st][1][om]);
-        doublex2 w1 = *reinterpret_cast<const doublex2 *>(&sB[st][1][om + 2]);
-        br[f][0] = z0[0]; br[f][1] = z0[1]; br[f][2] = z1[0]; br[f][3] = z1[1];
-        bi_[f][0] = w0[0]; bi_[f][1] = w0[1]; bi_[f][2] = w1[0]; bi_[f][3] = w1[1];
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int a = 0; a < F; ++a)
-#pragma unroll
-        for (int b = 0; b < F; ++b)
-          cmac<OPS>(cr[a][b], ci[a][b], ar[a][s], ai[a][s], br[b][s], bi_[b][s], mfma);
-    if (kt + 1 < nk) lstore(st ^ 1);
-    __syncthreads();
-  }
-
-  const bool has_x = p.beta != 0.0;
-#pragma unroll
-  for (int a = 0; a < F; ++a) {
-#pragma unroll
-    for (int b = 0; b < F; ++b) {
-      const int64_t col = int64_t(bj) * BM + wn * WM + b * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = int64_t(bi) * BM + wm * WM + a * 16 + h + 4 * r;
-        const int64_t o = row * ld + col;
-        double vr = p.alpha * cr[a][b][r], vi = p.alpha * ci[a][b][r];
-        if (has_x) {
-          vr += p.beta * p.x_re[o];
-          vi += p.beta * p.x_im[o];
-        }
-        p.c_re[o] = vr;
-        p.c_im[o] = vi;
-      }
-    }
-  }
+  tile_coords(blockIdx.x, int(p.ld / BM), LOWER, bi, bj);
+  cgemm_f64_tile<BM, OPS>(p, bi, bj, smem);
 }
 
 // ------------------------------------------------------------- launchers

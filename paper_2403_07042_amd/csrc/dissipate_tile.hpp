@@ -1,0 +1,146 @@
+// Device-side bodies of the decoherence step (shared by the per-step
+// kernels in dissipate.hip and the persistent batched step).
+// Decoherence step, Hermitian symmetrisation and trace renormalisation.
+//
+// Given the rotated state Z = U rho_k U^dag (only tiles on or below the
+// diagonal are valid), one step of the Lindblad term of Sec. II, Eq. 3 with
+// monomial decoherence operators in gather form:
+//   (A_j Z A_j^dag)[u,v] = c_j[u] c_j[v] Z[pi_j[u], pi_j[v]],
+//   (A_j^dag A_j)[u,u]   = a_j[u]^2,  d[u] = sum_j gamma_j a_j[u]^2,
+//   rho_d[u,v] = Z[u,v] (1 - dt (d[u] + d[v]) / 2)
+//              + dt sum_j cg_j[u] cg_j[v] Z[pi_j[u], pi_j[v]]   (cg = sqrt(gamma) c).
+//
+// trace_kernel (one workgroup) needs only the diagonal of Z: it forms
+// tr rho_d and the probability leaving the basis in FP64, updates the sink
+// and the renormalisation factor (1 - sink) / tr rho_d.  dissipate_kernel
+// then writes X = scale * rho_d for u >= v and its conjugate mirror, so X is
+// exactly Hermitian; all arithmetic is FP64 whatever the storage type.
+#pragma once
+
+#include "device.hpp"
+
+namespace qme {
+
+static constexpr int TD = 64;          // tile edge of the decoherence pass
+static constexpr int kDissThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ void zlower(const DissArgs<T> &p, int64_t a, int64_t b, double &re,
+                                       double &im) {
+  // element (a, b) of the Hermitian Z from its lower triangle
+  if (a >= b) {
+    re = double(p.z_re[a * p.ld + b]);
+    im = double(p.z_im[a * p.ld + b]);
+  } else {
+    re = double(p.z_re[b * p.ld + a]);
+    im = -double(p.z_im[b * p.ld + a]);
+  }
+}
+
+// One workgroup of NT threads: FP64 trace of rho_d, lost probability,
+// sink and renormalisation factor of one step (see the file comment).
+template <typename T, int NT>
+__device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, double *s_lost,
+                                           double *s_rot) {
+  double tr = 0.0, lost = 0.0, rot = 0.0;
+  for (int64_t u = threadIdx.x; u < p.n; u += NT) {
+    const double z = double(p.z_re[u * p.ld + u]);
+    double dd = z * (1.0 - p.dt * p.d[u]);
+    for (int j = 0; j < p.n_gather; ++j) {
+      const int32_t pu = p.pi[int64_t(j) * p.n + u];
+      if (pu >= 0) {
+        const double c = p.cg[int64_t(j) * p.n + u];
+        dd += p.dt * c * c * double(p.z_re[int64_t(pu) * p.ld + pu]);
+      }
+    }
+    tr += dd;
+    lost += p.leak[u] * z;
+    rot += z;
+  }
+  s_tr[threadIdx.x] = tr;
+  s_lost[threadIdx.x] = lost;
+  s_rot[threadIdx.x] = rot;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      s_tr[threadIdx.x] += s_tr[threadIdx.x + w];
+      s_lost[threadIdx.x] += s_lost[threadIdx.x + w];
+      s_rot[threadIdx.x] += s_rot[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double sink = p.aux_in[0] + p.dt * s_lost[0];
+    const double steps = p.aux_in[3] + 1.0;
+    p.aux_out[0] = sink;
+    p.aux_out[1] = s_rot[0];
+    p.aux_out[2] = s_lost[0];
+    p.aux_out[3] = steps;
+    p.aux_out[4] = (1.0 - sink) / s_tr[0];
+  }
+}
+
+// One TD x TD lower-triangle tile t of the decoherence pass (256 threads);
+// s_re / s_im: LDS staging of TD x (TD + 1) elements for the mirrored write.
+template <typename T>
+__device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*s_re)[TD + 1],
+                                               T (*s_im)[TD + 1]) {
+  int bi = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  while (bi * (bi + 1) / 2 > t) --bi;
+  const int bj = t - bi * (bi + 1) / 2;
+  const bool diag_tile = bi == bj;
+  const double scale = p.aux_out[4];
+  const double dt = p.dt;
+  const int c = threadIdx.x & (TD - 1);
+  const int r0 = threadIdx.x / TD;
+  const int64_t v = int64_t(bj) * TD + c;
+
+  double dv = 0.0;
+  if (v < p.n) dv = p.d[v];
+  for (int rr = r0; rr < TD; rr += kDissThreads / TD) {
+    const int64_t u = int64_t(bi) * TD + rr;
+    if (u >= p.n || v >= p.n || (diag_tile && v > u)) continue;
+    const int64_t o = u * p.ld + v;
+    const double zr = double(p.z_re[o]), zi = double(p.z_im[o]);
+    const double f = 1.0 - 0.5 * dt * (p.d[u] + dv);
+    double xr = f * zr, xi = f * zi;
+    for (int j = 0; j < p.n_gather; ++j) {
+      const int32_t pu = p.pi[int64_t(j) * p.n + u];
+      const int32_t pv = p.pi[int64_t(j) * p.n + v];
+      if (pu >= 0 && pv >= 0) {
+        const double w = dt * p.cg[int64_t(j) * p.n + u] * p.cg[int64_t(j) * p.n + v];
+        double gr, gi;
+        zlower(p, pu, pv, gr, gi);
+        xr += w * gr;
+        xi += w * gi;
+      }
+    }
+    xr *= scale;
+    xi *= scale;
+    if (u == v) xi = 0.0;
+    p.x_re[o] = T(xr);
+    p.x_im[o] = T(xi);
+    if (diag_tile) {
+      if (u != v) {
+        p.x_re[v * p.ld + u] = T(xr);
+        p.x_im[v * p.ld + u] = T(-xi);
+      }
+    } else {
+      s_re[rr][c] = T(xr);
+      s_im[rr][c] = T(xi);
+    }
+  }
+  if (diag_tile) return;
+  __syncthreads();
+  // mirror tile (bj, bi): element (a, b) = conj(X[bi*TD + b][bj*TD + a])
+  const int64_t ucol = int64_t(bi) * TD + c;
+  for (int a = r0; a < TD; a += kDissThreads / TD) {
+    const int64_t vrow = int64_t(bj) * TD + a;
+    if (vrow >= p.n || ucol >= p.n) continue;
+    p.x_re[vrow * p.ld + ucol] = s_re[c][a];
+    p.x_im[vrow * p.ld + ucol] = -s_im[c][a];
+  }
+}
+
+}  // namespace qme

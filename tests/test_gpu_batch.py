@@ -1,0 +1,144 @@
+"""Batched steps of uneven instances (one launch per phase over every
+instance's tiles, replayed from a captured hipGraph): every instance must
+equal its own qme_step run bitwise (same tile arithmetic), with and without
+the graph and for both instance orders; graph replays interleaved with eager
+work; oracle parity; argument errors."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import evolve as ev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2403_07042_amd")
+from paper_2403_07042_amd import _lib as L  # noqa: E402
+
+
+def mixed_instances():
+    sweep = W.batch_sweep(per_size=2, sizes=(64, 128, 256))
+    extra = W.photon_lattice(6, 5, mu=0.2, g=0.15, gamma=0.05, dt=0.1, start=(0, 2))  # N = 60, padded
+    tch = W.tch_2x2(steps=30)                                                            # N = 144, padded
+    return sweep + [extra, tch]
+
+
+def make_solvers(wls):
+    sols = []
+    for wl in wls:
+        s = P.Solver(wl, "fp32")
+        s.set_rho(W.initial_rho(wl, P.basis(wl)))
+        sols.append(s)
+    return sols
+
+
+def solo_rho(wl, steps):
+    s = P.Solver(wl, "fp32")
+    s.set_rho(W.initial_rho(wl, P.basis(wl)))
+    s.step(steps)
+    rho, sink = s.get_rho()
+    s.close()
+    return rho, sink
+
+
+@pytest.mark.parametrize("graph,largest", [(False, True), (False, False), (True, True)])
+def test_batch_equals_solo_bitwise(graph, largest):
+    wls = mixed_instances()
+    sols = make_solvers(wls)
+    b = P.Batch(sols)
+    b.config(use_graph=graph, largest_first=largest)
+    print(f"batch of {len(wls)} instances, graph={graph} largest_first={largest}", flush=True)
+    b.step(30)
+    torch.cuda.synchronize()
+    for wl, s in zip(wls, sols):
+        rho, sink = s.get_rho()
+        ref, ref_sink = solo_rho(wl, 30)
+        assert np.array_equal(rho, ref), wl["name"]
+        assert sink == ref_sink
+    b.close()
+    for s in sols:
+        s.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    wls = mixed_instances()
+    sols = make_solvers(wls)
+    b = P.Batch(sols)
+    b.config(use_graph=True)
+    other = P.Solver(W.jc_single(), "fp32")
+    other.set_rho(W.initial_rho(W.jc_single(), P.basis(W.jc_single())))
+    for rep in range(3):
+        b.step(10)
+        other.step(5)                       # eager work on the same stream
+        torch.cuda.synchronize()
+        for wl, s in zip(wls, sols):
+            rho, _ = s.get_rho()
+            ref, _ = solo_rho(wl, 10 * (rep + 1))
+            assert np.array_equal(rho, ref), (rep, wl["name"])
+    b.close()
+    other.close()
+    for s in sols:
+        s.close()
+
+
+def test_batch_against_oracle():
+    wls = [W.batch_sweep(per_size=1, sizes=(64,))[0], W.batch_sweep(per_size=1, sizes=(128,))[0]]
+    sols = make_solvers(wls)
+    b = P.Batch(sols)
+    b.step(200)
+    torch.cuda.synchronize()
+    for wl, s in zip(wls, sols):
+        sysm = ev.System(wl)
+        ref, ref_sink = ev.evolve(sysm, W.initial_rho(wl, sysm.occ), 200)
+        rho, sink = s.get_rho()
+        assert np.abs(rho - ref).max() < 1e-5
+        assert abs(sink - ref_sink) < 1e-6
+    b.close()
+    for s in sols:
+        s.close()
+
+
+def test_batch_argument_errors():
+    wl = W.tch_2x2()
+    s64 = P.Solver(wl, "fp64")
+    s64.set_rho(W.initial_rho(wl, P.basis(wl)))
+    with pytest.raises(L.QmeError) as e:
+        P.Batch([s64])
+    assert e.value.status == L.QME_E_UNSUPPORTED
+    s32 = P.Solver(wl, "fp32")
+    b = P.Batch([s32])
+    import ctypes
+    st = L.load().qme_batch_step(b.handle, 1, ctypes.c_void_p(b.workspace.data_ptr()), 16,
+                                 ctypes.c_void_p(0))
+    assert st == L.QME_E_SIZE
+    assert L.load().qme_batch_step(b.handle, -1, ctypes.c_void_p(b.workspace.data_ptr()),
+                                   b.workspace_bytes, ctypes.c_void_p(0)) == L.QME_E_ARG
+    b.close()
+    s32.close()
+    s64.close()
+
+
+def test_full_sweep_256_instances():
+    """The batched sweep workload at full size: 256 instances (64 each of
+    N = 64, 128, 256, 512), 500 steps in one launch; sampled instances equal
+    their solo runs bitwise and the smallest matches the oracle."""
+    wls = W.batch_sweep()
+    sols = make_solvers(wls)
+    b = P.Batch(sols)
+    print("full sweep: 256 instances x 500 steps", flush=True)
+    b.step(500)
+    torch.cuda.synchronize()
+    picks = {}
+    for i, wl in enumerate(wls):
+        picks.setdefault(wl["expected_n"], i)
+    for n, i in sorted(picks.items()):
+        rho, sink = sols[i].get_rho()
+        ref, ref_sink = solo_rho(wls[i], 500)
+        assert np.array_equal(rho, ref), n
+    i64 = picks[64]
+    sysm = ev.System(wls[i64])
+    ref, _ = ev.evolve(sysm, W.initial_rho(wls[i64], sysm.occ), 500)
+    assert np.abs(sols[i64].get_rho()[0] - ref).max() < 1e-5
+    b.close()
+    for s in sols:
+        s.close()
