@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--bf16x3-steps", type=int, default=1000)
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="steps of the timed FP32 adjoint (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=500,
+                    help="steps of the batched sweep of 256 uneven instances (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
     ap.add_argument("--adjoint-all-resident", type=int, default=1,
                     help="also time the adjoint with every state kept in HBM (no recompute)")
@@ -122,6 +124,37 @@ def adjoint_leg(P, W, torch, wl, steps, every):
     return {"ms_per_step": 1e3 * (t1 - t0) / steps, "steps": steps, "checkpoint_every": every,
             "value": f, "dvalue_dmu": float(g[maps["mu"]].sum()),
             "dvalue_dg": float(g[maps["g"]].sum())}
+
+
+def batch_leg(P, W, torch, steps):
+    """256 TCH instances (64 each of N = 64, 128, 256, 512), FP32, one graph
+    replay of `steps` batched steps (one launch per phase over all instances)."""
+    wls = W.batch_sweep(steps=steps)
+    sols = []
+    for wl in wls:
+        s = P.Solver(wl, "fp32")
+        s.set_rho(W.initial_rho(wl, P.basis(wl)))
+        sols.append(s)
+    b = P.Batch(sols)
+    b.config(use_graph=True, largest_first=True)
+    b.step(steps)                    # capture + warm-up run
+    torch.cuda.synchronize()
+    for wl, s in zip(wls, sols):
+        s.set_rho(W.initial_rho(wl, P.basis(wl)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    flops = sum(16.0 * s.n ** 3 for s in sols)
+    b.close()
+    for s in sols:
+        s.close()
+    rate = steps / (t1 - t0)
+    return {"instances": len(wls), "steps": steps, "batched_steps_per_s": rate,
+            "instance_steps_per_s": rate * len(wls), "ms_per_batched_step": 1e3 / rate,
+            "effective_tflops": flops * rate / 1e12,
+            "effective_frac_of_fp32_peak": flops * rate / 1e12 / PEAK_FP32_MFMA}
 
 
 def cpu_baseline(W, wl, gpu_leg, steps):
@@ -189,6 +222,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    batch = batch_leg(P, W, torch, args.batch_steps) if args.batch_steps > 0 else None
+
     adj = None
     if args.adjoint_steps > 0:
         adj = adjoint_leg(P, W, torch, wl, args.adjoint_steps, args.checkpoint_every)
@@ -244,6 +279,7 @@ def main():
         "parity": parity,
         "adjoint_ms_per_step": adj["ms_per_step"] if adj else None,
         "adjoint": adj,
+        "batch_sweep": batch,
     }
     if "bf16x3" in res:
         b = res["bf16x3"]

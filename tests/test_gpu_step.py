@@ -135,3 +135,34 @@ def test_state_roundtrip_and_zero_steps():
     rho, sink = sol.get_rho()
     assert np.array_equal(rho, rho0) and sink == 0.25
     sol.close()
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}.json")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
+def test_tch_chain3_n1728_against_stored_oracle_run(precision):
+    """Full-size TCH chain (3 cavities x 1 atom, cap 5, N = 1728; dephasing and
+    leaks), 2000 steps, against the oracle run stored by
+    tests/golden/make_golden.py: diagonal and a seeded sample of entries at
+    steps 1, 10, 1000 and 2000."""
+    gold = _golden("tch_chain3")
+    wl = W.tch_chain3()
+    assert gold["n"] == 1728
+    pairs = np.array(gold["pairs"])
+    tol = {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 1e-4}[precision]
+    ks = sorted(int(k) for k in gold["records"])
+    got = gpu_run(wl, precision, ks)
+    for k in ks:
+        rec = gold["records"][str(k)]
+        rho, sink, trace = got[k]
+        assert np.abs(np.real(np.diag(rho)) - np.array(rec["diag"])).max() < tol
+        sample = rho[pairs[:, 0], pairs[:, 1]]
+        ref = np.array(rec["sample_re"]) + 1j * np.array(rec["sample_im"])
+        assert np.abs(sample - ref).max() < tol
+        assert abs(sink - rec["sink"]) < TRACE_TOL[precision]
+        assert abs(trace - rec["trace"]) < TRACE_TOL[precision]
