@@ -34,17 +34,19 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": (393453.6 + 32768.0) * 1024,
-                        "sha256": "a7fb55ff7ad60e4082c180b44be803bf8e0d848a96b0235ef0b5ca7d4c703844",
+TRAFFIC_FP32_PRODUCT = {"bytes": 404908.0 * 1024,
+                        "sha256": "8e155ea606e3b847c6125f3922a6219fb892d8f3364cd7edd747c5d3c1c68866",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
+KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 
 
 def measured_traffic():
     import hashlib
-    src = os.path.join(ROOT, "paper_2403_07042_amd", "csrc", "cgemm.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    return TRAFFIC_FP32_PRODUCT["bytes"] if digest == TRAFFIC_FP32_PRODUCT["sha256"] else None
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_07042_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return TRAFFIC_FP32_PRODUCT["bytes"] if h.hexdigest() == TRAFFIC_FP32_PRODUCT["sha256"] else None
 
 
 def parse():

@@ -60,9 +60,10 @@ __device__ __forceinline__ void tri_coords(int t, int &bi, int &bj) {
 
 template <int PHASE>
 __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p) {
-  constexpr int kSmemFloats = PHASE <= 1 ? cgemm_f32_smem<64, kConjB>()
-                              : PHASE == 2 ? 3 * kBatchThreads * 2
-                                           : 2 * TD * (TD + 1);
+  constexpr int kSmemFloats =
+      PHASE <= 1 ? cgemm_f32_smem<64, kConjB>()
+      : PHASE == 2 ? 3 * kBatchThreads * 2
+                   : 2 * TD * (TD + 1) + int(sizeof(GatherLds) / sizeof(float)) + 2;
   __shared__ float smem[kSmemFloats];
   const int64_t r = blockIdx.x;
   int lo = 0, hi = p.count;   // largest position with off[pos] <= r
@@ -91,7 +92,10 @@ __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p
     } else {
       float (*sr)[TD + 1] = reinterpret_cast<float (*)[TD + 1]>(smem);
       float (*si)[TD + 1] = reinterpret_cast<float (*)[TD + 1]>(smem + TD * (TD + 1));
-      dissipate_tile<float>(da, tile, sr, si);
+      // 8-byte aligned start for the tables after the two staging arrays
+      float *gp = smem + 2 * TD * (TD + 1);
+      gp += (reinterpret_cast<uintptr_t>(gp) & 7) ? 1 : 0;
+      dissipate_tile<float>(da, tile, sr, si, reinterpret_cast<GatherLds *>(gp));
     }
   }
 }

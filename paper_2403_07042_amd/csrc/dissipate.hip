@@ -30,7 +30,8 @@ template <typename T>
 __global__ __launch_bounds__(kDissThreads) void dissipate_kernel(DissArgs<T> p) {
   __shared__ T s_re[TD][TD + 1];
   __shared__ T s_im[TD][TD + 1];
-  dissipate_tile<T>(p, blockIdx.x, s_re, s_im);
+  __shared__ GatherLds g;
+  dissipate_tile<T>(p, blockIdx.x, s_re, s_im, &g);
 }
 
 template <typename T>

@@ -80,11 +80,20 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
   }
 }
 
+// Gather tables of up to kGatherChunk channels for one tile's rows (u) and
+// columns (v), staged in LDS once per tile.
+constexpr int kGatherChunk = 8;
+struct GatherLds {
+  int32_t pu[kGatherChunk][TD], pv[kGatherChunk][TD];
+  double cu[kGatherChunk][TD], cv[kGatherChunk][TD];
+};
+
 // One TD x TD lower-triangle tile t of the decoherence pass (256 threads);
-// s_re / s_im: LDS staging of TD x (TD + 1) elements for the mirrored write.
+// s_re / s_im: LDS staging of TD x (TD + 1) elements for the mirrored write;
+// g: LDS for the gather tables (used when 0 < n_gather <= kGatherChunk).
 template <typename T>
 __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*s_re)[TD + 1],
-                                               T (*s_im)[TD + 1]) {
+                                               T (*s_im)[TD + 1], GatherLds *g) {
   int bi = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
   while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
   while (bi * (bi + 1) / 2 > t) --bi;
@@ -95,6 +104,19 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
   const int c = threadIdx.x & (TD - 1);
   const int r0 = threadIdx.x / TD;
   const int64_t v = int64_t(bj) * TD + c;
+  const bool staged = p.n_gather > 0 && p.n_gather <= kGatherChunk;
+  if (staged) {
+    for (int e = threadIdx.x; e < p.n_gather * TD; e += kDissThreads) {
+      const int j = e / TD, i = e - (e / TD) * TD;
+      const int64_t u = int64_t(bi) * TD + i, w = int64_t(bj) * TD + i;
+      const int64_t base = int64_t(j) * p.n;
+      g->pu[j][i] = u < p.n ? p.pi[base + u] : -1;
+      g->cu[j][i] = u < p.n ? p.cg[base + u] : 0.0;
+      g->pv[j][i] = w < p.n ? p.pi[base + w] : -1;
+      g->cv[j][i] = w < p.n ? p.cg[base + w] : 0.0;
+    }
+    __syncthreads();
+  }
 
   double dv = 0.0;
   if (v < p.n) dv = p.d[v];
@@ -106,10 +128,21 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
     const double f = 1.0 - 0.5 * dt * (p.d[u] + dv);
     double xr = f * zr, xi = f * zi;
     for (int j = 0; j < p.n_gather; ++j) {
-      const int32_t pu = p.pi[int64_t(j) * p.n + u];
-      const int32_t pv = p.pi[int64_t(j) * p.n + v];
+      int32_t pu, pv;
+      double cu, cv;
+      if (staged) {
+        pu = g->pu[j][rr];
+        pv = g->pv[j][c];
+        cu = g->cu[j][rr];
+        cv = g->cv[j][c];
+      } else {
+        pu = p.pi[int64_t(j) * p.n + u];
+        pv = p.pi[int64_t(j) * p.n + v];
+        cu = p.cg[int64_t(j) * p.n + u];
+        cv = p.cg[int64_t(j) * p.n + v];
+      }
       if (pu >= 0 && pv >= 0) {
-        const double w = dt * p.cg[int64_t(j) * p.n + u] * p.cg[int64_t(j) * p.n + v];
+        const double w = dt * cu * cv;
         double gr, gi;
         zlower(p, pu, pv, gr, gi);
         xr += w * gr;
