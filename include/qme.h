@@ -269,6 +269,17 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
  * leading dimension ld (qme_state_layout), else QME_E_ARG. */
 qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
 
+/* Tail split of the lower-triangle product (on by default).  When that
+ * product's tile count exceeds a multiple of the device's compute-unit count
+ * by a small remainder, the remainder tiles are computed in k-chunks that
+ * fill the otherwise idle units, and a reduce pass sums each tile's chunks in
+ * k order.  The chunk partials live in the output state's planes, which the
+ * step overwrites afterwards, so no memory is added.  Results differ from the
+ * unsplit product only by FP rounding (the k sum is regrouped) and are
+ * deterministic for a given (ld, tile, device).  enable: 0 or 1, else
+ * QME_E_ARG. */
+qme_status qme_set_split(qme_ctx *ctx, int32_t enable);
+
 /* Per-kernel timing of qme_step with HIP events recorded on the caller's
  * stream around every launch (the tracing facility used by the benchmark).
  * enable != 0 starts recording (and clears earlier records); 0 stops it. */

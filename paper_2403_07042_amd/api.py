@@ -184,6 +184,10 @@ class Solver:
     def set_tiles(self, tile1: int, tile2: int):
         L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
 
+    def set_split(self, enable: bool):
+        """Tail split of the lower-triangle product on (default) or off."""
+        L.check(self.lib.qme_set_split(self.ctx, int(bool(enable))))
+
     # ---------------------------------------------------------- profiling
     KINDS = ("product_full", "product_lower", "trace", "dissipate")
 

@@ -1,14 +1,17 @@
 """Autotuner for the solver's launch knobs, with a JSON cache.
 
-Knobs: the tile edges of the two products of a step (qme_set_tiles) for a
-single instance, and graph replay / instance order for a batch.  Every
+Knobs: the tile edges of the two products of a step (qme_set_tiles) and the
+tail split of the lower-triangle product (qme_set_split) for a single
+instance, and graph replay / instance order for a batch.  Every
 candidate is timed on the real step (median of several trials of a few steps,
 on a scratch copy of the state so the caller's state does not advance) and
 the fastest is applied.  Results are cached per (GPU architecture,
 precision, N, ld) in $QME_TUNE_CACHE (default ~/.cache/qme_mi355x/tune.json).
 
-Tile choice never changes results: every tile size accumulates each output
-element over k in the same order, so the products are bitwise identical.
+With the split off, tile choice never changes results: every tile size
+accumulates each output element over k in the same order, so the products are
+bitwise identical.  A tail split regroups the k sum of the split tiles (FP
+rounding only, deterministic for a given configuration).
 """
 from __future__ import annotations
 
@@ -77,27 +80,33 @@ def _time(torch, fn, trials: int) -> float:
 
 def tune_solver(sol, steps: int = 4, trials: int = 3, use_cache: bool = True,
                 path: str | None = None):
-    """Pick and apply the fastest tile pair for this solver; returns it."""
+    """Pick and apply the fastest (tile1, tile2, split) for this solver;
+    returns it."""
     torch = sol.torch
     key = solver_key(_arch(torch), sol.precision, sol.n, sol.ld)
     cache = load_cache(path) if use_cache else {}
-    if key in cache:
-        best = tuple(cache[key]["tiles"])
-        sol.set_tiles(*best)
+    if key in cache and "split" in cache[key]:
+        best = tuple(cache[key]["tiles"]) + (bool(cache[key]["split"]),)
+        sol.set_tiles(*best[:2])
+        sol.set_split(best[2])
         return best
     scratch = sol.state.clone()
     results = {}
     for tiles in candidates(sol.precision, sol.ld):
-        sol.set_tiles(*tiles)
-        sol.step(1, state=scratch)                       # warm-up
-        results[tiles] = _time(torch, lambda: sol.step(steps, state=scratch), trials)
+        for split in (True, False):
+            sol.set_tiles(*tiles)
+            sol.set_split(split)
+            sol.step(1, state=scratch)                   # warm-up
+            results[tiles + (split,)] = _time(torch, lambda: sol.step(steps, state=scratch), trials)
     best = min(results, key=results.get)
-    sol.set_tiles(*best)
+    sol.set_tiles(*best[:2])
+    sol.set_split(best[2])
     del scratch
     if use_cache:
         cache = load_cache(path)
-        cache[key] = {"tiles": list(best),
-                      "seconds_per_step": {f"{a}x{b}": t / steps for (a, b), t in results.items()}}
+        cache[key] = {"tiles": list(best[:2]), "split": best[2],
+                      "seconds_per_step": {f"{a}x{b}{'/split' if sp else ''}": t / steps
+                                           for (a, b, sp), t in results.items()}}
         save_cache(cache, path)
     return best
 

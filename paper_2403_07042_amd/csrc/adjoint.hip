@@ -378,11 +378,18 @@ static AdjLayout adj_layout(const qme_ctx *c, int64_t n_steps, int32_t every) {
   return L;
 }
 
+// part: 2 * ld^2 elements of dead planes for a tail split of a lower product
 template <typename T>
 static hipError_t gemm(const qme_ctx *c, int tile, const GemmOps &o, const T *a_re, const T *a_im,
                        const T *m_re, const T *m_im, const T *x_re, const T *x_im, T *c_re,
-                       T *c_im, hipStream_t s) {
+                       T *c_im, hipStream_t s, T *part = nullptr) {
   CgemmArgs<T> g{a_re, a_im, m_re, m_im, x_re, x_im, c_re, c_im, c->ld, T(1), T(1)};
+  if (o.lower && part && c->tail_split) {
+    const SplitPlan sp = plan_tail_split(int(c->ld / tile), tile, 16, c->ld, c->cus, 2 * plane_elems(c));
+    g.full = sp.full;
+    g.split = sp.split;
+    g.part = part;
+  }
   if constexpr (sizeof(T) == 4) return launch_cgemm_f32(g, tile, o, s);
   else return launch_cgemm_f64(g, tile, o, s);
 }
@@ -488,7 +495,8 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
       ADJ_OK(launch_gamma_reduce(aa.gbuf, L.blocks, c->n_arrival, c->arrival_of, c->ada, q, n,
                                  nj, c->model.dt, ggam, s));
       ADJ_OK(gemm<T>(c, c->tile1, ox, u_re, u_im, mu_re, mu_im, mu_re, mu_im, x_re, x_im, s));
-      ADJ_OK(gemm<T>(c, c->tile2, ol, x_re, x_im, u_re, u_im, x_re, x_im, lam_re, lam_im, s));
+      // mu is dead once X is formed: it holds the split partials
+      ADJ_OK(gemm<T>(c, c->tile2, ol, x_re, x_im, u_re, u_im, x_re, x_im, lam_re, lam_im, s, mu_re));
       const T *r_re = reinterpret_cast<const T *>(R + size_t(i) * sba), *r_im = r_re + pe;
       ADJ_OK(gemm<T>(c, c->tile1, og, r_re, r_im, x_re, x_im, g_re, g_im, g_re, g_im, s));
     }

@@ -26,13 +26,22 @@
 //     output), enumerated triangularly.
 #include "cgemm_tile.hpp"
 
+#include <algorithm>
+
 namespace qme {
 
 template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
   __shared__ float smem[cgemm_f32_smem<BM, OPS>()];
   int bi, bj;
-  tile_coords(blockIdx.x, int(p.ld / BM), LOWER, bi, bj);
+  if (LOWER) {
+    const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
+    tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
+    cgemm_f32_tile<BM, OPS>(p, bi, bj, smem, w.kb, w.ke,
+                            w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
+    return;
+  }
+  tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
   cgemm_f32_tile<BM, OPS>(p, bi, bj, smem);
 }
 
@@ -40,19 +49,114 @@ template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p) {
   __shared__ double smem[cgemm_f64_smem<BM, OPS>()];
   int bi, bj;
-  tile_coords(blockIdx.x, int(p.ld / BM), LOWER, bi, bj);
+  if (LOWER) {
+    const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
+    tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
+    cgemm_f64_tile<BM, OPS>(p, bi, bj, smem, w.kb, w.ke,
+                            w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
+    return;
+  }
+  tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
   cgemm_f64_tile<BM, OPS>(p, bi, bj, smem);
 }
+
+// C = alpha * sum_s part[tile, s] + beta * X over the split tiles: one
+// 64-thread block per (split tile, 64 * V elements).  The chunk loads are
+// issued in groups of 8 ahead of the additions, which run in chunk (k) order.
+template <typename T, int BM>
+__global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int PER_TILE = BM * BM / (64 * V);
+  constexpr int G = 8;
+  typedef T vec __attribute__((ext_vector_type(V)));
+  const int tl = blockIdx.x / PER_TILE;
+  const int e = (blockIdx.x % PER_TILE) * 64 * V + threadIdx.x * V;
+  int bi, bj;
+  tile_coords(p.full + tl, int(p.ld / BM), true, bi, bj);
+  vec sr = vec(T(0)), si = vec(T(0));
+  const T *src = p.part + size_t(tl) * p.split * 2 * BM * BM + e;
+  for (int c0 = 0; c0 < p.split; c0 += G) {
+    vec lr[G], li[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (c0 + g < p.split) {
+        lr[g] = *reinterpret_cast<const vec *>(src + size_t(c0 + g) * 2 * BM * BM);
+        li[g] = *reinterpret_cast<const vec *>(src + size_t(c0 + g) * 2 * BM * BM + BM * BM);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (c0 + g < p.split) {
+        sr += lr[g];
+        si += li[g];
+      }
+    }
+  }
+  const int64_t o = (int64_t(bi) * BM + e / BM) * p.ld + int64_t(bj) * BM + e % BM;
+  const bool has_x = p.beta != T(0);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    T vr = p.alpha * sr[v], vi = p.alpha * si[v];
+    if (has_x) {
+      vr += p.beta * p.x_re[o + v];
+      vi += p.beta * p.x_im[o + v];
+    }
+    p.c_re[o + v] = vr;
+    p.c_im[o + v] = vi;
+  }
+}
+
+SplitPlan plan_tail_split(int tiles, int bm, int kt, int64_t ld, int cus, size_t cap_elems) {
+  SplitPlan sp;
+  const int all = tiles * (tiles + 1) / 2;
+  if (cus <= 0 || all <= cus) return sp;
+  const int tail = all % cus;
+  if (tail == 0) return sp;
+  int s = std::min<int>(cus / tail, int(ld / kt));
+  while (s >= 2 && size_t(tail) * s * 2 * bm * bm > cap_elems) --s;
+  if (s < 2) return sp;
+  sp.full = all - tail;
+  sp.split = s;
+  return sp;
+}
+
+template <typename T>
+hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, hipStream_t s) {
+  if (a.split < 2) return hipSuccess;
+  const int tiles = int(a.ld / tile);
+  const int tail = tiles * (tiles + 1) / 2 - a.full;
+  const int per_tile = tile * tile / (64 * int(16 / sizeof(T)));
+  if (tail <= 0 || per_tile <= 0) return hipErrorInvalidValue;
+  const dim3 grid(unsigned(tail * per_tile)), block(64);
+  if (tile == 128)
+    hipLaunchKernelGGL((split_reduce_kernel<T, 128>), grid, block, 0, s, a);
+  else if (tile == 64)
+    hipLaunchKernelGGL((split_reduce_kernel<T, 64>), grid, block, 0, s, a);
+  else if (tile == 32)
+    hipLaunchKernelGGL((split_reduce_kernel<T, 32>), grid, block, 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+template hipError_t launch_split_reduce<float>(const CgemmArgs<float> &, int, hipStream_t);
+template hipError_t launch_split_reduce<double>(const CgemmArgs<double> &, int, hipStream_t);
 
 // ------------------------------------------------------------- launchers
 
 template <typename Args, typename K>
 static hipError_t launch(K kernel, const Args &a, int tile, bool lower, hipStream_t s) {
   const int tiles = int(a.ld / tile);
-  const int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
+  int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
   if (blocks == 0) return hipSuccess;
+  const bool split = lower && a.split > 1;
+  if (split) {
+    if (!a.part || a.full < 0 || a.full >= blocks) return hipErrorInvalidValue;
+    blocks = a.full + (blocks - a.full) * a.split;
+  }
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && split) e = launch_split_reduce(a, tile, s);
+  return e;
 }
 
 #define QME_KERNEL_TABLE(NAME, ARGS)                                                          \

@@ -65,9 +65,17 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
   __shared__ __bf16 sB[6][BM * LDK];
 
   const int tiles = int(p.ld / BM);
-  int bi, bj;
+  int bi, bj, kb = 0, ke = int(p.ld / KT);
+  float *part = nullptr;
   {
-    const int t = blockIdx.x;
+    int t = blockIdx.x;
+    if (LOWER && p.split > 1 && t >= p.full) {   // k-chunk of a tail tile
+      const int q = t - p.full, s = q % p.split, nk = int(p.ld / KT);
+      t = p.full + q / p.split;
+      kb = s * nk / p.split;
+      ke = (s + 1) * nk / p.split;
+      part = p.part + size_t(q) * 2 * BM * BM;
+    }
     if (LOWER) {
       int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
       while ((r + 1) * (r + 2) / 2 <= t) ++r;
@@ -131,13 +139,12 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
 #pragma unroll
   for (int r = 0; r < 16; ++r) { cr[r] = 0.0f; ci[r] = 0.0f; }
 
-  const int nk = int(ld / KT);
-  gload(0);
-  for (int kt = 0; kt < nk; ++kt) {
+  gload(kb * KT);
+  for (int kt = kb; kt < ke; ++kt) {
     __syncthreads();             // previous tile's fragments consumed
     lstore();
     __syncthreads();
-    if (kt + 1 < nk) gload((kt + 1) * KT);
+    if (kt + 1 < ke) gload((kt + 1) * KT);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       bf16x8 ar[3], ai[3], br[3], bim[3];
@@ -166,6 +173,15 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
     }
   }
 
+  if (part) {   // raw accumulator of the chunk, tile-local row-major
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = (wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) * BM + wn * 32 + li;
+      part[o] = cr[r];
+      part[BM * BM + o] = ci[r];
+    }
+    return;
+  }
   const bool has_x = p.beta != 0.0f;
   const int64_t col = int64_t(bj) * BM + wn * 32 + li;
 #pragma unroll
@@ -185,10 +201,17 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
 template <typename K>
 static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipStream_t s) {
   const int tiles = int(a.ld / 64);
-  const int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
+  int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
   if (blocks == 0) return hipSuccess;
+  const bool split = lower && a.split > 1;
+  if (split) {
+    if (!a.part || a.full < 0 || a.full >= blocks) return hipErrorInvalidValue;
+    blocks = a.full + (blocks - a.full) * a.split;
+  }
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && split) e = launch_split_reduce(a, 64, s);
+  return e;
 }
 
 hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s) {

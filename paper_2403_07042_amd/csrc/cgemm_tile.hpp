@@ -41,6 +41,20 @@ __device__ __forceinline__ void tile_coords(int t, int tiles, bool lower, int &b
   bj = in / rows;
 }
 
+// Work of one block of a product launch.  Blocks [0, full) are whole tiles
+// (tile index = block).  With a tail split (S > 1) the remaining tiles are cut
+// along k: block full + q computes k-chunk q % S (K-tile iterations
+// [s*nk/S, (s+1)*nk/S)) of tile full + q / S and writes its raw accumulator
+// to partial slot q; a reduce pass sums the S slots of a tile in chunk order.
+struct TileWork {
+  int tile, kb, ke, slot;   // slot < 0: whole tile, normal epilogue
+};
+__device__ __forceinline__ TileWork tile_work(int b, int nk, int full, int S) {
+  if (S <= 1 || b < full) return {b, 0, nk, -1};
+  const int q = b - full, s = q % S;
+  return {full + q / S, s * nk / S, (s + 1) * nk / S, q};
+}
+
 // The four real products of one complex multiply-add, signs folded into
 // fragment negations.  a*/b*: fragments; mfma(x, y, acc) accumulates x*y.
 //   Cr += Ar Br - sA sB Ai Bi,   Ci += sB Ar Bi + sA Ai Br
@@ -74,7 +88,8 @@ constexpr int cgemm_f64_smem() {
 }
 
 template <int BM, int OPS>
-__device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi, int bj, float *smem) {
+__device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi, int bj, float *smem,
+                                               int kb = 0, int ke = -1, float *part = nullptr) {
   constexpr bool BROW = OPS & kBRow;
   constexpr int KT = 16;
   constexpr int LDK = KT + 4;          // padded LDS row of A / NT-B (floats)
@@ -147,12 +162,12 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
     return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
   };
 
-  const int nk = int(ld / KT);
-  gload(0);
+  const int nk = ke < 0 ? int(ld / KT) : ke;
+  gload(kb * KT);
   lstore(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
+  for (int kt = kb; kt < nk; ++kt) {
+    const int st = (kt - kb) & 1;
     if (kt + 1 < nk) gload((kt + 1) * KT);
     float ar[F][8], ai[F][8], br[F][8], bi_[F][8];
 #pragma unroll
@@ -198,6 +213,19 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
     __syncthreads();
   }
 
+  if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
+#pragma unroll
+    for (int a = 0; a < F; ++a)
+#pragma unroll
+      for (int b = 0; b < F; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int o = (wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) * BM + wn * WM + b * 32 + li;
+          part[o] = cr[a][b][r];
+          part[BM * BM + o] = ci[a][b][r];
+        }
+    return;
+  }
   // epilogue: C = alpha * acc + beta * X
   const bool has_x = p.beta != 0.0f;
 #pragma unroll
@@ -227,7 +255,8 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
 // register r: row l/16 + 4*r).
 
 template <int BM, int OPS>
-__device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int bi, int bj, double *smem) {
+__device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int bi, int bj, double *smem,
+                                               int kb = 0, int ke = -1, double *part = nullptr) {
   constexpr bool BROW = OPS & kBRow;
   constexpr int KT = 16;
   constexpr int LDK = KT + 2;          // padded LDS row (doubles)
@@ -299,12 +328,12 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
     return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
   };
 
-  const int nk = int(ld / KT);
-  gload(0);
+  const int nk = ke < 0 ? int(ld / KT) : ke;
+  gload(kb * KT);
   lstore(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
+  for (int kt = kb; kt < nk; ++kt) {
+    const int st = (kt - kb) & 1;
     if (kt + 1 < nk) gload((kt + 1) * KT);
     double ar[F][4], ai[F][4], br[F][4], bi_[F][4];
 #pragma unroll
@@ -344,6 +373,19 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
     __syncthreads();
   }
 
+  if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
+#pragma unroll
+    for (int a = 0; a < F; ++a)
+#pragma unroll
+      for (int b = 0; b < F; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (wm * WM + a * 16 + h + 4 * r) * BM + wn * WM + b * 16 + li;
+          part[o] = cr[a][b][r];
+          part[BM * BM + o] = ci[a][b][r];
+        }
+    return;
+  }
   const bool has_x = p.beta != 0.0;
 #pragma unroll
   for (int a = 0; a < F; ++a) {

@@ -98,6 +98,14 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   GemmOps o1, o2;
   o1.conj_b = o2.conj_b = true;
   o2.lower = true;
+  if (c->tail_split) {
+    // chunk partials go to the output planes: dead until the decoherence pass
+    const int kt = c->precision == QME_BF16X3 ? 32 : 16;
+    const SplitPlan sp = plan_tail_split(int(c->ld / c->tile2), c->tile2, kt, c->ld, c->cus, 2 * pe);
+    g2.full = sp.full;
+    g2.split = sp.split;
+    g2.part = o_re;
+  }
   hipError_t e = mark(c, s, -1);
   if constexpr (sizeof(T) == 4) {
     if (c->precision == QME_BF16X3) {
@@ -174,6 +182,7 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   c->jt = jump_tables(c->model);
 
   HIP_OK(hipGetDevice(&c->device));
+  HIP_OK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const size_t pe = plane_elems(c.get());
   // propagator planes, padded with zeros, in the storage type
@@ -460,6 +469,14 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
   if (e != hipSuccess) { set_error(std::string("launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
   return QME_OK;
   QME_GUARD_END
+}
+
+extern "C" qme_status qme_set_split(qme_ctx *c, int32_t enable) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->tail_split = enable != 0;
+  return QME_OK;
 }
 
 extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {

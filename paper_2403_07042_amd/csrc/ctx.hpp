@@ -19,7 +19,9 @@ struct qme_ctx {
   int64_t elem = 4;                   // storage bytes per real
   int64_t n = 0, ld = 0;
   int tile1 = 64, tile2 = 64;         // tiles of the two products of a step
+  bool tail_split = true;             // qme_set_split
   int device = 0;
+  int cus = 0;                        // compute units of the device
   // device tables (owned)
   void *du_re = nullptr, *du_im = nullptr;   // dU planes, ld x ld, storage type
   double *d = nullptr, *leak = nullptr, *diag = nullptr;

@@ -16,6 +16,10 @@ struct GemmOps {
   bool conj_a = false, conj_b = false, b_rows = false, lower = false;
 };
 
+// Tail split (lower-triangle launches only): when split > 1, tiles
+// [full, all) are computed in `split` k-chunks each, into partial slots of
+// 2 * tile^2 elements at `part` (re then im, tile-local row-major), and a
+// reduce pass writes C = alpha * (sum of the chunks in order) + beta * X.
 template <typename T>
 struct CgemmArgs {
   const T *a_re, *a_im;
@@ -24,7 +28,19 @@ struct CgemmArgs {
   T *c_re, *c_im;
   int64_t ld;
   T alpha, beta;
+  int32_t full = 0, split = 0;
+  T *part = nullptr;
 };
+
+// Plan of a tail split for a lower-triangle product of `tiles` tile rows
+// (tile edge bm) on a device with `cus` compute units, with room for
+// `cap_elems` partial elements.  split = 0: no split.
+struct SplitPlan {
+  int32_t full = 0, split = 0;
+};
+SplitPlan plan_tail_split(int tiles, int bm, int kt, int64_t ld, int cus, size_t cap_elems);
+template <typename T>
+hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, hipStream_t s);
 
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o,
                             hipStream_t s);

@@ -1,6 +1,6 @@
-"""The autotuner on the device: it picks a valid tile pair, caches it, and
-every tile pair gives bitwise-identical steps (tile size does not change the
-accumulation order)."""
+"""The autotuner on the device: it picks a valid tile pair and split setting,
+caches them, and every tile pair gives bitwise-identical steps when no tail
+split applies (tile size does not change the accumulation order)."""
 import numpy as np
 import pytest
 
@@ -30,11 +30,13 @@ def test_tile_choice_is_bitwise_neutral_and_tuner_picks_valid(precision, tmp_pat
     path = str(tmp_path / "tune.json")
     sol.set_rho(rho0)
     best = A.tune_solver(sol, steps=2, trials=2, path=path)
-    assert best in A.candidates(precision, sol.ld)
+    assert best[:2] in A.candidates(precision, sol.ld) and best[2] in (True, False)
     rho, _ = sol.get_rho()
     assert np.array_equal(rho, rho0)      # tuning ran on a scratch state
     key = A.solver_key(A._arch(torch), precision, sol.n, sol.ld)
-    assert tuple(A.load_cache(path)[key]["tiles"]) == best
+    entry = A.load_cache(path)[key]
+    assert tuple(entry["tiles"]) == best[:2] and entry["split"] == best[2]
+    assert A.tune_solver(sol, path=path) == best          # served from the cache
     sol.close()
 
 

@@ -126,6 +126,30 @@ def test_lattice_2048_fp64_against_oracle_steps():
     compare(wl, "fp64", [1, 3])
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-5)])
+def test_tail_split_of_the_lower_product(precision, tol):
+    """N = 2048: the lower-triangle product has 528 tiles of 64 (2080 of 32
+    in FP64), 16 (32) more than a multiple of the 256 compute units, so its
+    tail tiles run in k-chunks summed by a reduce pass.  From a dense pure
+    state, split and unsplit steps differ only by the regrouped k sums."""
+    wl = dict(W.photon_lattice(), init={"kind": "haar", "seed": 7})
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, precision)
+    outs = {}
+    for split in (False, True):
+        sol.set_split(split)
+        sol.set_rho(rho0)
+        print(f"tail split {precision} split={split}", flush=True)
+        sol.step(3)
+        outs[split] = sol.get_rho()
+    sol.close()
+    (a, sa), (b, sb) = outs[False], outs[True]
+    assert not np.array_equal(a, b)          # the split really ran
+    assert np.abs(a - b).max() < tol * np.abs(a).max()
+    assert abs(sa - sb) < 1e-12
+
+
 def test_state_roundtrip_and_zero_steps():
     wl = W.tch_2x2()
     sol = P.Solver(wl, "fp64")
