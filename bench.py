@@ -63,6 +63,8 @@ def parse():
                     help="steps of the timed FP32 adjoint (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the batched sweep of 256 uneven instances (0: skip)")
+    ap.add_argument("--latency", type=int, default=1,
+                    help="time the latency-bound N = 8 and N = 144 workloads (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
     ap.add_argument("--adjoint-all-resident", type=int, default=1,
                     help="also time the adjoint with every state kept in HBM (no recompute)")
@@ -174,6 +176,51 @@ def batch_leg(P, W, torch, steps):
             "dense_equivalent_frac_of_fp32_peak": flops * rate / 1e12 / PEAK_FP32_MFMA}
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def latency_leg(P, W, torch, warmup=20):
+    """The launch-latency-bound workloads: the Jaynes-Cummings model (N = 8,
+    FP64, 10000 steps) on the single-workgroup path and on the four-launch
+    step; the 2 x 2 Tavis-Cummings-Hubbard model (N = 144, FP32, 5000 steps)
+    stepped eagerly and as a one-instance batch replayed from a hipGraph."""
+    out = {}
+    wl = W.jc_single()
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    for fused in (True, False):
+        sol = P.Solver(wl, "fp64")
+        sol.set_fused(fused)
+        sol.set_rho(rho0)
+        sol.step(warmup)
+        sol.set_rho(rho0)
+        dt = _timed(torch, lambda: sol.step(wl["steps"]))
+        sol.close()
+        out["jc_n8_fp64_" + ("single_launch" if fused else "four_launch")] = {
+            "steps": wl["steps"], "steps_per_s": wl["steps"] / dt}
+    wl = W.tch_2x2()
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(rho0)
+    sol.step(warmup)
+    sol.set_rho(rho0)
+    dt = _timed(torch, lambda: sol.step(wl["steps"]))
+    out["tch_n144_fp32_eager"] = {"steps": wl["steps"], "steps_per_s": wl["steps"] / dt}
+    b = P.Batch([sol])
+    b.config(use_graph=True, largest_first=True)
+    b.step(wl["steps"])                      # capture + warm-up run
+    sol.set_rho(rho0)
+    dt = _timed(torch, lambda: b.step(wl["steps"]))
+    out["tch_n144_fp32_graph"] = {"steps": wl["steps"], "steps_per_s": wl["steps"] / dt}
+    b.close()
+    sol.close()
+    return out
+
+
 def cpu_baseline(W, wl, gpu_leg, steps):
     """The CPU oracle (NumPy complex128) timed on the host cores on a bounded
     sample of the same workload, plus the parity of the GPU run's final
@@ -240,6 +287,7 @@ def main():
         del src, dst
 
     batch = batch_leg(P, W, torch, args.batch_steps) if args.batch_steps > 0 else None
+    latency = latency_leg(P, W, torch) if args.latency else None
 
     adj = None
     if args.adjoint_steps > 0:
@@ -300,6 +348,7 @@ def main():
         "adjoint_ms_per_step": adj["ms_per_step"] if adj else None,
         "adjoint": adj,
         "batch_sweep": batch,
+        "latency_bound": latency,
     }
     if "bf16x3" in res:
         b = res["bf16x3"]

@@ -280,6 +280,15 @@ qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
  * QME_E_ARG. */
 qme_status qme_set_split(qme_ctx *ctx, int32_t enable);
 
+/* Single-workgroup path (on by default): for FP32 and FP64 contexts with
+ * N <= 32, qme_step runs all its steps in one launch of one workgroup per
+ * 4096 steps, the state and dU held in LDS.  The arithmetic is the same step;
+ * the products accumulate with scalar FMAs in k order instead of MFMA, so
+ * results differ from the tiled path by rounding only.  With profiling on,
+ * such a launch is counted under index 0 of qme_profile_read.  enable: 0 or
+ * 1, else QME_E_ARG. */
+qme_status qme_set_fused(qme_ctx *ctx, int32_t enable);
+
 /* Per-kernel timing of qme_step with HIP events recorded on the caller's
  * stream around every launch (the tracing facility used by the benchmark).
  * enable != 0 starts recording (and clears earlier records); 0 stops it. */

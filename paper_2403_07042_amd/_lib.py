@@ -72,6 +72,7 @@ SIGNATURES = {
     "qme_batch_destroy": (None, [c_void_p]),
     "qme_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
     "qme_set_split": (c_int32, [c_void_p, c_int32]),
+    "qme_set_fused": (c_int32, [c_void_p, c_int32]),
     "qme_profile_enable": (c_int32, [c_void_p, c_int32]),
     "qme_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "qme_destroy": (None, [c_void_p]),

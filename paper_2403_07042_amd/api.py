@@ -188,6 +188,10 @@ class Solver:
         """Tail split of the lower-triangle product on (default) or off."""
         L.check(self.lib.qme_set_split(self.ctx, int(bool(enable))))
 
+    def set_fused(self, enable: bool):
+        """Single-workgroup path for N <= 32 (FP32 / FP64) on (default) or off."""
+        L.check(self.lib.qme_set_fused(self.ctx, int(bool(enable))))
+
     # ---------------------------------------------------------- profiling
     KINDS = ("product_full", "product_lower", "trace", "dissipate")
 

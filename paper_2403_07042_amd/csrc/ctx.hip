@@ -133,10 +133,31 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
 template hipError_t step_once<float>(qme_ctx *, const void *, void *, void *, void *, hipStream_t);
 template hipError_t step_once<double>(qme_ctx *, const void *, void *, void *, void *, hipStream_t);
 
+// The single-workgroup path applies to FP32 / FP64 contexts with n <= kSmallN.
+bool uses_small_path(const qme_ctx *c) {
+  return c->fused && c->n <= kSmallN && c->precision != QME_BF16X3;
+}
+
 template <typename T>
 static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
                             hipStream_t s) {
   const size_t pe = plane_elems(c);
+  if (uses_small_path(c)) {
+    if (n_steps == 0) return QME_OK;
+    T *re = static_cast<T *>(state);
+    SmallArgs<T> a{re, re + pe, reinterpret_cast<double *>(re + 2 * pe),
+                   static_cast<const T *>(c->du_re), static_cast<const T *>(c->du_im),
+                   c->ld, int(c->n), c->model.dt, c->d, c->leak, c->pi, c->cg,
+                   c->jt.n_gather, n_steps};
+    hipError_t e = mark(c, s, -1);
+    if (e == hipSuccess) e = launch_small_steps<T>(a, s);
+    if (e == hipSuccess) e = mark(c, s, 0);
+    if (e != hipSuccess) {
+      set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return QME_E_DEVICE;
+    }
+    return QME_OK;
+  }
   T *y = static_cast<T *>(ws);
   T *z = y + 2 * pe;
   for (int64_t k = 0; k < n_steps; ++k) {
@@ -469,6 +490,14 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
   if (e != hipSuccess) { set_error(std::string("launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
   return QME_OK;
   QME_GUARD_END
+}
+
+extern "C" qme_status qme_set_fused(qme_ctx *c, int32_t enable) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->fused = enable != 0;
+  return QME_OK;
 }
 
 extern "C" qme_status qme_set_split(qme_ctx *c, int32_t enable) {

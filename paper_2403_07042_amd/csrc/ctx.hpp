@@ -20,6 +20,7 @@ struct qme_ctx {
   int64_t n = 0, ld = 0;
   int tile1 = 64, tile2 = 64;         // tiles of the two products of a step
   bool tail_split = true;             // qme_set_split
+  bool fused = true;                  // qme_set_fused (single-workgroup path, n <= 32)
   int device = 0;
   int cus = 0;                        // compute units of the device
   // device tables (owned)
@@ -67,4 +68,5 @@ qme_status check_device(const qme_ctx *c);
 // workspace plane pairs y (product T) and z (rotated state, lower tiles).
 template <typename T>
 hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s);
+bool uses_small_path(const qme_ctx *c);
 }  // namespace qme

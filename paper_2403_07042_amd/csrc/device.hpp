@@ -75,6 +75,27 @@ hipError_t launch_dissipate(const DissArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_diag(const T *x_re, int64_t ld, int64_t n, double *out, hipStream_t s);
 
+// Whole time steps of a system with n <= kSmallN in one single-workgroup
+// launch (state and dU held in LDS; see small.hip).  re / im / aux: the
+// state buffer (planes of ld x ld, FP64 scalars), updated in place.
+constexpr int kSmallN = 32;
+template <typename T>
+struct SmallArgs {
+  T *re, *im;
+  double *aux;
+  const T *u_re, *u_im;
+  int64_t ld;
+  int n;
+  double dt;
+  const double *d, *leak;
+  const int32_t *pi;
+  const double *cg;
+  int n_gather;
+  int64_t steps;
+};
+template <typename T>
+hipError_t launch_small_steps(const SmallArgs<T> &a, hipStream_t s);
+
 // Adjoint of one step's decoherence, fused with the rate-gradient partials.
 //   mu = lam + dt * sum_j gamma_j (A_j^dag lam A_j - 1/2 {A_j^dag A_j, lam})
 // from the lower triangle of the Hermitian lam (written in full), and, with

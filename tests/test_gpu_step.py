@@ -93,6 +93,82 @@ def test_jaynes_cummings_n8(precision):
     assert abs(rho[2, 2].real - p1) < 5e-6 and abs(rho[1, 1].real - p2) < 5e-6
 
 
+def n32_system():
+    """Two cavities (photon caps 3 and 1, one atom each), full tensor product:
+    N = 32, the largest size of the single-workgroup path; every jump kind."""
+    return {
+        "name": "n32", "atoms": [1, 1], "photon_cap": [3, 1], "exc_min": 0, "exc_max": -1,
+        "omega_c": [1.0, 0.95], "omega_a": [1.0, 1.02], "g": [0.12, 0.08],
+        "hops": [(0, 1, 0.05)],
+        "jumps": [(W.PHOTON_LEAK, 0, -1, 0.03), (W.ATOM_DECAY, 1, 0, 0.02),
+                  (W.ATOM_DEPHASE, 0, 0, 0.01)],
+        "dt": 0.05, "steps": 1000, "init": {"kind": "haar", "seed": 13},
+    }
+
+
+def n33_system():
+    """One cavity with photon cap 32, no atoms: N = 33, just past the
+    single-workgroup path."""
+    return {
+        "name": "n33", "atoms": [0], "photon_cap": [32], "exc_min": 0, "exc_max": -1,
+        "omega_c": [1.0], "omega_a": [], "g": [], "hops": [],
+        "jumps": [(W.PHOTON_LEAK, 0, -1, 0.01)],
+        "dt": 0.05, "steps": 100, "init": {"kind": "haar", "seed": 17},
+    }
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_n32_all_jump_kinds_against_oracle(precision):
+    compare(n32_system(), precision, [1, 10, 1000])
+
+
+@pytest.mark.parametrize("make", [W.jc_single, n32_system, lambda: small_open_system((1, 2))])
+@pytest.mark.parametrize("precision,steps,tol", [("fp64", 5000, 1e-12), ("fp32", 1000, 1e-5)])
+def test_single_workgroup_path_matches_tiled(make, precision, steps, tol):
+    """N <= 32: all steps in one single-workgroup launch (per 4096 steps)
+    against the tiled four-launch step; 5000 FP64 steps span two launches."""
+    wl = make()
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, precision)
+    out = {}
+    for fused in (True, False):
+        sol.set_fused(fused)
+        sol.set_rho(rho0, sink=0.125)
+        print(f"{wl['name']} {precision} fused={fused} {steps} steps", flush=True)
+        sol.step(steps)
+        rho, sink = sol.get_rho()
+        pops, trace, _ = sol.observe()
+        out[fused] = (rho, sink, trace)
+    sol.close()
+    (a, sa, ta), (b, sb, tb) = out[True], out[False]
+    assert np.abs(a - b).max() < tol
+    assert abs(sa - sb) < TRACE_TOL[precision] and abs(ta - tb) < TRACE_TOL[precision]
+    assert np.array_equal(a, a.conj().T)          # exactly Hermitian on both paths
+    assert sa >= 0.125                             # the sink is carried (grows where jumps leave the basis)
+
+
+def test_single_workgroup_dispatch_rule():
+    """N <= 32 in FP32 / FP64 takes the single launch (only index 0 of the
+    per-kind launch counts moves); N = 33, BF16X3, and the knob off take the
+    four-launch step."""
+    def launches(wl, precision, fused=True):
+        sol = P.Solver(wl, precision)
+        sol.set_fused(fused)
+        sol.set_rho(W.initial_rho(wl, P.basis(wl)))
+        sol.profile(True)
+        sol.step(3)
+        torch.cuda.synchronize()
+        counts = [c for _, c in sol.profile_read().values()]
+        sol.close()
+        return counts
+    assert launches(n32_system(), "fp64") == [1, 0, 0, 0]
+    assert launches(n32_system(), "fp32") == [1, 0, 0, 0]
+    assert launches(n32_system(), "fp32", fused=False) == [3, 3, 3, 3]
+    assert launches(n32_system(), "bf16x3") == [3, 3, 3, 3]
+    assert launches(n33_system(), "fp64") == [3, 3, 3, 3]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_tch_n144(precision):
     wl = W.tch_2x2()
