@@ -13,10 +13,8 @@
 //
 // Used for both products of a time step, in the same NT forms as the FP32
 // kernel (A rows and M rows stream contiguous k; see cgemm.hip).
-#include "device.hpp"
+#include "cgemm_tile.hpp"
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
@@ -76,23 +74,7 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
       ke = (s + 1) * nk / p.split;
       part = p.part + size_t(q) * 2 * BM * BM;
     }
-    if (LOWER) {
-      int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
-      while ((r + 1) * (r + 2) / 2 <= t) ++r;
-      while (r * (r + 1) / 2 > t) --r;
-      bi = r;
-      bj = t - r * (r + 1) / 2;
-    } else {
-      const int nb = tiles * tiles;
-      int tt = t;
-      if ((nb & 7) == 0) tt = (t & 7) * (nb >> 3) + (t >> 3);
-      const int group = 4, gsz = group * tiles;
-      const int g = tt / gsz, first = g * group;
-      const int rows = min(group, tiles - first);
-      const int in = tt - g * gsz;
-      bi = first + in % rows;
-      bj = in / rows;
-    }
+    tile_coords(t, tiles, LOWER, bi, bj);
   }
   const int64_t ld = p.ld;
   const int tid = threadIdx.x;

@@ -16,19 +16,61 @@ static constexpr int kThreads = 256;   // 4 waves per tile
 
 enum : int { kConjA = 1, kConjB = 2, kBRow = 4 };
 
-// Tile index -> (bi, bj).  Full grid: the launch order is remapped so that the
-// blocks one XCD receives (block b runs on XCD b % 8) form compact groups of
-// tile rows, which share A rows and B tiles in that XCD's L2.
+// Tile index -> (bi, bj).  Block b runs on XCD b % 8, and each XCD has its
+// own L2, so the mapping gives every XCD a compact block of output tiles
+// whose operand row panels it can share:
+//   full grid, tiles % 8 == 0: the 8 XCDs own a 4 x 2 grid of blocks of
+//     (tiles/4) x (tiles/2) tiles; inside a block, groups of up to 8 tile
+//     rows, column by column;
+//   lower triangle, tiles % 8 == 0: a contiguous run of the triangle walked
+//     in 8 x 8-tile super-blocks (row-major over the lower super-blocks,
+//     triangular inside diagonal ones, column by column inside the others);
+//   otherwise: XCD-contiguous runs of 4-row groups (full) or the plain
+//     row-major triangle (lower).
+// The mapping only reorders whole tiles: results do not depend on it.
+__device__ __forceinline__ void tri_rowmajor(int t, int &r, int &c) {
+  r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  c = t - r * (r + 1) / 2;
+}
+
 __device__ __forceinline__ void tile_coords(int t, int tiles, bool lower, int &bi, int &bj) {
   if (lower) {
-    int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
-    while ((r + 1) * (r + 2) / 2 <= t) ++r;
-    while (r * (r + 1) / 2 > t) --r;
-    bi = r;
-    bj = t - r * (r + 1) / 2;
+    const int nb = tiles * (tiles + 1) / 2;
+    if ((tiles & 7) != 0 || (nb & 7) != 0) {
+      tri_rowmajor(t, bi, bj);
+      return;
+    }
+    int tt = (t & 7) * (nb >> 3) + (t >> 3);
+    for (int sr = 0;; ++sr) {               // super-block row sr: sr off-diagonal + 1 diagonal
+      const int row_tiles = sr * 64 + 36;
+      if (tt >= row_tiles) { tt -= row_tiles; continue; }
+      const int sc = tt / 64;
+      if (sc < sr) {
+        const int in = tt - sc * 64;
+        bi = sr * 8 + (in & 7);
+        bj = sc * 8 + (in >> 3);
+      } else {
+        int r, c;
+        tri_rowmajor(tt - sr * 64, r, c);
+        bi = sr * 8 + r;
+        bj = sr * 8 + c;
+      }
+      return;
+    }
+  }
+  const int nb = tiles * tiles;
+  if ((tiles & 7) == 0) {
+    const int x = t & 7, l = t >> 3;
+    const int R = tiles >> 2, C = tiles >> 1;
+    const int G = R < 8 ? R : 8;
+    const int g = l / (G * C), in = l - g * (G * C);
+    const int rows = min(G, R - g * G);
+    bi = (x >> 1) * R + g * G + in % rows;
+    bj = (x & 1) * C + in / rows;
     return;
   }
-  int nb = tiles * tiles;
   int tt = t;
   if ((nb & 7) == 0) tt = (t & 7) * (nb >> 3) + (t >> 3);
   const int group = 4;
