@@ -148,3 +148,42 @@ def test_adjoint_with_scaling_and_squaring_fp64():
     sol.close()
     assert abs(f - f_ref) < 1e-11
     assert rel(g, g_ref) < 1e-9
+
+
+@pytest.mark.parametrize("size", [64, 128, 256, 512])
+def test_batched_sweep_instance_gradients_against_finite_differences(size):
+    """Instances of the batched sweep (one per N): FP32 adjoint of the final
+    total photon number after 500 steps (checkpoint every 32) with respect to
+    every g, mu and gamma term, against central finite differences of FP64
+    forward runs on the device (step 1e-6)."""
+    wl = next(w for w in W.batch_sweep(per_size=1) if w["expected_n"] == size)
+    occ = P.basis(wl)
+    assert occ.shape[0] == size
+    rho0 = W.initial_rho(wl, occ)
+    obs = md.photon_number(wl, occ).astype(float)
+    steps = wl["steps"]
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(rho0)
+    print(f"sweep instance N={size}: fp32 adjoint {steps} steps", flush=True)
+    f, g = sol.adjoint(steps, obs, checkpoint_every=32)
+    sol.close()
+    from paper_2403_07042_amd.autograd import parameters_of, with_parameters
+    theta = parameters_of(wl).numpy()
+
+    def forward(t):
+        s2 = P.Solver(with_parameters(wl, t), "fp64")
+        s2.set_rho(rho0)
+        s2.step(steps)
+        pops, _, _ = s2.observe()
+        s2.close()
+        return float(obs @ pops)
+
+    h = 1e-6
+    fd = []
+    for i in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd.append((forward(tp) - forward(tm)) / (2 * h))
+    assert abs(f - forward(theta)) < 1e-5
+    assert rel(g, fd) < 1e-4, (g, fd)
