@@ -298,8 +298,10 @@ def main():
             adj["all_resident_matches"] = (full["dvalue_dmu"] == adj["dvalue_dmu"]
                                            and full["dvalue_dg"] == adj["dvalue_dg"])
 
-    if not res:
-        print(json.dumps({"metric": METRIC, "value": None, "note": "no timed leg selected"}))
+    if "fp32" not in res and "fp64" not in res:
+        print(json.dumps({"metric": METRIC, "value": None,
+                          "note": "the fp32 or fp64 leg is needed for the headline value",
+                          "bf16x3": {k: v for k, v in res.get("bf16x3", {}).items() if k != "pops"}}))
         return
     main_leg = res.get("fp32") or res.get("fp64")
     prec = "fp32" if "fp32" in res else "fp64"

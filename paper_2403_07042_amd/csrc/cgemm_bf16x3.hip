@@ -54,7 +54,9 @@ __device__ __forceinline__ floatx16 mac3(const bf16x8 *x, const bf16x8 *y, float
 // prefetched into registers during the products.
 // v_mfma_f32_32x32x16_bf16: A 32x16 (lane l: row l%32, k 8*(l/32)..+7),
 // B 16x32 (lane l: k 8*(l/32)..+7, col l%32), D as for the FP32 32x32 MFMA.
-template <bool CONJA, bool CONJB, bool LOWER>
+// PRE: 0 both operands FP32 (split while staged), 1 first operand pre-split
+// (a_split), 2 second operand pre-split (m_split).
+template <bool CONJA, bool CONJB, bool LOWER, int PRE>
 __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float> p) {
   constexpr int BM = 64;
   constexpr int KT = 32;
@@ -88,17 +90,43 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
                          p.a_im + (int64_t(bi) * BM + lr) * ld + lk,
                          p.m_re + (int64_t(bj) * BM + lr) * ld + lk,
                          p.m_im + (int64_t(bj) * BM + lr) * ld + lk};
+  // a pre-split operand: 64 rows x 32 k per plane = 256 chunks of 8 bf16,
+  // one per thread and plane
+  const int pr = tid >> 2, pk = (tid & 3) * 8;
+  const __bf16 *psrc = nullptr;
+  if constexpr (PRE == 1)
+    psrc = static_cast<const __bf16 *>(p.a_split) + (int64_t(bi) * BM + pr) * ld + pk;
+  if constexpr (PRE == 2)
+    psrc = static_cast<const __bf16 *>(p.m_split) + (int64_t(bj) * BM + pr) * ld + pk;
+  const int64_t pstride = ld * ld;
+  auto skip = [](int o) { return (PRE == 1 && o < 2) || (PRE == 2 && o >= 2); };
   floatx4 reg[4][2];
+  bf16x8 preg[PRE ? 6 : 1];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int o = 0; o < 4; ++o)
+    for (int o = 0; o < 4; ++o) {
+      if (skip(o)) continue;
 #pragma unroll
       for (int q = 0; q < 2; ++q)
         reg[o][q] = *reinterpret_cast<const floatx4 *>(src[o] + int64_t(q) * 32 * ld + k0);
+    }
+    if constexpr (PRE != 0) {
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        preg[pl] = *reinterpret_cast<const bf16x8 *>(psrc + pl * pstride + k0);
+    }
   };
   auto lstore = [&]() {
+    if constexpr (PRE != 0) {
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) {
+        __bf16 *base = PRE == 1 ? &sA[pl][0] : &sB[pl][0];
+        *reinterpret_cast<bf16x8 *>(base + pr * LDK + pk) = preg[pl];
+      }
+    }
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
+      if (skip(o)) continue;
       __bf16 *base = (o < 2) ? &sA[(o & 1) * 3][0] : &sB[(o & 1) * 3][0];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -198,18 +226,50 @@ static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipSt
 
 hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s) {
   if (a.ld % 64 != 0 || o.b_rows) return hipErrorInvalidValue;
+  if (a.a_split && a.m_split) return hipErrorInvalidValue;
+  if (a.a_split || a.m_split) {
+    // the two forward products of a step: T = rho + dU rho^H-form (dU
+    // pre-split as A) and rho_u = T + T conj(dU) (dU pre-split as M)
+    if (o.conj_a || !o.conj_b) return hipErrorInvalidValue;
+    if (a.a_split && !o.lower) return launch3(cgemm_bf16x3_kernel<false, true, false, 1>, a, false, s);
+    if (a.m_split && o.lower) return launch3(cgemm_bf16x3_kernel<false, true, true, 2>, a, true, s);
+    return hipErrorInvalidValue;
+  }
   const int code = (o.conj_a ? 4 : 0) | (o.conj_b ? 2 : 0) | (o.lower ? 1 : 0);
   switch (code) {
-    case 0: return launch3(cgemm_bf16x3_kernel<false, false, false>, a, false, s);
-    case 1: return launch3(cgemm_bf16x3_kernel<false, false, true>, a, true, s);
-    case 2: return launch3(cgemm_bf16x3_kernel<false, true, false>, a, false, s);
-    case 3: return launch3(cgemm_bf16x3_kernel<false, true, true>, a, true, s);
-    case 4: return launch3(cgemm_bf16x3_kernel<true, false, false>, a, false, s);
-    case 5: return launch3(cgemm_bf16x3_kernel<true, false, true>, a, true, s);
-    case 6: return launch3(cgemm_bf16x3_kernel<true, true, false>, a, false, s);
-    case 7: return launch3(cgemm_bf16x3_kernel<true, true, true>, a, true, s);
+    case 0: return launch3(cgemm_bf16x3_kernel<false, false, false, 0>, a, false, s);
+    case 1: return launch3(cgemm_bf16x3_kernel<false, false, true, 0>, a, true, s);
+    case 2: return launch3(cgemm_bf16x3_kernel<false, true, false, 0>, a, false, s);
+    case 3: return launch3(cgemm_bf16x3_kernel<false, true, true, 0>, a, true, s);
+    case 4: return launch3(cgemm_bf16x3_kernel<true, false, false, 0>, a, false, s);
+    case 5: return launch3(cgemm_bf16x3_kernel<true, false, true, 0>, a, true, s);
+    case 6: return launch3(cgemm_bf16x3_kernel<true, true, false, 0>, a, false, s);
+    case 7: return launch3(cgemm_bf16x3_kernel<true, true, true, 0>, a, true, s);
   }
   return hipErrorInvalidValue;
+}
+
+__global__ __launch_bounds__(256) void split_bf16x3_kernel(const float *re, const float *im,
+                                                          __bf16 *out, size_t elems) {
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= elems) return;
+  __bf16 h, m, l;
+  split3(re[i], h, m, l);
+  out[i] = h;
+  out[elems + i] = m;
+  out[2 * elems + i] = l;
+  split3(im[i], h, m, l);
+  out[3 * elems + i] = h;
+  out[4 * elems + i] = m;
+  out[5 * elems + i] = l;
+}
+
+hipError_t launch_split_bf16x3(const float *re, const float *im, void *out, size_t elems,
+                               hipStream_t s) {
+  if (elems == 0) return hipSuccess;
+  hipLaunchKernelGGL(split_bf16x3_kernel, dim3(unsigned((elems + 255) / 256)), dim3(256), 0, s,
+                     re, im, static_cast<__bf16 *>(out), elems);
+  return hipGetLastError();
 }
 
 }  // namespace qme

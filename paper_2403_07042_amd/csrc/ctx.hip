@@ -109,6 +109,9 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   hipError_t e = mark(c, s, -1);
   if constexpr (sizeof(T) == 4) {
     if (c->precision == QME_BF16X3) {
+      // dU pre-split for the first product; the lower product splits its
+      // dU tiles while staging them (measured faster there at N = 2048)
+      g1.a_split = c->du_split;
       if (e == hipSuccess) e = launch_cgemm_bf16x3(g1, o1, s);
       if (e == hipSuccess) e = mark(c, s, 0);
       if (e == hipSuccess) e = launch_cgemm_bf16x3(g2, o2, s);
@@ -221,6 +224,12 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
     void **dst = plane ? &c->du_im : &c->du_re;
     HIP_OK(hipMalloc(dst, buf.size()));
     HIP_OK(hipMemcpyAsync(*dst, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  if (c->precision == QME_BF16X3) {
+    HIP_OK(hipMalloc(&c->du_split, 6 * pe * sizeof(uint16_t)));
+    HIP_OK(launch_split_bf16x3(static_cast<const float *>(c->du_re),
+                               static_cast<const float *>(c->du_im), c->du_split, pe, s));
     HIP_OK(hipStreamSynchronize(s));
   }
   const int64_t n = c->n;
@@ -561,7 +570,7 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
 
 qme_ctx::~qme_ctx() {
   for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
-  for (void *p : {du_re, du_im, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
+  for (void *p : {du_re, du_im, du_split, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,
                   (void *)h_ptr, (void *)h_col, (void *)h_val, (void *)t_row, (void *)t_col,
                   (void *)t_val})

@@ -25,6 +25,7 @@ struct qme_ctx {
   int cus = 0;                        // compute units of the device
   // device tables (owned)
   void *du_re = nullptr, *du_im = nullptr;   // dU planes, ld x ld, storage type
+  void *du_split = nullptr;                  // BF16X3: dU as six bf16 planes (split once)
   double *d = nullptr, *leak = nullptr, *diag = nullptr;
   int32_t *pi = nullptr;
   double *cg = nullptr;

@@ -30,6 +30,10 @@ struct CgemmArgs {
   T alpha, beta;
   int32_t full = 0, split = 0;
   T *part = nullptr;
+  // BF16x3 products only: the first operand (a_split) or the second
+  // (m_split) given as six bf16 planes [re hi, re mid, re lo, im hi, im mid,
+  // im lo] of ld x ld, split once instead of per tile
+  const void *a_split = nullptr, *m_split = nullptr;
 };
 
 // Plan of a tail split for a lower-triangle product of `tiles` tile rows
@@ -48,6 +52,10 @@ hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, const GemmOps 
                             hipStream_t s);
 // Split-BF16x3 products on FP32 planes (tile 64, NT forms only).
 hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s);
+// The six bf16 planes of a complex FP32 matrix (elems per plane), with the
+// split the BF16x3 products apply per tile.
+hipError_t launch_split_bf16x3(const float *re, const float *im, void *out, size_t elems,
+                               hipStream_t s);
 
 // Fused decoherence step on the rotated state Z (lower triangle valid):
 //   X = scale * Herm(Z + dt * D(Z)),  D(Z)[u,v] = sum_j cg_j[u] cg_j[v]
