@@ -213,6 +213,40 @@ qme_status qme_adjoint(qme_ctx *ctx, const void *state0_dev, int64_t n_steps,
 qme_status qme_adjoint_workspace_size(const qme_ctx *ctx, int64_t n_steps,
                                       int32_t checkpoint_every, size_t *bytes);
 
+/* ------------------------------------------------ state-space selection */
+
+/* State-space selection, Sec. III.B (the loop of Fig. 2 and Table I): after a
+ * solve, compute each state's probability growth speed, remove the states
+ * whose speed is below eps, renormalise, and continue on the states that
+ * remain.  The growth speed of state s over an interval of length `interval`
+ * is read as |p_now[s] - p_prev[s]| / interval (an absolute rate of change:
+ * states whose probability neither grows nor decays do not take part in the
+ * dynamics).  Writes the indices of the kept states (growth >= eps) into
+ * keep[0..N) in ascending order and their count into *n_keep.  eps = 0 keeps
+ * every state.  Host only; p_prev / p_now: the n populations of a basis
+ * (qme_observe), n >= 1.
+ * Errors: QME_E_ARG for interval <= 0, eps < 0 or non-finite values;
+ * QME_E_STATE (with *n_keep = 0) when every state would be removed. */
+qme_status qme_select_states(int64_t n, const double *p_prev, const double *p_now,
+                             double interval, double eps, int32_t *keep, int64_t *n_keep);
+
+/* A context on the subset keep[0..n_keep) of ctx's basis (strictly
+ * increasing indices, order kept), with ctx's parameters and precision: the
+ * Hamiltonian restricted to the subset (P H P), decoherence operators whose
+ * image leaves the subset counted in the sink as for the excitation window,
+ * and a new propagator (Taylor stage).  Synchronous. */
+qme_status qme_subspace(const qme_ctx *ctx, const int32_t *keep, int64_t n_keep,
+                        void *hip_stream, qme_ctx **out);
+
+/* Moves a state of `from` onto the subset context `to` (made by
+ * qme_subspace from a context with from's basis):
+ *   rho_to = P rho P * (1 - sink) / tr(P rho P),   sink_to = sink_from,
+ * the renormalisation of Sec. III.B.  Scalar 2 of the new state (see
+ * qme_state_layout) holds the probability the removed states had.  The two
+ * buffers must differ.  Asynchronous on hip_stream. */
+qme_status qme_compact_state(const qme_ctx *from, const void *state_from_dev,
+                             const qme_ctx *to, void *state_to_dev, void *hip_stream);
+
 /* ------------------------------------------------------- batched instances */
 
 typedef struct qme_batch qme_batch;

@@ -16,6 +16,9 @@ finite-dimensional quantum electrodynamics applications"):
 * ``gradients``    tangent-linear (forward-mode) derivatives of final
                    observables with respect to g, mu and gamma, and central
                    finite differences
+* ``selection``    the state-space selection loop of Sec. III.B (growth
+                   speed, deletion below epsilon, renormalisation, solving
+                   on the kept states)
 * ``closed_forms`` analytic solutions that pin the above (Rabi oscillation,
                    damped Jaynes-Cummings, photon leakage, dephasing, the
                    open-boundary lattice in its sine-mode eigenbasis)

@@ -36,12 +36,16 @@ from . import model
 
 
 class System:
-    """Everything the oracle needs about one workload, built from its dict."""
+    """Everything the oracle needs about one workload, built from its dict.
+    occ: an explicit occupation table (a subset of the window basis, as the
+    state-space selection produces); default: the whole window basis."""
 
-    def __init__(self, wl):
+    def __init__(self, wl, occ=None):
         self.wl = wl
-        self.occ = model.basis(wl["atoms"], wl["photon_cap"],
-                               wl.get("exc_min", 0), wl.get("exc_max", -1))
+        if occ is None:
+            occ = model.basis(wl["atoms"], wl["photon_cap"],
+                              wl.get("exc_min", 0), wl.get("exc_max", -1))
+        self.occ = np.asarray(occ)
         self.n = self.occ.shape[0]
         self.terms = model.hamiltonian_terms(wl, self.occ)
         h = None

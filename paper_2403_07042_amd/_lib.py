@@ -73,6 +73,10 @@ SIGNATURES = {
     "qme_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
     "qme_set_split": (c_int32, [c_void_p, c_int32]),
     "qme_set_fused": (c_int32, [c_void_p, c_int32]),
+    "qme_select_states": (c_int32, [c_int64, POINTER(c_double), POINTER(c_double), c_double,
+                                    c_double, POINTER(c_int32), POINTER(c_int64)]),
+    "qme_subspace": (c_int32, [c_void_p, POINTER(c_int32), c_int64, c_void_p, POINTER(c_void_p)]),
+    "qme_compact_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qme_profile_enable": (c_int32, [c_void_p, c_int32]),
     "qme_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "qme_destroy": (None, [c_void_p]),

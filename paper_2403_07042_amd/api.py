@@ -88,7 +88,7 @@ class Solver:
     """One context on the current HIP device plus a torch-owned state buffer
     and workspace."""
 
-    def __init__(self, wl: dict, precision: str = "fp32", stream=None):
+    def __init__(self, wl: dict, precision: str = "fp32", stream=None, _ctx=None):
         torch = _torch()
         self.torch = torch
         self.lib = L.load()
@@ -96,9 +96,12 @@ class Solver:
         self._m = Marshal(wl)
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        ctx = c_void_p()
-        L.check(self.lib.qme_hamiltonian(byref(self._m.system), byref(self._m.params),
-                                         L.PRECISIONS[precision], self._sptr(), byref(ctx)))
+        if _ctx is None:
+            ctx = c_void_p()
+            L.check(self.lib.qme_hamiltonian(byref(self._m.system), byref(self._m.params),
+                                             L.PRECISIONS[precision], self._sptr(), byref(ctx)))
+        else:
+            ctx = _ctx
         self.ctx = ctx
         n, ld, eb, sb = c_int64(), c_int64(), c_int64(), c_size_t()
         L.check(self.lib.qme_state_layout(ctx, byref(n), byref(ld), byref(eb), byref(sb)))
@@ -181,6 +184,22 @@ class Solver:
         del buf
         return val.value, grad[:n_par]
 
+    # ------------------------------------------------ state-space selection
+    def subspace(self, keep) -> "Solver":
+        """A solver on the subset `keep` (ascending indices into this basis);
+        its state is zero until compact_into or set_rho fills it."""
+        keep = np.ascontiguousarray(keep, dtype=np.int32)
+        ctx = c_void_p()
+        L.check(self.lib.qme_subspace(self.ctx, keep.ctypes.data_as(POINTER(c_int32)),
+                                      int(keep.size), self._sptr(), byref(ctx)))
+        return Solver(self.wl, self.precision, self.stream, _ctx=ctx)
+
+    def compact_into(self, sub: "Solver", state=None):
+        """Renormalised P rho P of this solver's state into sub's state."""
+        st = self.state if state is None else state
+        L.check(self.lib.qme_compact_state(self.ctx, c_void_p(st.data_ptr()), sub.ctx,
+                                           c_void_p(sub.state.data_ptr()), self._sptr()))
+
     def set_tiles(self, tile1: int, tile2: int):
         L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
 
@@ -247,3 +266,51 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def select_states(p_prev, p_now, interval: float, eps: float) -> np.ndarray:
+    """Indices of the states whose probability growth speed
+    |p_now - p_prev| / interval is at least eps (qme_select_states)."""
+    lib = L.load()
+    p_prev = np.ascontiguousarray(p_prev, dtype=np.float64)
+    p_now = np.ascontiguousarray(p_now, dtype=np.float64)
+    if p_prev.shape != p_now.shape or p_prev.ndim != 1:
+        raise ValueError("p_prev and p_now must be vectors of one length")
+    keep = np.zeros(p_now.size, dtype=np.int32)
+    n_keep = c_int64(0)
+    L.check(lib.qme_select_states(int(p_now.size), _dptr(p_prev), _dptr(p_now), float(interval),
+                                  float(eps), keep.ctypes.data_as(POINTER(c_int32)), byref(n_keep)))
+    return keep[:n_keep.value].copy()
+
+
+def evolve_with_selection(sol: Solver, n_steps: int, eps: float, every: int = 1):
+    """The selection loop of Sec. III.B on a solver whose state is set: solve
+    `every` steps, compare each state's growth speed over them with eps, move
+    the state onto the kept states (renormalised), repeat until n_steps.  The
+    next comparison starts from the renormalised state.  Returns (solver,
+    kept, sizes): the solver on the final basis (the input solver if nothing
+    was removed; solvers made on the way are closed except the last, which
+    the caller owns), the indices of its states in the input basis, and the
+    basis size after each solve."""
+    kept = np.arange(sol.n, dtype=np.int64)
+    sizes = []
+    owned = False
+    p_prev, _, _ = sol.observe()
+    done = 0
+    while done < n_steps:
+        k = min(every, n_steps - done)
+        sol.step(k)
+        done += k
+        p_now, _, _ = sol.observe()
+        keep = select_states(p_prev, p_now, k * float(sol.wl["dt"]), eps)
+        if keep.size < sol.n:
+            sub = sol.subspace(keep)
+            sol.compact_into(sub)
+            p_now, _, _ = sub.observe()          # synchronises the stream
+            if owned:
+                sol.close()
+            sol, owned = sub, True
+            kept = kept[keep]
+        p_prev = p_now
+        sizes.append(sol.n)
+    return sol, kept, sizes

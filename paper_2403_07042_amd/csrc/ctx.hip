@@ -173,27 +173,14 @@ static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   return QME_OK;
 }
 
-}  // namespace qme
-
-extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
-                                      int32_t precision, void *hip_stream, qme_ctx **out) {
-  QME_GUARD_BEGIN
-  set_error("");
-  if (!out) { set_error("out is NULL"); return QME_E_ARG; }
-  *out = nullptr;
-  if (!par) { set_error("params is NULL"); return QME_E_ARG; }
-  if (precision != QME_FP64 && precision != QME_FP32 && precision != QME_BF16X3) {
-    set_error("unknown precision");
-    return QME_E_ARG;
-  }
-  auto c = std::make_unique<qme_ctx>();
+// Everything of a context after its basis is fixed: Hamiltonian, FP64
+// propagator, decoherence tables and the device copies.
+static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream) {
   std::string err;
-  if (!build_model(sys, par, c->model, err)) { set_error(err); return QME_E_ARG; }
-  if (!enumerate_basis(c->model, err)) { set_error(err); return QME_E_SIZE; }
   c->precision = precision;
   c->elem = precision == QME_FP64 ? 8 : 4;
   c->n = c->model.n;
-  pick_tiles(c.get());
+  pick_tiles(c);
   std::vector<int32_t> r, cc;
   std::vector<double> v;
   hamiltonian_coo(c->model, r, cc, v);
@@ -208,7 +195,7 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   HIP_OK(hipGetDevice(&c->device));
   HIP_OK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const size_t pe = plane_elems(c.get());
+  const size_t pe = plane_elems(c);
   // propagator planes, padded with zeros, in the storage type
   std::vector<char> buf(pe * c->elem);
   for (int plane = 0; plane < 2; ++plane) {
@@ -312,7 +299,114 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
       HIP_OK(hipMemcpy(c->t_val, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice));
     }
   }
+  return QME_OK;
+}
+
+}  // namespace qme
+
+extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
+                                      int32_t precision, void *hip_stream, qme_ctx **out) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!out) { set_error("out is NULL"); return QME_E_ARG; }
+  *out = nullptr;
+  if (!par) { set_error("params is NULL"); return QME_E_ARG; }
+  if (precision != QME_FP64 && precision != QME_FP32 && precision != QME_BF16X3) {
+    set_error("unknown precision");
+    return QME_E_ARG;
+  }
+  auto c = std::make_unique<qme_ctx>();
+  std::string err;
+  if (!build_model(sys, par, c->model, err)) { set_error(err); return QME_E_ARG; }
+  if (!enumerate_basis(c->model, err)) { set_error(err); return QME_E_SIZE; }
+  qme_status st = finish_context(c.get(), precision, hip_stream);
+  if (st != QME_OK) return st;
   *out = c.release();
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_select_states(int64_t n, const double *p_prev, const double *p_now,
+                                        double interval, double eps, int32_t *keep,
+                                        int64_t *n_keep) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!p_prev || !p_now || !keep || !n_keep) { set_error("NULL argument"); return QME_E_ARG; }
+  if (n < 1 || n > (int64_t(1) << 31) - 1) { set_error("n must be in [1, 2^31)"); return QME_E_ARG; }
+  if (!(interval > 0.0) || !std::isfinite(interval)) { set_error("interval must be > 0"); return QME_E_ARG; }
+  if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps must be finite and >= 0"); return QME_E_ARG; }
+  int64_t k = 0;
+  for (int64_t s = 0; s < n; ++s) {
+    if (!std::isfinite(p_prev[s]) || !std::isfinite(p_now[s])) {
+      set_error("populations are not finite");
+      return QME_E_ARG;
+    }
+    if (std::fabs(p_now[s] - p_prev[s]) / interval >= eps) keep[k++] = int32_t(s);
+  }
+  *n_keep = k;
+  if (k == 0) { set_error("every state would be removed"); return QME_E_STATE; }
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_subspace(const qme_ctx *parent, const int32_t *keep, int64_t n_keep,
+                                   void *hip_stream, qme_ctx **out) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!out) { set_error("out is NULL"); return QME_E_ARG; }
+  *out = nullptr;
+  if (!parent || !keep) { set_error("NULL argument"); return QME_E_ARG; }
+  qme_status st = check_device(parent);
+  if (st != QME_OK) return st;
+  auto c = std::make_unique<qme_ctx>();
+  c->model = parent->model;
+  std::string err;
+  if (!restrict_basis(c->model, keep, n_keep, err)) { set_error(err); return QME_E_ARG; }
+  st = finish_context(c.get(), parent->precision, hip_stream);
+  if (st != QME_OK) return st;
+  c->tail_split = parent->tail_split;
+  c->fused = parent->fused;
+  c->parent_n = parent->n;
+  c->parent_ld = parent->ld;
+  HIP_OK(hipMalloc(&c->parent_keep, sizeof(int32_t) * size_t(n_keep)));
+  HIP_OK(hipMemcpy(c->parent_keep, keep, sizeof(int32_t) * size_t(n_keep), hipMemcpyHostToDevice));
+  *out = c.release();
+  return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_compact_state(const qme_ctx *from, const void *state_from,
+                                        const qme_ctx *to, void *state_to, void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!from || !to || !state_from || !state_to) { set_error("NULL argument"); return QME_E_ARG; }
+  if (!to->parent_keep || to->parent_n != from->n || to->parent_ld != from->ld ||
+      to->precision != from->precision) {
+    set_error("'to' was not made by qme_subspace from a context with the basis of 'from'");
+    return QME_E_STATE;
+  }
+  if (state_from == state_to) { set_error("the two states must be different buffers"); return QME_E_ARG; }
+  qme_status st = check_device(to);
+  if (st != QME_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const size_t pf = plane_elems(from), pt = plane_elems(to);
+  hipError_t e;
+  if (from->elem == 8) {
+    const double *fr = static_cast<const double *>(state_from);
+    double *tr = static_cast<double *>(state_to);
+    CompactArgs<double> a{fr, fr + pf, reinterpret_cast<const double *>(fr + 2 * pf),
+                          tr, tr + pt, reinterpret_cast<double *>(tr + 2 * pt), to->parent_keep,
+                          from->n, from->ld, to->n, to->ld};
+    e = launch_compact<double>(a, s);
+  } else {
+    const float *fr = static_cast<const float *>(state_from);
+    float *tr = static_cast<float *>(state_to);
+    CompactArgs<float> a{fr, fr + pf, reinterpret_cast<const double *>(fr + 2 * pf),
+                         tr, tr + pt, reinterpret_cast<double *>(tr + 2 * pt), to->parent_keep,
+                         from->n, from->ld, to->n, to->ld};
+    e = launch_compact<float>(a, s);
+  }
+  if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
   return QME_OK;
   QME_GUARD_END
 }
@@ -570,7 +664,7 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
 
 qme_ctx::~qme_ctx() {
   for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
-  for (void *p : {du_re, du_im, du_split, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
+  for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,
                   (void *)h_ptr, (void *)h_col, (void *)h_val, (void *)t_row, (void *)t_col,
                   (void *)t_val})

@@ -46,6 +46,9 @@ struct qme_ctx {
   double *t_val = nullptr;
   std::vector<int64_t> term_offset;   // host: entries of term p are [off[p], off[p+1])
   int squarings = 0;                  // of the propagator build
+  // a context made by qme_subspace: the kept indices into its parent's basis
+  int32_t *parent_keep = nullptr;     // device, [n]
+  int64_t parent_n = 0, parent_ld = 0;
   double h_norm1 = 0.0;               // |H|_1
 
   // per-kernel timing (qme_profile_enable / qme_profile_read)

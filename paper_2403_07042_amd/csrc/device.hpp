@@ -104,6 +104,19 @@ struct SmallArgs {
 template <typename T>
 hipError_t launch_small_steps(const SmallArgs<T> &a, hipStream_t s);
 
+// Gather of a state onto a subset of its basis (state-space selection).
+template <typename T>
+struct CompactArgs {
+  const T *from_re, *from_im;
+  const double *aux_from;
+  T *to_re, *to_im;
+  double *aux_to;
+  const int32_t *keep;     // [n_to] indices into the source basis
+  int64_t n_from, ld_from, n_to, ld_to;
+};
+template <typename T>
+hipError_t launch_compact(const CompactArgs<T> &a, hipStream_t s);
+
 // Adjoint of one step's decoherence, fused with the rate-gradient partials.
 //   mu = lam + dt * sum_j gamma_j (A_j^dag lam A_j - 1/2 {A_j^dag A_j, lam})
 // from the lower triangle of the Hermitian lam (written in full), and, with

@@ -134,7 +134,35 @@ int64_t Model::rank(const int32_t *x) const {
     s += l;
   }
   if (s < exc_lo || s > exc_hi) return -1;
-  return r;
+  return remap.empty() ? r : int64_t(remap[size_t(r)]);
+}
+
+bool restrict_basis(Model &m, const int32_t *keep, int64_t n_keep, std::string &err) {
+  if (n_keep < 1 || n_keep > m.n) { err = "n_keep must be in [1, N]"; return false; }
+  if (!keep) { err = "keep is NULL"; return false; }
+  std::vector<int32_t> pos(size_t(m.n), -1);
+  for (int64_t i = 0; i < n_keep; ++i) {
+    if (keep[i] < 0 || keep[i] >= m.n || (i > 0 && keep[i] <= keep[i - 1])) {
+      err = "keep must be strictly increasing basis indices";
+      return false;
+    }
+    pos[size_t(keep[i])] = int32_t(i);
+  }
+  // window index -> current index -> new index
+  if (m.remap.empty()) {
+    m.remap = pos;
+  } else {
+    for (int32_t &f : m.remap)
+      if (f >= 0) f = pos[size_t(f)];
+  }
+  const int M = m.n_modes;
+  std::vector<int32_t> occ(size_t(n_keep) * M);
+  for (int64_t i = 0; i < n_keep; ++i)
+    std::copy(m.occ.begin() + size_t(keep[i]) * M, m.occ.begin() + size_t(keep[i] + 1) * M,
+              occ.begin() + size_t(i) * M);
+  m.occ.swap(occ);
+  m.n = n_keep;
+  return true;
 }
 
 bool enumerate_basis(Model &m, std::string &err) {

@@ -38,6 +38,10 @@ struct Model {
   // cnt[m * (exc_hi + 1) + s]: completions of modes m.. given prefix sum s
   // that land in the window; rank() sums it over the levels below a tuple's
   std::vector<uint64_t> cnt;
+  // selected subset of the window basis (state-space selection): remap[f]
+  // is the index of window state f in this basis, -1 if it was removed;
+  // empty when the basis is the whole window
+  std::vector<int32_t> remap;
 
   int64_t rank(const int32_t *levels) const;   // index in basis or -1
 };
@@ -85,6 +89,9 @@ struct JumpTables {
 bool build_model(const qme_system *sys, const qme_params *par, Model &m,
                  std::string &err);
 bool enumerate_basis(Model &m, std::string &err);
+// Keep only basis states keep[0..n_keep) (strictly increasing indices into
+// the current basis), in that order.
+bool restrict_basis(Model &m, const int32_t *keep, int64_t n_keep, std::string &err);
 void hamiltonian_coo(const Model &m, std::vector<int32_t> &r,
                      std::vector<int32_t> &c, std::vector<double> &v);
 Csr to_csr(int64_t n, const std::vector<int32_t> &r,

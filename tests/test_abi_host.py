@@ -132,3 +132,36 @@ def test_size_query_two_call_pattern():
     st = lib.qme_basis(ctypes.byref(m.system), ctypes.byref(n),
                        small.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 10)
     assert st == L.QME_E_SIZE and n.value == 144
+
+
+def test_select_states_matches_oracle_decisions():
+    """qme_select_states keeps exactly the states whose growth speed
+    |p_now - p_prev| / interval is >= eps, as the oracle decides it (same
+    FP64 expression), including a speed exactly at eps."""
+    import numpy as np
+    from oracle import selection as sel
+    rng = np.random.default_rng(20240311 + 41)
+    p_prev = rng.random(1000) * 1e-3
+    p_now = p_prev + rng.standard_normal(1000) * 1e-6
+    p_now[7] = p_prev[7]                       # zero speed
+    interval = 0.05
+    speed = sel.growth_speed(p_prev, p_now, interval)
+    for eps in (0.0, 1e-6, float(np.median(speed)), float(speed[123])):
+        keep = P.select_states(p_prev, p_now, interval, eps)
+        assert np.array_equal(keep, np.nonzero(speed >= eps)[0])
+    assert 123 in P.select_states(p_prev, p_now, interval, float(speed[123]))
+    assert P.select_states(p_prev, p_now, interval, 0.0).size == 1000
+
+
+def test_select_states_errors():
+    import numpy as np
+    p = np.array([0.5, 0.5])
+    q = np.array([0.4, 0.6])
+    for args in [(p, q, 0.0, 0.1), (p, q, -1.0, 0.1), (p, q, 0.1, -1e-9),
+                 (p, np.array([0.4, np.nan]), 0.1, 0.1), (p, q, 0.1, float("inf"))]:
+        with pytest.raises(L.QmeError) as e:
+            P.select_states(*args)
+        assert "QME_E_ARG" in str(e.value)
+    with pytest.raises(L.QmeError) as e:
+        P.select_states(p, p, 0.1, 1e-3)         # nothing moves: every state removed
+    assert "QME_E_STATE" in str(e.value)
