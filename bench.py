@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -65,6 +67,10 @@ def parse():
                     help="steps of the batched sweep of 256 uneven instances (0: skip)")
     ap.add_argument("--latency", type=int, default=1,
                     help="time the latency-bound N = 8 and N = 144 workloads (0: skip)")
+    ap.add_argument("--selection", type=int, default=1,
+                    help="time the state-space selection loop on the N = 2048 lattice (0: skip)")
+    ap.add_argument("--plane-steps", type=int, default=100,
+                    help="steps timed on the N = 4131 photon plane (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
     ap.add_argument("--adjoint-all-resident", type=int, default=1,
                     help="also time the adjoint with every state kept in HBM (no recompute)")
@@ -221,6 +227,66 @@ def latency_leg(P, W, torch, warmup=20):
     return out
 
 
+def selection_leg(P, W, torch, steps=1000, eps=1e-20):
+    """State-space selection (Sec. III.B) on the N = 2048 lattice, FP32,
+    compared after every step: the first solve (step, populations, selection,
+    subset context with its propagator, compaction), then the remaining steps
+    on the selected basis with a comparison after each; plus the compaction
+    kernel alone on a half-size gather of the full state (HIP events)."""
+    wl = W.photon_lattice(steps=steps)
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(rho0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, kept, sizes = P.evolve_with_selection(sol, 1, eps, 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out2, kept2, sizes2 = P.evolve_with_selection(out, steps - 1, eps, 1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    final_n = sizes2[-1] if sizes2 else sizes[-1]
+    if out2 is not out:
+        out2.close()
+    if out is not sol:
+        out.close()
+    # compaction kernel: keep every other state of the full 2048 basis
+    sol.set_rho(rho0)
+    sub = sol.subspace(np.arange(0, sol.n, 2))
+    sol.compact_into(sub)                       # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        sol.compact_into(sub)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    moved = 2 * 4 * sub.n * sub.n * 2           # FP32 re+im gathered and written
+    sub.close()
+    sol.close()
+    return {"workload": "jch_lattice_32x32_n2048", "precision": "fp32", "eps": eps,
+            "steps": steps, "compare_every": 1, "basis_after_first_solve": sizes[0],
+            "final_basis": int(final_n),
+            "first_solve_s": t1 - t0, "remaining_steps_per_s": (steps - 1) / (t2 - t1),
+            "compact_2048_to_1024_us": us, "compact_gbs": moved / (us * 1e-6) / 1e9}
+
+
+def plane_leg(P, W, torch, steps=100, warmup=5):
+    """The paper's own 2D photon-motion plane (81 x 51 cavities, one photon,
+    N = 4131, ld = 4160), FP32, symmetric start: steps/s and per-kernel
+    durations (HIP events on the launch stream)."""
+    wl = W.photon_plane(steps=steps)
+    out = timed_leg(P, W, torch, wl, "fp32", steps, warmup)
+    flops = executed_flops(out)
+    return {"workload": "photon_plane_81x51_n4131", "precision": "fp32", "N": out["n"],
+            "ld": out["ld"], "steps": steps, "steps_per_s": out["steps_per_s"],
+            "ms_per_step": out["ms_per_step"], "kernels_us": out["kernels_us"],
+            "executed_tflops": flops * out["steps_per_s"] / 1e12,
+            "executed_frac_of_fp32_peak": flops * out["steps_per_s"] / 1e12 / PEAK_FP32_MFMA}
+
+
 def cpu_baseline(W, wl, gpu_leg, steps):
     """The CPU oracle (NumPy complex128) timed on the host cores on a bounded
     sample of the same workload, plus the parity of the GPU run's final
@@ -288,6 +354,8 @@ def main():
 
     batch = batch_leg(P, W, torch, args.batch_steps) if args.batch_steps > 0 else None
     latency = latency_leg(P, W, torch) if args.latency else None
+    selection = selection_leg(P, W, torch) if args.selection else None
+    plane = plane_leg(P, W, torch, args.plane_steps) if args.plane_steps > 0 else None
 
     adj = None
     if args.adjoint_steps > 0:
@@ -351,6 +419,8 @@ def main():
         "adjoint": adj,
         "batch_sweep": batch,
         "latency_bound": latency,
+        "state_selection": selection,
+        "photon_plane": plane,
     }
     if "bf16x3" in res:
         b = res["bf16x3"]

@@ -150,6 +150,19 @@ def photon_lattice(length=32, height=32, mu=0.01, g=0.01, gamma=0.001,
     }
 
 
+def photon_plane(start=(40, 0), zeta=0.2, omega=1.0, dt=0.25, steps=1000):
+    """The paper's 2D photon motion (Sec. IV.B): an 81 x 51 plane of cavities
+    without atoms, one photon (N = 4131), hopping zeta, closed (no leak),
+    start (40, 0) (symmetric) or (20, 0) (asymmetric).  The paper does not
+    give omega, zeta, dt or the step count; with these, 1000 steps carry the
+    wavefront about 2 zeta t = 100 sites, past the boundaries and back."""
+    wl = photon_lattice(81, 51, mu=zeta, g=0.0, gamma=0.0, dt=dt, steps=steps,
+                        atoms_per_site=0, start=start)
+    wl["omega_c"] = [omega] * (81 * 51)
+    wl["name"] = f"photon_plane_81x51_{start[0]}_{start[1]}"
+    return wl
+
+
 # structures of the batched sweep, keyed by N (all photon caps 3, chain hops)
 BATCH_STRUCTURES = {64: [1, 1], 128: [1, 2], 256: [2, 2], 512: [1, 1, 1]}
 
