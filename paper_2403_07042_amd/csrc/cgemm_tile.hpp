@@ -97,17 +97,36 @@ __device__ __forceinline__ TileWork tile_work(int b, int nk, int full, int S) {
   return {full + q / S, s * nk / S, (s + 1) * nk / S, q};
 }
 
-// The four real products of one complex multiply-add, signs folded into
-// fragment negations.  a*/b*: fragments; mfma(x, y, acc) accumulates x*y.
-//   Cr += Ar Br - sA sB Ai Bi,   Ci += sB Ar Bi + sA Ai Br
-template <int OPS, typename V, typename S, typename F>
-__device__ __forceinline__ void cmac(V &cr, V &ci, S ar, S ai, S br, S bi, F mfma) {
-  constexpr bool ca = OPS & kConjA, cb = OPS & kConjB;
-  cr = mfma(ar, br, cr);
-  ci = mfma(ca ? -ai : ai, br, ci);
-  cr = mfma((ca != cb) ? ai : -ai, bi, cr);
-  ci = mfma(ar, cb ? -bi : bi, ci);
+// One complex multiply-add in three real products (Gauss's 3M form) with
+// the conjugations folded into the operand sums; A' = Ar + i sA Ai,
+// B' = Br + i sB Bi:
+//   P1 += Ar Br,   P2 += Ai Bi,   P3 += (Ar + sA Ai)(Br + sB Bi)
+//   Re A'B' = P1 - sA sB P2,      Im A'B' = P3 - P1 - sA sB P2
+// (combine3 forms the two after the k loop; both are linear in the
+// accumulators, so k-chunk partials can be combined before they are summed).
+// asum / bsum: Ar + sA Ai and Br + sB Bi, formed once per fragment.
+template <typename V, typename S, typename F>
+__device__ __forceinline__ void cmac3(V &p1, V &p2, V &p3, S ar, S ai, S asum, S br, S bi, S bsum,
+                                      F mfma) {
+  p1 = mfma(ar, br, p1);
+  p2 = mfma(ai, bi, p2);
+  p3 = mfma(asum, bsum, p3);
 }
+template <int OPS, typename V>
+__device__ __forceinline__ void combine3(const V &p1, const V &p2, const V &p3, V &cr, V &ci) {
+  constexpr bool flip = bool(OPS & kConjA) != bool(OPS & kConjB);   // sA sB = -1
+  if (flip) {
+    cr = p1 + p2;
+    ci = (p3 - p1) + p2;
+  } else {
+    cr = p1 - p2;
+    ci = (p3 - p1) - p2;
+  }
+}
+template <int OPS, typename S>
+__device__ __forceinline__ S opsum_a(S r, S i) { return (OPS & kConjA) ? r - i : r + i; }
+template <int OPS, typename S>
+__device__ __forceinline__ S opsum_b(S r, S i) { return (OPS & kConjB) ? r - i : r + i; }
 
 // ----------------------------------------------------------------- FP32
 // v_mfma_f32_32x32x2_f32: A 32x2 (lane l: row l%32, k-slot l/32), B 2x32
@@ -192,13 +211,13 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
     }
   };
 
-  floatx16 cr[F][F], ci[F][F];
+  floatx16 p1[F][F], p2[F][F], p3[F][F];
 #pragma unroll
   for (int a = 0; a < F; ++a)
 #pragma unroll
     for (int b = 0; b < F; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) { cr[a][b][r] = 0.0f; ci[a][b][r] = 0.0f; }
+      for (int r = 0; r < 16; ++r) { p1[a][b][r] = 0.0f; p2[a][b][r] = 0.0f; p3[a][b][r] = 0.0f; }
 
   auto mfma = [](float x, float y, floatx16 acc) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
@@ -244,16 +263,30 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
         }
       }
     }
+    float as_[F][8], bs_[F][8];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        as_[f][s] = opsum_a<OPS>(ar[f][s], ai[f][s]);
+        bs_[f][s] = opsum_b<OPS>(br[f][s], bi_[f][s]);
+      }
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int a = 0; a < F; ++a)
 #pragma unroll
         for (int b = 0; b < F; ++b)
-          cmac<OPS>(cr[a][b], ci[a][b], ar[a][s], ai[a][s], br[b][s], bi_[b][s], mfma);
+          cmac3(p1[a][b], p2[a][b], p3[a][b], ar[a][s], ai[a][s], as_[a][s], br[b][s], bi_[b][s],
+                bs_[b][s], mfma);
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
+  floatx16 cr[F][F], ci[F][F];
+#pragma unroll
+  for (int a = 0; a < F; ++a)
+#pragma unroll
+    for (int b = 0; b < F; ++b) combine3<OPS>(p1[a][b], p2[a][b], p3[a][b], cr[a][b], ci[a][b]);
 
   if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
 #pragma unroll
@@ -358,13 +391,13 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
     }
   };
 
-  doublex4 cr[F][F], ci[F][F];
+  doublex4 p1[F][F], p2[F][F], p3[F][F];
 #pragma unroll
   for (int a = 0; a < F; ++a)
 #pragma unroll
     for (int b = 0; b < F; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0.0; ci[a][b][r] = 0.0; }
+      for (int r = 0; r < 4; ++r) { p1[a][b][r] = 0.0; p2[a][b][r] = 0.0; p3[a][b][r] = 0.0; }
 
   auto mfma = [](double x, double y, doublex4 acc) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
@@ -404,16 +437,30 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
         bi_[f][0] = w0[0]; bi_[f][1] = w0[1]; bi_[f][2] = w1[0]; bi_[f][3] = w1[1];
       }
     }
+    double as_[F][4], bs_[F][4];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        as_[f][s] = opsum_a<OPS>(ar[f][s], ai[f][s]);
+        bs_[f][s] = opsum_b<OPS>(br[f][s], bi_[f][s]);
+      }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int a = 0; a < F; ++a)
 #pragma unroll
         for (int b = 0; b < F; ++b)
-          cmac<OPS>(cr[a][b], ci[a][b], ar[a][s], ai[a][s], br[b][s], bi_[b][s], mfma);
+          cmac3(p1[a][b], p2[a][b], p3[a][b], ar[a][s], ai[a][s], as_[a][s], br[b][s], bi_[b][s],
+                bs_[b][s], mfma);
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
+  doublex4 cr[F][F], ci[F][F];
+#pragma unroll
+  for (int a = 0; a < F; ++a)
+#pragma unroll
+    for (int b = 0; b < F; ++b) combine3<OPS>(p1[a][b], p2[a][b], p3[a][b], cr[a][b], ci[a][b]);
 
   if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
 #pragma unroll
