@@ -43,19 +43,35 @@ template <typename T, int NT>
 __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, double *s_lost,
                                            double *s_rot) {
   double tr = 0.0, lost = 0.0, rot = 0.0;
-  for (int64_t u = threadIdx.x; u < p.n; u += NT) {
-    const double z = double(p.z_re[u * p.ld + u]);
-    double dd = z * (1.0 - p.dt * p.d[u]);
-    for (int j = 0; j < p.n_gather; ++j) {
-      const int32_t pu = p.pi[int64_t(j) * p.n + u];
-      if (pu >= 0) {
-        const double c = p.cg[int64_t(j) * p.n + u];
-        dd += p.dt * c * c * double(p.z_re[int64_t(pu) * p.ld + pu]);
-      }
+  // u = threadIdx.x + k NT in increasing k; the loads of G values of k are
+  // issued together, the sums keep that order
+  constexpr int G = 4;
+  for (int64_t u0 = threadIdx.x; u0 < p.n; u0 += int64_t(G) * NT) {
+    double z[G], dk[G], lk[G];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+      const int64_t u = u0 + int64_t(gi) * NT;
+      const bool ok = u < p.n;
+      z[gi] = ok ? double(p.z_re[u * p.ld + u]) : 0.0;
+      dk[gi] = ok ? p.d[u] : 0.0;
+      lk[gi] = ok ? p.leak[u] : 0.0;
     }
-    tr += dd;
-    lost += p.leak[u] * z;
-    rot += z;
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+      const int64_t u = u0 + int64_t(gi) * NT;
+      if (u >= p.n) break;
+      double dd = z[gi] * (1.0 - p.dt * dk[gi]);
+      for (int j = 0; j < p.n_gather; ++j) {
+        const int32_t pu = p.pi[int64_t(j) * p.n + u];
+        if (pu >= 0) {
+          const double c = p.cg[int64_t(j) * p.n + u];
+          dd += p.dt * c * c * double(p.z_re[int64_t(pu) * p.ld + pu]);
+        }
+      }
+      tr += dd;
+      lost += lk[gi] * z[gi];
+      rot += z[gi];
+    }
   }
   s_tr[threadIdx.x] = tr;
   s_lost[threadIdx.x] = lost;
