@@ -36,8 +36,8 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": 404908.0 * 1024,
-                        "sha256": "8e155ea606e3b847c6125f3922a6219fb892d8f3364cd7edd747c5d3c1c68866",
+TRAFFIC_FP32_PRODUCT = {"bytes": 375451.0 * 1024,
+                        "sha256": "ead10661a9a3fa2cedb9b274270f085736ef39d549d567feca903223f0700e56",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
 KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 
