@@ -213,6 +213,35 @@ qme_status qme_adjoint(qme_ctx *ctx, const void *state0_dev, int64_t n_steps,
 qme_status qme_adjoint_workspace_size(const qme_ctx *ctx, int64_t n_steps,
                                       int32_t checkpoint_every, size_t *bytes);
 
+/* ---------------------------------------------------- general models */
+
+/* One decoherence operator in monomial form (each basis state has at most
+ * one image and at most one preimage): A |source[e]> = coef[e] |target[e]>,
+ * target -1 meaning the image leaves the basis (its probability goes to the
+ * sink); rate gamma >= 0. */
+typedef struct {
+  double gamma;
+  int64_t n_moves;
+  const int32_t *source;   /* [n_moves] */
+  const int32_t *target;   /* [n_moves], -1 or a basis index */
+  const double *coef;      /* [n_moves] */
+} qme_general_jump;
+
+/* A context for a model given directly as matrices, for systems beyond the
+ * cavity / atom / hopping structure of qme_system -- for example the
+ * hydrogen-bond model of Sec. IV.A (Eqs. 4-9), whose couplings are
+ * conditional on other modes and include non-RWA terms.  H: real symmetric
+ * n x n as COO triplets (duplicates summed; the summed matrix must equal its
+ * transpose exactly, else QME_E_ARG); jumps: monomial decoherence operators
+ * (QME_E_UNSUPPORTED when an operator is not monomial).  The step, batching,
+ * selection (qme_subspace) and observation work as for qme_hamiltonian;
+ * qme_adjoint returns QME_E_UNSUPPORTED (the gradient parameters are those of
+ * qme_params).  Synchronous. */
+qme_status qme_hamiltonian_general(int64_t n, int64_t h_nnz, const int32_t *h_rows,
+                                   const int32_t *h_cols, const double *h_vals, int32_t n_jumps,
+                                   const qme_general_jump *jumps, double dt, int32_t precision,
+                                   void *hip_stream, qme_ctx **out);
+
 /* ------------------------------------------------ state-space selection */
 
 /* State-space selection, Sec. III.B (the loop of Fig. 2 and Table I): after a

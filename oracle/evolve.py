@@ -57,6 +57,45 @@ class System:
         self.u = propagator(self.h, self.dt)
 
 
+class GeneralSystem:
+    """A model given directly as matrices (a general-form workload: real
+    symmetric H as COO triplets, decoherence operators as monomial moves
+    A|source> = coef |target>, target -1 for an image outside the basis),
+    optionally restricted to the states `keep` (indices into its basis).
+    Restriction follows the same reading as the window basis: P H P and
+    P A P on the kept states, A^dag A taken before the projection, so moves
+    onto removed states leave through the sink."""
+
+    def __init__(self, wl, keep=None):
+        import scipy.sparse as sp
+        self.wl = wl
+        n = int(wl["n"])
+        rows, cols, vals = wl["h"]
+        h = sp.coo_matrix((np.asarray(vals, float), (np.asarray(rows), np.asarray(cols))),
+                          shape=(n, n)).toarray()
+        keep = np.arange(n) if keep is None else np.asarray(keep)
+        pos = -np.ones(n, dtype=np.int64)
+        pos[keep] = np.arange(keep.size)
+        self.keep = keep
+        self.n = keep.size
+        self.h = h[np.ix_(keep, keep)]
+        self.jumps = []
+        for gamma, src, dst, coef in wl["jumps"]:
+            src, dst, coef = np.asarray(src), np.asarray(dst), np.asarray(coef, float)
+            ada_diag = np.zeros(self.n)
+            r, c, v = [], [], []
+            for a, b, x in zip(src, dst, coef):
+                if pos[a] < 0:
+                    continue
+                ada_diag[pos[a]] += x * x
+                if b >= 0 and pos[b] >= 0:
+                    r.append(pos[b]); c.append(pos[a]); v.append(x)
+            a_mat = sp.csr_matrix((v, (r, c)), shape=(self.n, self.n))
+            self.jumps.append((float(gamma), a_mat, sp.diags(ada_diag).tocsr()))
+        self.dt = float(wl["dt"])
+        self.u = propagator(self.h, self.dt)
+
+
 def propagator(h, dt):
     """U = exp(-i H dt) for real symmetric H, via H = V diag(lam) V^T."""
     lam, v = np.linalg.eigh(h)

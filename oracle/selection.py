@@ -38,7 +38,8 @@ def select_evolve(wl, rho0, n_steps, eps, every=1, sink0=0.0):
     steps.  Returns (rho, sink, kept, sizes): the final reduced state, its
     sink, the indices of its states in the window basis and the basis size
     after each solve."""
-    sysm = evolve.System(wl)
+    general = bool(wl.get("general", False))
+    sysm = evolve.GeneralSystem(wl) if general else evolve.System(wl)
     kept = np.arange(sysm.n)
     rho, sink = np.asarray(rho0, dtype=np.complex128), float(sink0)
     sizes = []
@@ -57,6 +58,7 @@ def select_evolve(wl, rho0, n_steps, eps, every=1, sink0=0.0):
             block = rho[np.ix_(sel, sel)]
             rho = block * ((1.0 - sink) / np.trace(block).real)
             kept = kept[sel]
-            sysm = evolve.System(wl, occ=sysm.occ[sel])
+            sysm = (evolve.GeneralSystem(wl, keep=kept) if general
+                    else evolve.System(wl, occ=sysm.occ[sel]))
         sizes.append(sysm.n)
     return rho, sink, kept, sizes

@@ -32,6 +32,11 @@ class Jump(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("cavity", c_int32), ("atom", c_int32), ("gamma", c_double)]
 
 
+class GeneralJump(ctypes.Structure):
+    _fields_ = [("gamma", c_double), ("n_moves", c_int64), ("source", POINTER(c_int32)),
+                ("target", POINTER(c_int32)), ("coef", POINTER(c_double))]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("omega_c", POINTER(c_double)), ("omega_a", POINTER(c_double)),
                 ("g", POINTER(c_double)), ("n_hops", c_int32), ("hops", POINTER(Hop)),
@@ -73,6 +78,9 @@ SIGNATURES = {
     "qme_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
     "qme_set_split": (c_int32, [c_void_p, c_int32]),
     "qme_set_fused": (c_int32, [c_void_p, c_int32]),
+    "qme_hamiltonian_general": (c_int32, [c_int64, c_int64, POINTER(c_int32), POINTER(c_int32),
+                                          POINTER(c_double), c_int32, POINTER(GeneralJump), c_double,
+                                          c_int32, c_void_p, POINTER(c_void_p)]),
     "qme_select_states": (c_int32, [c_int64, POINTER(c_double), POINTER(c_double), c_double,
                                     c_double, POINTER(c_int32), POINTER(c_int64)]),
     "qme_subspace": (c_int32, [c_void_p, POINTER(c_int32), c_int64, c_void_p, POINTER(c_void_p)]),

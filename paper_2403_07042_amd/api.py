@@ -34,6 +34,39 @@ class Marshal:
                                len(jumps), self._jumps, float(wl["dt"]))
 
 
+class MarshalGeneral:
+    """C arrays of a general-form workload: {"general": True, "n": N,
+    "h": (rows, cols, vals), "jumps": [(gamma, source, target, coef), ...],
+    "dt": dt} (keeps the arrays alive)."""
+
+    def __init__(self, wl: dict):
+        rows, cols, vals = wl["h"]
+        self.n = int(wl["n"])
+        self.rows = np.ascontiguousarray(rows, dtype=np.int32)
+        self.cols = np.ascontiguousarray(cols, dtype=np.int32)
+        self.vals = np.ascontiguousarray(vals, dtype=np.float64)
+        self._keep = []
+        js = []
+        for gamma, src, dst, coef in wl["jumps"]:
+            src = np.ascontiguousarray(src, dtype=np.int32)
+            dst = np.ascontiguousarray(dst, dtype=np.int32)
+            coef = np.ascontiguousarray(coef, dtype=np.float64)
+            self._keep += [src, dst, coef]
+            js.append(L.GeneralJump(float(gamma), int(src.size),
+                                    src.ctypes.data_as(POINTER(c_int32)),
+                                    dst.ctypes.data_as(POINTER(c_int32)),
+                                    coef.ctypes.data_as(POINTER(c_double))))
+        self.jumps = (L.GeneralJump * max(len(js), 1))(*js)
+        self.n_jumps = len(js)
+        self.dt = float(wl["dt"])
+
+    def create(self, lib, precision: int, stream, out):
+        return lib.qme_hamiltonian_general(
+            self.n, int(self.vals.size), self.rows.ctypes.data_as(POINTER(c_int32)),
+            self.cols.ctypes.data_as(POINTER(c_int32)), _dptr(self.vals), self.n_jumps,
+            self.jumps, self.dt, precision, stream, out)
+
+
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(POINTER(c_double))
 
@@ -93,13 +126,17 @@ class Solver:
         self.torch = torch
         self.lib = L.load()
         self.wl = wl
-        self._m = Marshal(wl)
+        self.general = bool(wl.get("general", False))
+        self._m = MarshalGeneral(wl) if self.general else Marshal(wl)
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         if _ctx is None:
             ctx = c_void_p()
-            L.check(self.lib.qme_hamiltonian(byref(self._m.system), byref(self._m.params),
-                                             L.PRECISIONS[precision], self._sptr(), byref(ctx)))
+            if self.general:
+                L.check(self._m.create(self.lib, L.PRECISIONS[precision], self._sptr(), byref(ctx)))
+            else:
+                L.check(self.lib.qme_hamiltonian(byref(self._m.system), byref(self._m.params),
+                                                 L.PRECISIONS[precision], self._sptr(), byref(ctx)))
         else:
             ctx = _ctx
         self.ctx = ctx
@@ -175,7 +212,8 @@ class Solver:
         L.check(self.lib.qme_adjoint_workspace_size(self.ctx, int(n_steps), int(checkpoint_every),
                                                     byref(ws)))
         buf = self.torch.empty(max(ws.value, 256), dtype=self.torch.uint8, device=st.device)
-        n_par = int(sum(self.wl["atoms"])) + len(self.wl.get("hops", [])) + len(self.wl.get("jumps", []))
+        n_par = 0 if self.general else (int(sum(self.wl["atoms"])) + len(self.wl.get("hops", []))
+                                         + len(self.wl.get("jumps", [])))
         grad = np.zeros(max(n_par, 1))
         val = c_double()
         L.check(self.lib.qme_adjoint(self.ctx, c_void_p(st.data_ptr()), int(n_steps),

@@ -612,6 +612,10 @@ extern "C" qme_status qme_adjoint(qme_ctx *c, const void *state0, int64_t n_step
   try {
     set_error("");
     if (!c || !state0 || !obs || !grad || !ws) { set_error("NULL argument"); return QME_E_ARG; }
+    if (c->model.general) {
+      set_error("gradients need a context built from qme_system / qme_params");
+      return QME_E_UNSUPPORTED;
+    }
     if (n_steps < 0 || checkpoint_every < 1) { set_error("n_steps < 0 or checkpoint_every < 1"); return QME_E_ARG; }
     if ((reinterpret_cast<uintptr_t>(ws) | reinterpret_cast<uintptr_t>(state0)) & 255) {
       set_error("state and workspace must be 256-byte aligned");

@@ -326,6 +326,34 @@ extern "C" qme_status qme_hamiltonian(const qme_system *sys, const qme_params *p
   QME_GUARD_END
 }
 
+extern "C" qme_status qme_hamiltonian_general(int64_t n, int64_t h_nnz, const int32_t *h_rows,
+                                              const int32_t *h_cols, const double *h_vals,
+                                              int32_t n_jumps, const qme_general_jump *jumps,
+                                              double dt, int32_t precision, void *hip_stream,
+                                              qme_ctx **out) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!out) { set_error("out is NULL"); return QME_E_ARG; }
+  *out = nullptr;
+  if (precision != QME_FP64 && precision != QME_FP32 && precision != QME_BF16X3) {
+    set_error("unknown precision");
+    return QME_E_ARG;
+  }
+  auto c = std::make_unique<qme_ctx>();
+  std::string err;
+  bool unsupported = false;
+  if (!build_general_model(n, h_nnz, h_rows, h_cols, h_vals, n_jumps, jumps, dt, c->model, err,
+                           unsupported)) {
+    set_error(err);
+    return unsupported ? QME_E_UNSUPPORTED : QME_E_ARG;
+  }
+  qme_status st = finish_context(c.get(), precision, hip_stream);
+  if (st != QME_OK) return st;
+  *out = c.release();
+  return QME_OK;
+  QME_GUARD_END
+}
+
 extern "C" qme_status qme_select_states(int64_t n, const double *p_prev, const double *p_now,
                                         double interval, double eps, int32_t *keep,
                                         int64_t *n_keep) {

@@ -16,6 +16,13 @@
 namespace qme {
 
 static constexpr int64_t kMaxStates = int64_t(1) << 20;
+
+namespace {
+struct Trip {
+  int32_t r, c;
+  double v;
+};
+}  // namespace
 static constexpr int kMaxLevel = 64;
 
 static bool finite(double x) { return std::isfinite(x); }
@@ -137,6 +144,80 @@ int64_t Model::rank(const int32_t *x) const {
   return remap.empty() ? r : int64_t(remap[size_t(r)]);
 }
 
+bool build_general_model(int64_t n, int64_t h_nnz, const int32_t *h_rows, const int32_t *h_cols,
+                         const double *h_vals, int32_t n_jumps, const qme_general_jump *jumps,
+                         double dt, Model &m, std::string &err, bool &unsupported) {
+  unsupported = false;
+  if (n < 1 || n > kMaxStates) { err = "n must be in [1, 2^20]"; return false; }
+  if (h_nnz < 0 || (h_nnz > 0 && (!h_rows || !h_cols || !h_vals))) { err = "H arrays are NULL"; return false; }
+  if (n_jumps < 0 || (n_jumps > 0 && !jumps)) { err = "jumps is NULL"; return false; }
+  if (!(dt > 0.0) || !std::isfinite(dt)) { err = "dt must be finite and > 0"; return false; }
+  m = Model();
+  m.general = true;
+  m.n = n;
+  m.dt = dt;
+  m.has_params = true;
+  std::vector<Trip> t;
+  t.reserve(size_t(h_nnz));
+  for (int64_t e = 0; e < h_nnz; ++e) {
+    if (h_rows[e] < 0 || h_rows[e] >= n || h_cols[e] < 0 || h_cols[e] >= n) {
+      err = "H index out of range"; return false;
+    }
+    if (!std::isfinite(h_vals[e])) { err = "H value is not finite"; return false; }
+    t.push_back({h_rows[e], h_cols[e], h_vals[e]});
+  }
+  std::sort(t.begin(), t.end(), [](const Trip &a, const Trip &b) {
+    return a.r != b.r ? a.r < b.r : a.c < b.c;
+  });
+  for (const Trip &x : t) {
+    if (!m.h_row.empty() && m.h_row.back() == x.r && m.h_col.back() == x.c) {
+      m.h_val.back() += x.v;
+    } else {
+      m.h_row.push_back(x.r); m.h_col.push_back(x.c); m.h_val.push_back(x.v);
+    }
+  }
+  // symmetric: the transpose, sorted the same way, must match entry for entry
+  {
+    std::vector<size_t> idx(m.h_val.size());
+    for (size_t e = 0; e < idx.size(); ++e) idx[e] = e;
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+      return m.h_col[a] != m.h_col[b] ? m.h_col[a] < m.h_col[b] : m.h_row[a] < m.h_row[b];
+    });
+    for (size_t e = 0; e < idx.size(); ++e) {
+      const size_t q = idx[e];
+      if (m.h_col[q] != m.h_row[e] || m.h_row[q] != m.h_col[e] || m.h_val[q] != m.h_val[e]) {
+        err = "H must be symmetric (real Hermitian)";
+        return false;
+      }
+    }
+  }
+  m.moves.resize(size_t(n_jumps));
+  std::vector<int32_t> seen_src(size_t(n), -1), seen_dst(size_t(n), -1);
+  for (int32_t j = 0; j < n_jumps; ++j) {
+    const qme_general_jump &jp = jumps[j];
+    if (!(jp.gamma >= 0.0) || !std::isfinite(jp.gamma)) { err = "gamma must be finite and >= 0"; return false; }
+    if (jp.n_moves < 0 || (jp.n_moves > 0 && (!jp.source || !jp.target || !jp.coef))) {
+      err = "jump arrays are NULL"; return false;
+    }
+    qme_jump q{-1, 0, 0, jp.gamma};
+    m.jumps.push_back(q);
+    for (int64_t e = 0; e < jp.n_moves; ++e) {
+      const int32_t a = jp.source[e], b = jp.target[e];
+      if (a < 0 || a >= n || b < -1 || b >= n) { err = "jump index out of range"; return false; }
+      if (!std::isfinite(jp.coef[e])) { err = "jump coefficient is not finite"; return false; }
+      if (seen_src[size_t(a)] == j || (b >= 0 && seen_dst[size_t(b)] == j)) {
+        err = "decoherence operator is not monomial (a state has two images or two preimages)";
+        unsupported = true;
+        return false;
+      }
+      seen_src[size_t(a)] = j;
+      if (b >= 0) seen_dst[size_t(b)] = j;
+      if (jp.coef[e] != 0.0) m.moves[size_t(j)].push_back({a, b, jp.coef[e]});
+    }
+  }
+  return true;
+}
+
 bool restrict_basis(Model &m, const int32_t *keep, int64_t n_keep, std::string &err) {
   if (n_keep < 1 || n_keep > m.n) { err = "n_keep must be in [1, N]"; return false; }
   if (!keep) { err = "keep is NULL"; return false; }
@@ -147,6 +228,26 @@ bool restrict_basis(Model &m, const int32_t *keep, int64_t n_keep, std::string &
       return false;
     }
     pos[size_t(keep[i])] = int32_t(i);
+  }
+  if (m.general) {
+    std::vector<int32_t> r, c;
+    std::vector<double> v;
+    for (size_t e = 0; e < m.h_val.size(); ++e) {
+      const int32_t a = pos[size_t(m.h_row[e])], b = pos[size_t(m.h_col[e])];
+      if (a >= 0 && b >= 0) { r.push_back(a); c.push_back(b); v.push_back(m.h_val[e]); }
+    }
+    m.h_row.swap(r);
+    m.h_col.swap(c);
+    m.h_val.swap(v);
+    for (auto &mv : m.moves) {
+      std::vector<Model::Move> kept;
+      for (const Model::Move &x : mv)
+        if (pos[size_t(x.src)] >= 0)
+          kept.push_back({pos[size_t(x.src)], x.dst >= 0 ? pos[size_t(x.dst)] : -1, x.c});
+      mv.swap(kept);
+    }
+    m.n = n_keep;
+    return true;
   }
   // window index -> current index -> new index
   if (m.remap.empty()) {
@@ -209,12 +310,6 @@ bool enumerate_basis(Model &m, std::string &err) {
 
 // ------------------------------------------------------------ Hamiltonian
 
-namespace {
-struct Trip {
-  int32_t r, c;
-  double v;
-};
-}  // namespace
 
 // Visit every off-diagonal move of the coupling/hopping terms from source
 // state u: fn(param_index, target, amplitude).  param_index follows the
@@ -257,6 +352,12 @@ static void for_each_move(const Model &m, int64_t u, std::vector<int32_t> &buf,
 
 void hamiltonian_coo(const Model &m, std::vector<int32_t> &r,
                      std::vector<int32_t> &c, std::vector<double> &v) {
+  if (m.general) {   // already sorted by (row, col) and merged; a subset keeps the order
+    r = m.h_row;
+    c = m.h_col;
+    v = m.h_val;
+    return;
+  }
   const int M = m.n_modes;
   const int n_atoms = int(m.atom_mode.size());
   std::vector<Trip> t;
@@ -287,6 +388,7 @@ void hamiltonian_coo(const Model &m, std::vector<int32_t> &r,
 }
 
 std::vector<TermCoo> hamiltonian_terms(const Model &m) {
+  if (m.general) return {};
   const int n_atoms = int(m.atom_mode.size());
   std::vector<TermCoo> terms(n_atoms + m.hops.size());
   std::vector<int32_t> buf(m.n_modes);
@@ -332,7 +434,22 @@ JumpTables jump_tables(const Model &m) {
   jt.unit_ada.assign(size_t(nj) * n, 0.0);
   std::vector<int32_t> buf(M);
   std::vector<char> has_arrival(nj, 0);
-  for (int j = 0; j < nj; ++j) {
+  for (int j = 0; m.general && j < nj; ++j) {
+    const double gamma = m.jumps[j].gamma;
+    for (const Model::Move &x : m.moves[j]) {
+      const double a2 = x.c * x.c;
+      jt.unit_ada[size_t(j) * n + x.src] = a2;
+      jt.d[x.src] += gamma * a2;
+      if (x.dst >= 0) {
+        jt.unit_pi[size_t(j) * n + x.dst] = x.src;
+        jt.unit_c[size_t(j) * n + x.dst] = x.c;
+        has_arrival[j] = 1;
+      } else {
+        jt.leak[x.src] += gamma * a2;
+      }
+    }
+  }
+  for (int j = 0; !m.general && j < nj; ++j) {
     const qme_jump &jp = m.jumps[j];
     int mode = jp.kind == QME_JUMP_PHOTON_LEAK
                    ? m.photon_mode[jp.cavity]

@@ -38,6 +38,18 @@ struct Model {
   // cnt[m * (exc_hi + 1) + s]: completions of modes m.. given prefix sum s
   // that land in the window; rank() sums it over the levels below a tuple's
   std::vector<uint64_t> cnt;
+  // general form (qme_hamiltonian_general): H given as sorted, merged,
+  // symmetric COO and each decoherence operator as monomial moves
+  // (A |src> = c |dst>, dst = -1: out of the basis); jumps[j].gamma holds the
+  // rates.  No occupation table, no parameter terms.
+  struct Move {
+    int32_t src, dst;
+    double c;
+  };
+  bool general = false;
+  std::vector<int32_t> h_row, h_col;
+  std::vector<double> h_val;
+  std::vector<std::vector<Move>> moves;   // per jump
   // selected subset of the window basis (state-space selection): remap[f]
   // is the index of window state f in this basis, -1 if it was removed;
   // empty when the basis is the whole window
@@ -92,6 +104,10 @@ bool enumerate_basis(Model &m, std::string &err);
 // Keep only basis states keep[0..n_keep) (strictly increasing indices into
 // the current basis), in that order.
 bool restrict_basis(Model &m, const int32_t *keep, int64_t n_keep, std::string &err);
+// A model in the general form (validates: symmetric H, monomial jumps).
+bool build_general_model(int64_t n, int64_t h_nnz, const int32_t *h_rows, const int32_t *h_cols,
+                         const double *h_vals, int32_t n_jumps, const qme_general_jump *jumps,
+                         double dt, Model &m, std::string &err, bool &unsupported);
 void hamiltonian_coo(const Model &m, std::vector<int32_t> &r,
                      std::vector<int32_t> &c, std::vector<double> &v);
 Csr to_csr(int64_t n, const std::vector<int32_t> &r,

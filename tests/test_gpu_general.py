@@ -1,0 +1,155 @@
+"""General-form models on the device (qme_hamiltonian_general): a structured
+model exported to matrices steps bitwise as its structured context; the
+hydrogen-bond model of Sec. IV.A (N = 64) against the oracle in every
+precision; the three-molecule model (N = 4096) against the product of two
+one-bond runs (bonds are independent, so a product state stays a product);
+state-space selection on the model (the mechanism of Table I) against the
+oracle loop; argument errors."""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import hydrogen_bond as hb
+from oracle import evolve as ev
+from oracle import selection as sel
+from general_models import export_general
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2403_07042_amd")
+from paper_2403_07042_amd import _lib as L  # noqa: E402
+
+TOL = {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_exported_model_is_bitwise_the_structured_one(precision):
+    wl = W.tch_2x2(steps=50)
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    a = P.Solver(wl, precision)
+    # the library's own H (its rounding of mu sqrt(n) sqrt(m + 1) and the
+    # like), the oracle's decoherence moves
+    b = P.Solver(export_general(wl, P.hamiltonian_coo(wl)), precision)
+    assert b.n == a.n and b.ld == a.ld
+    for s in (a, b):
+        s.set_rho(rho0)
+        s.step(50)
+    ra, sa = a.get_rho()
+    rb, sb = b.get_rho()
+    a.close()
+    b.close()
+    assert np.array_equal(ra, rb) and sa == sb
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_hydrogen_bond_64_against_oracle(precision):
+    wl = hb.hb_model(1, steps=2000)
+    rho0 = hb.initial_rho(wl)
+    ref = {}
+    s = ev.GeneralSystem(wl)
+    rho, sink, rec = ev.evolve(s, rho0, 2000, record_every=500)
+    for k, r, sk in rec:
+        ref[k] = (r, sk)
+    sol = P.Solver(wl, precision)
+    sol.set_rho(rho0)
+    done = 0
+    for k in sorted(ref):
+        print(f"hydrogen bond 64 {precision}: step {k}", flush=True)
+        sol.step(k - done)
+        done = k
+        got, gsink = sol.get_rho()
+        assert np.abs(got - ref[k][0]).max() < TOL[precision], k
+        assert abs(gsink - ref[k][1]) < 1e-6
+    pops, trace, _ = sol.observe()
+    probs = hb.bond_probabilities(wl, pops)
+    assert abs(probs.sum() - 1.0) < 1e-5
+    sol.close()
+
+
+def test_hydrogen_bond_4096_closed_is_product_of_one_bond_runs():
+    """Three molecules (two bonds, N = 4096), decoherence off, FP32, 400
+    steps from a product basis state: the bonds do not interact, so the
+    state is the Kronecker product of two N = 64 runs, to FP32 tolerance.
+    (With decoherence on, the explicit dissipator step adds a cross term
+    dt^2 D(a) x D(b) per step, so the product holds only to O(dt^2); that
+    case is checked against the oracle below.)"""
+    one = hb.hb_model(1, gamma_photon=0.0, gamma_phonon=0.0)
+    two = hb.hb_model(2, gamma_photon=0.0, gamma_phonon=0.0)
+    s1 = P.Solver(one, "fp32")
+    s1.set_rho(hb.initial_rho(one))
+    s2 = P.Solver(two, "fp32")
+    assert s2.n == 4096
+    s2.set_rho(hb.initial_rho(two))
+    print("hydrogen bond 4096 closed fp32: 400 steps", flush=True)
+    s1.step(400)
+    s2.step(400)
+    r1, _ = s1.get_rho()
+    r2, sink2 = s2.get_rho()
+    s1.close()
+    s2.close()
+    assert np.abs(r2 - np.kron(r1, r1)).max() < 2e-5
+    probs = hb.bond_probabilities(two, np.real(np.diag(r2)))
+    p1 = hb.bond_probabilities(one, np.real(np.diag(r1)))
+    assert abs(probs[2] - p1[1] ** 2) < 1e-5 and abs(probs[0] - p1[0] ** 2) < 1e-5
+
+
+def test_hydrogen_bond_4096_open_against_oracle():
+    """Three molecules with the leaks on, FP32, first 3 steps against the
+    oracle at full size."""
+    two = hb.hb_model(2)
+    rho0 = hb.initial_rho(two)
+    print("hydrogen bond 4096: oracle propagator", flush=True)
+    s = ev.GeneralSystem(two)
+    ref, ref_sink = ev.evolve(s, rho0, 3)
+    sol = P.Solver(two, "fp32")
+    sol.set_rho(rho0)
+    sol.step(3)
+    got, sink = sol.get_rho()
+    sol.close()
+    assert np.abs(got - ref).max() < 1e-6
+    assert abs(sink - ref_sink) < 1e-9
+
+
+def test_selection_on_hydrogen_bond_64_matches_oracle():
+    """The mechanism of Table I on the paper's model: after every 10 steps
+    states whose probability moves slower than eps are removed."""
+    wl = hb.hb_model(1, steps=400)
+    rho0 = hb.initial_rho(wl)
+    for eps in (1e-35, 1e-20):
+        ref_rho, ref_sink, ref_kept, ref_sizes = sel.select_evolve(wl, rho0, 400, eps, every=10)
+        sol = P.Solver(wl, "fp64")
+        sol.set_rho(rho0)
+        out, kept, sizes = P.evolve_with_selection(sol, 400, eps, every=10)
+        rho, sink = out.get_rho()
+        if out is not sol:
+            out.close()
+        sol.close()
+        print(f"selection eps={eps}: 64 -> {sizes[-1]} states", flush=True)
+        assert sizes == ref_sizes and np.array_equal(kept, ref_kept)
+        assert np.abs(rho - ref_rho).max() < 1e-11
+        assert sizes[-1] < 64
+
+
+def test_general_model_errors():
+    wl = hb.hb_model(1)
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(hb.initial_rho(wl))
+    with pytest.raises(L.QmeError) as e:
+        sol.adjoint(5, np.zeros(64))
+    assert "QME_E_UNSUPPORTED" in str(e.value)
+    sol.close()
+    r, c, v = wl["h"]
+    bad = dict(wl, h=(r, c, v + (r > c) * 1e-3))              # H no longer symmetric
+    with pytest.raises(L.QmeError) as e:
+        P.Solver(bad, "fp32")
+    assert "QME_E_ARG" in str(e.value)
+    two_images = dict(wl, jumps=[(0.1, [0, 0], [1, 2], [1.0, 1.0])])
+    with pytest.raises(L.QmeError) as e:
+        P.Solver(two_images, "fp32")
+    assert "QME_E_UNSUPPORTED" in str(e.value)
+    out_of_range = dict(wl, jumps=[(0.1, [0], [64], [1.0])])
+    with pytest.raises(L.QmeError) as e:
+        P.Solver(out_of_range, "fp32")
+    assert "QME_E_ARG" in str(e.value)
