@@ -71,6 +71,8 @@ def parse():
                     help="time the state-space selection loop on the N = 2048 lattice (0: skip)")
     ap.add_argument("--plane-steps", type=int, default=100,
                     help="steps timed on the N = 4131 photon plane (0: skip)")
+    ap.add_argument("--hb-steps", type=int, default=100,
+                    help="steps timed on the N = 4096 hydrogen-bond model (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
     ap.add_argument("--adjoint-all-resident", type=int, default=1,
                     help="also time the adjoint with every state kept in HBM (no recompute)")
@@ -292,6 +294,36 @@ def plane_leg(P, W, torch, steps=100, warmup=5):
             "executed_frac_of_fp32_peak": flops * out["steps_per_s"] / 1e12 / PEAK_FP32_MFMA}
 
 
+def hydrogen_bond_leg(P, torch, steps=100, warmup=5):
+    """The hydrogen-bond model of Sec. IV.A with two bonds (three molecules,
+    N = 4096), built as a general-form model: FP32 steps/s, and the basis
+    left by the state-space selection loop (compared every 10 steps over
+    200 steps) at the two epsilons of Table I."""
+    from workloads import hydrogen_bond as hb
+    wl = hb.hb_model(2, steps=steps)
+    rho0 = hb.initial_rho(wl)
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(rho0)
+    sol.step(warmup)
+    sol.set_rho(rho0)
+    sol.profile(True)
+    dt = _timed(torch, lambda: sol.step(steps))
+    prof = sol.profile_read()
+    sol.profile(False)
+    sizes = {}
+    for eps in (1e-35, 1e-20):
+        sol.set_rho(rho0)
+        out, kept, hist = P.evolve_with_selection(sol, 200, eps, 10)
+        sizes[str(eps)] = int(hist[-1])
+        if out is not sol:
+            out.close()
+    sol.close()
+    return {"workload": "hydrogen_bond_3_molecules_n4096", "precision": "fp32", "N": wl["n"],
+            "steps": steps, "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "kernels_us": {k: (1e3 * ms / max(cnt, 1)) for k, (ms, cnt) in prof.items()},
+            "selected_basis_after_200_steps": sizes}
+
+
 def cpu_baseline(W, wl, gpu_leg, steps):
     """The CPU oracle (NumPy complex128) timed on the host cores on a bounded
     sample of the same workload, plus the parity of the GPU run's final
@@ -361,6 +393,7 @@ def main():
     latency = latency_leg(P, W, torch) if args.latency else None
     selection = selection_leg(P, W, torch) if args.selection else None
     plane = plane_leg(P, W, torch, args.plane_steps) if args.plane_steps > 0 else None
+    hbond = hydrogen_bond_leg(P, torch, args.hb_steps) if args.hb_steps > 0 else None
 
     adj = None
     if args.adjoint_steps > 0:
@@ -431,6 +464,7 @@ def main():
         "latency_bound": latency,
         "state_selection": selection,
         "photon_plane": plane,
+        "hydrogen_bond": hbond,
     }
     if "bf16x3" in res:
         b = res["bf16x3"]

@@ -33,7 +33,7 @@ struct BatchInstance {
   double *aux;
   float *y_re, *y_im, *z_re, *z_im;
   const float *u_re, *u_im;
-  const double *d, *leak, *cg;
+  const double *d, *leak, *cg, *trw;
   const int32_t *pi;
   int64_t n, ld;
   double dt;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p
     cgemm_f32_tile<64, kConjB>(g, bi, bj, smem);
   } else {
     const DissArgs<float> da{in.z_re, in.z_im, in.x_re, in.x_im, in.ld, in.n, in.dt, in.d,
-                             in.leak, in.pi, in.cg, in.n_gather, in.aux, in.aux};
+                             in.leak, in.pi, in.cg, in.n_gather, in.aux, in.aux, in.trw};
     if constexpr (PHASE == 2) {
       double *sd = reinterpret_cast<double *>(smem);
       trace_body<float, kBatchThreads>(da, sd, sd + kBatchThreads, sd + 2 * kBatchThreads);
@@ -179,6 +179,7 @@ static qme_status build_tables(qme_batch *b) {
     t.u_im = static_cast<const float *>(c->du_im);
     t.d = c->d;
     t.leak = c->leak;
+    t.trw = c->trw;
     t.cg = c->cg;
     t.pi = c->pi;
     t.n = c->n;

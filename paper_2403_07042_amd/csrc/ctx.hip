@@ -94,7 +94,7 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   CgemmArgs<T> g1{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
   CgemmArgs<T> g2{y_re, y_im, u_re, u_im, y_re, y_im, z_re, z_im, c->ld, T(1), T(1)};
   DissArgs<T> da{z_re, z_im, o_re, o_im, c->ld, c->n, c->model.dt, c->d, c->leak,
-                 c->pi, c->cg, c->jt.n_gather, aux_in, aux_out};
+                 c->pi, c->cg, c->jt.n_gather, aux_in, aux_out, c->trw};
   GemmOps o1, o2;
   o1.conj_b = o2.conj_b = true;
   o2.lower = true;
@@ -151,7 +151,7 @@ static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     SmallArgs<T> a{re, re + pe, reinterpret_cast<double *>(re + 2 * pe),
                    static_cast<const T *>(c->du_re), static_cast<const T *>(c->du_im),
                    c->ld, int(c->n), c->model.dt, c->d, c->leak, c->pi, c->cg,
-                   c->jt.n_gather, n_steps};
+                   c->jt.n_gather, n_steps, c->trw};
     hipError_t e = mark(c, s, -1);
     if (e == hipSuccess) e = launch_small_steps<T>(a, s);
     if (e == hipSuccess) e = mark(c, s, 0);
@@ -225,6 +225,23 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
   HIP_OK(hipMalloc(&c->diag, sizeof(double) * (n + 8)));
   HIP_OK(hipMemcpy(c->d, c->jt.d.data(), sizeof(double) * n, hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(c->leak, c->jt.leak.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  {
+    // trace weights: every jump term c_j[u]^2 Z[w,w] (w = pi_j[u]) counted
+    // at the state w it reads
+    const double dt = c->model.dt;
+    std::vector<double> trw(static_cast<size_t>(n), 0.0);
+    for (int64_t w = 0; w < n; ++w) trw[size_t(w)] = 1.0 - dt * c->jt.d[size_t(w)];
+    for (int j = 0; j < c->jt.n_gather; ++j)
+      for (int64_t u = 0; u < n; ++u) {
+        const int32_t w = c->jt.pi[size_t(j) * n + u];
+        if (w >= 0) {
+          const double cg = c->jt.cg[size_t(j) * n + u];
+          trw[size_t(w)] += dt * cg * cg;
+        }
+      }
+    HIP_OK(hipMalloc(&c->trw, sizeof(double) * n));
+    HIP_OK(hipMemcpy(c->trw, trw.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  }
   const size_t ng = size_t(std::max(1, c->jt.n_gather)) * n;
   HIP_OK(hipMalloc(&c->pi, sizeof(int32_t) * ng));
   HIP_OK(hipMalloc(&c->cg, sizeof(double) * ng));
@@ -692,7 +709,7 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
 
 qme_ctx::~qme_ctx() {
   for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
-  for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)diag, (void *)pi, (void *)cg,
+  for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)trw, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,
                   (void *)h_ptr, (void *)h_col, (void *)h_val, (void *)t_row, (void *)t_col,
                   (void *)t_val})

@@ -27,6 +27,7 @@ struct qme_ctx {
   void *du_re = nullptr, *du_im = nullptr;   // dU planes, ld x ld, storage type
   void *du_split = nullptr;                  // BF16X3: dU as six bf16 planes (split once)
   double *d = nullptr, *leak = nullptr, *diag = nullptr;
+  double *trw = nullptr;              // trace weights (DissArgs::trw)
   int32_t *pi = nullptr;
   double *cg = nullptr;
   // adjoint tables (owned)

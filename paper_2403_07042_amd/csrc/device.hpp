@@ -74,6 +74,9 @@ struct DissArgs {
   int n_gather;
   const double *aux_in;  // scalars of the input state (sink)
   double *aux_out;       // scalars of the output state (see qme_state_layout)
+  // trace weights: tr rho_d = sum_w trw[w] Z[w,w] with
+  // trw[w] = 1 - dt d[w] + dt sum_{j,u: pi_j[u] = w} cg_j[u]^2
+  const double *trw = nullptr;
 };
 
 template <typename T>
@@ -100,6 +103,7 @@ struct SmallArgs {
   const double *cg;
   int n_gather;
   int64_t steps;
+  const double *trw;       // trace weights (see DissArgs)
 };
 template <typename T>
 hipError_t launch_small_steps(const SmallArgs<T> &a, hipStream_t s);

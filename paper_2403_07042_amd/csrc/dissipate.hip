@@ -9,8 +9,10 @@
 //              + dt sum_j cg_j[u] cg_j[v] Z[pi_j[u], pi_j[v]]   (cg = sqrt(gamma) c).
 //
 // trace_kernel (one workgroup) needs only the diagonal of Z: it forms
-// tr rho_d and the probability leaving the basis in FP64, updates the sink
-// and the renormalisation factor (1 - sink) / tr rho_d.  dissipate_kernel
+// tr rho_d = sum_w trw[w] Z[w,w] (the jump terms regrouped by the diagonal
+// element they read, weights fixed per context) and the probability leaving
+// the basis in FP64, updates the sink and the renormalisation factor
+// (1 - sink) / tr rho_d.  dissipate_kernel
 // then writes X = scale * rho_d for u >= v and its conjugate mirror, so X is
 // exactly Hermitian; all arithmetic is FP64 whatever the storage type.
 #include "dissipate_tile.hpp"

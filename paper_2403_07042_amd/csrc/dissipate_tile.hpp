@@ -11,8 +11,10 @@
 //              + dt sum_j cg_j[u] cg_j[v] Z[pi_j[u], pi_j[v]]   (cg = sqrt(gamma) c).
 //
 // trace_kernel (one workgroup) needs only the diagonal of Z: it forms
-// tr rho_d and the probability leaving the basis in FP64, updates the sink
-// and the renormalisation factor (1 - sink) / tr rho_d.  dissipate_kernel
+// tr rho_d = sum_w trw[w] Z[w,w] (the jump terms regrouped by the diagonal
+// element they read, weights fixed per context) and the probability leaving
+// the basis in FP64, updates the sink and the renormalisation factor
+// (1 - sink) / tr rho_d.  dissipate_kernel
 // then writes X = scale * rho_d for u >= v and its conjugate mirror, so X is
 // exactly Hermitian; all arithmetic is FP64 whatever the storage type.
 #pragma once
@@ -42,33 +44,25 @@ __device__ __forceinline__ void zlower(const DissArgs<T> &p, int64_t a, int64_t 
 template <typename T, int NT>
 __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, double *s_lost,
                                            double *s_rot) {
+  // tr rho_d = sum_u rho_d[u,u] = sum_w trw[w] Z[w,w]: the jump terms
+  // c_j[u]^2 Z[pi_j u, pi_j u] regrouped by the state w = pi_j u they read
   double tr = 0.0, lost = 0.0, rot = 0.0;
   // u = threadIdx.x + k NT in increasing k; the loads of G values of k are
   // issued together, the sums keep that order
   constexpr int G = 4;
   for (int64_t u0 = threadIdx.x; u0 < p.n; u0 += int64_t(G) * NT) {
-    double z[G], dk[G], lk[G];
+    double z[G], wk[G], lk[G];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
       const int64_t u = u0 + int64_t(gi) * NT;
       const bool ok = u < p.n;
       z[gi] = ok ? double(p.z_re[u * p.ld + u]) : 0.0;
-      dk[gi] = ok ? p.d[u] : 0.0;
+      wk[gi] = ok ? p.trw[u] : 0.0;
       lk[gi] = ok ? p.leak[u] : 0.0;
     }
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
-      const int64_t u = u0 + int64_t(gi) * NT;
-      if (u >= p.n) break;
-      double dd = z[gi] * (1.0 - p.dt * dk[gi]);
-      for (int j = 0; j < p.n_gather; ++j) {
-        const int32_t pu = p.pi[int64_t(j) * p.n + u];
-        if (pu >= 0) {
-          const double c = p.cg[int64_t(j) * p.n + u];
-          dd += p.dt * c * c * double(p.z_re[int64_t(pu) * p.ld + pu]);
-        }
-      }
-      tr += dd;
+      tr += wk[gi] * z[gi];
       lost += lk[gi] * z[gi];
       rot += z[gi];
     }

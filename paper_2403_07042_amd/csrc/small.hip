@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_steps_kernel(SmallArgs<T>
   __shared__ T sU[2][kSmallN * kSmallLd];
   __shared__ T sA[2][kSmallN * kSmallLd];
   __shared__ T sB[2][kSmallN * kSmallLd];
-  __shared__ double s_d[kSmallN], s_leak[kSmallN];
+  __shared__ double s_d[kSmallN], s_leak[kSmallN], s_trw[kSmallN];
   __shared__ int32_t s_pi[kSmallGather][kSmallN];
   __shared__ double s_cg[kSmallGather][kSmallN];
   __shared__ double s_scale;
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_steps_kernel(SmallArgs<T>
   for (int u = tid; u < n; u += kSmallThreads) {
     s_d[u] = p.d[u];
     s_leak[u] = p.leak[u];
+    s_trw[u] = p.trw[u];
   }
   if (staged)
     for (int e = tid; e < p.n_gather * n; e += kSmallThreads) {
@@ -99,15 +100,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_steps_kernel(SmallArgs<T>
       if (tid < n) {
         const int u = tid;
         const double zu = double(z[0][u * kSmallLd + u]);
-        double dd = zu * (1.0 - dt * s_d[u]);
-        for (int j = 0; j < p.n_gather; ++j) {
-          const int32_t pu = staged ? s_pi[j][u] : p.pi[int64_t(j) * n + u];
-          if (pu >= 0) {
-            const double c = staged ? s_cg[j][u] : p.cg[int64_t(j) * n + u];
-            dd += dt * c * c * double(z[0][pu * kSmallLd + pu]);
-          }
-        }
-        tr = dd;
+        tr = s_trw[u] * zu;
         lo = s_leak[u] * zu;
         ro = zu;
       }
