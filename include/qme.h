@@ -352,6 +352,21 @@ qme_status qme_set_split(qme_ctx *ctx, int32_t enable);
  * 1, else QME_E_ARG. */
 qme_status qme_set_fused(qme_ctx *ctx, int32_t enable);
 
+/* Folded steps (on by default).  For a model in which no decoherence
+ * operator maps a basis state onto another basis state (every jump leaves
+ * the basis, as the boundary leaks of the single-excitation lattice do), the
+ * decoherence step is one factor per element, (1 - dt (d_u + d_v) / 2): the
+ * lower-triangle product applies it in its epilogue and writes the state
+ * (both triangles) directly, the trace pass reads the diagonal it stored,
+ * and the renormalisation factor is applied by the next step's first
+ * product (its scalars come from the state's scalars on the device) and,
+ * after the last step of a qme_step call, by one pass over the state.  This
+ * is the renormalisation "folded into the next product" and saves the
+ * decoherence pass.  Applies to FP32 contexts whose lower-product tile is 64
+ * and to FP64 contexts; results differ from the unfolded step by rounding
+ * only.  enable: 0 or 1, else QME_E_ARG. */
+qme_status qme_set_fold(qme_ctx *ctx, int32_t enable);
+
 /* Per-kernel timing of qme_step with HIP events recorded on the caller's
  * stream around every launch (the tracing facility used by the benchmark).
  * enable != 0 starts recording (and clears earlier records); 0 stops it. */

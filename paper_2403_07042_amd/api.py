@@ -245,6 +245,11 @@ class Solver:
         """Tail split of the lower-triangle product on (default) or off."""
         L.check(self.lib.qme_set_split(self.ctx, int(bool(enable))))
 
+    def set_fold(self, enable: bool):
+        """Folded steps (decoherence in the lower product's epilogue,
+        renormalisation in the next product) on (default) or off."""
+        L.check(self.lib.qme_set_fold(self.ctx, int(bool(enable))))
+
     def set_fused(self, enable: bool):
         """Single-workgroup path for N <= 32 (FP32 / FP64) on (default) or off."""
         L.check(self.lib.qme_set_fused(self.ctx, int(bool(enable))))

@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
   if (LOWER) {
     const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
     tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
-    cgemm_f32_tile<BM, OPS>(p, bi, bj, smem, w.kb, w.ke,
-                            w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
+    cgemm_f32_tile<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke,
+                                  w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
     return;
   }
   tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p
   if (LOWER) {
     const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
     tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
-    cgemm_f64_tile<BM, OPS>(p, bi, bj, smem, w.kb, w.ke,
-                            w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
+    cgemm_f64_tile<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke,
+                                  w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
     return;
   }
   tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
@@ -96,17 +96,60 @@ __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
   }
   const int64_t o = (int64_t(bi) * BM + e / BM) * p.ld + int64_t(bj) * BM + e % BM;
   const bool has_x = p.beta != T(0);
+  const bool scaled = p.scale != nullptr;
+  const double sc = scaled ? *p.scale : 1.0;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    T vr = p.alpha * sr[v], vi = p.alpha * si[v];
-    if (has_x) {
-      vr += p.beta * p.x_re[o + v];
-      vi += p.beta * p.x_im[o + v];
+    T vr, vi;
+    epi_value(p, has_x, scaled, sc, o + v, sr[v], si[v], vr, vi);
+    if (!p.fold_d) {
+      p.c_re[o + v] = vr;
+      p.c_im[o + v] = vi;
+      continue;
     }
-    p.c_re[o + v] = vr;
-    p.c_im[o + v] = vi;
+    // folded decoherence step (as fold_elem), mirror written directly
+    const int rl = e / BM, cl = e % BM + v;
+    if (bi == bj && cl > rl) continue;
+    const int64_t row = int64_t(bi) * BM + rl, col = int64_t(bj) * BM + cl;
+    const double zr = double(vr), zi = double(vi);
+    const double du = row < p.fold_n ? p.fold_d[row] : 0.0;
+    const double dv = col < p.fold_n ? p.fold_d[col] : 0.0;
+    const double f = 1.0 - 0.5 * p.fold_dt * (du + dv);
+    double xr = f * zr, xi = f * zi;
+    if (row == col) {
+      xi = 0.0;
+      if (row < p.fold_n) p.zdiag[row] = zr;
+    }
+    p.c_re[o + v] = T(xr);
+    p.c_im[o + v] = T(xi);
+    if (row != col) {
+      p.c_re[col * p.ld + row] = T(xr);
+      p.c_im[col * p.ld + row] = T(-xi);
+    }
   }
 }
+
+// x *= *scale over a state's planes (FP64 product, rounded to T)
+template <typename T>
+__global__ __launch_bounds__(256) void apply_scale_kernel(T *re, T *im, int64_t elems,
+                                                          const double *scale) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= elems) return;
+  const double s = *scale;
+  re[i] = T(s * double(re[i]));
+  im[i] = T(s * double(im[i]));
+}
+
+template <typename T>
+hipError_t launch_apply_scale(T *re, T *im, int64_t elems, const double *scale, hipStream_t s) {
+  if (elems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(apply_scale_kernel<T>, dim3(unsigned((elems + 255) / 256)), dim3(256), 0, s,
+                     re, im, elems, scale);
+  return hipGetLastError();
+}
+template hipError_t launch_apply_scale<float>(float *, float *, int64_t, const double *, hipStream_t);
+template hipError_t launch_apply_scale<double>(double *, double *, int64_t, const double *,
+                                               hipStream_t);
 
 SplitPlan plan_tail_split(int tiles, int bm, int kt, int64_t ld, int cus, size_t cap_elems) {
   SplitPlan sp;

@@ -128,6 +128,68 @@ __device__ __forceinline__ S opsum_a(S r, S i) { return (OPS & kConjA) ? r - i :
 template <int OPS, typename S>
 __device__ __forceinline__ S opsum_b(S r, S i) { return (OPS & kConjB) ? r - i : r + i; }
 
+// Value of one output element: alpha acc + beta X, or with a device scale
+// s (the previous step's renormalisation) s acc + s X formed in FP64.
+template <typename T>
+__device__ __forceinline__ void epi_value(const CgemmArgs<T> &p, bool has_x, bool scaled, double s,
+                                          int64_t o, T ar, T ai, T &vr, T &vi) {
+  if (scaled) {
+    double xr = s * double(ar), xi = s * double(ai);
+    if (has_x) {
+      xr += s * double(p.x_re[o]);
+      xi += s * double(p.x_im[o]);
+    }
+    vr = T(xr);
+    vi = T(xi);
+  } else {
+    vr = p.alpha * ar;
+    vi = p.alpha * ai;
+    if (has_x) {
+      vr += p.beta * p.x_re[o];
+      vi += p.beta * p.x_im[o];
+    }
+  }
+}
+
+// Folded decoherence epilogue of a lower-triangle tile (see CgemmArgs):
+// element (rl, cl) of tile (bi, bj) with Z = (vr, vi).  The element is
+// written and staged in LDS for the conjugate mirror; the strict upper part
+// of a diagonal tile is left to fold_mirror.
+// du, dv: fold_d of the element's row and column (0 past fold_n).
+template <typename T, int BM>
+__device__ __forceinline__ void fold_elem(const CgemmArgs<T> &p, int bi, int bj, int rl, int cl,
+                                          T vr, T vi, double du, double dv, T (*s_re)[BM + 1],
+                                          T (*s_im)[BM + 1]) {
+  if (bi == bj && cl > rl) return;
+  const int64_t row = int64_t(bi) * BM + rl, col = int64_t(bj) * BM + cl;
+  const double zr = double(vr), zi = double(vi);
+  const double f = 1.0 - 0.5 * p.fold_dt * (du + dv);
+  double xr = f * zr, xi = f * zi;
+  if (row == col) {
+    xi = 0.0;
+    if (row < p.fold_n) p.zdiag[row] = zr;
+  }
+  const int64_t o = row * p.ld + col;
+  p.c_re[o] = T(xr);
+  p.c_im[o] = T(xi);
+  s_re[rl][cl] = T(xr);
+  s_im[rl][cl] = T(xi);
+}
+
+// The conjugate mirror of a folded tile from its LDS copy (after a barrier):
+// element (bj*BM + a, bi*BM + b) = conj(tile[b][a]), rows written contiguously.
+template <typename T, int BM>
+__device__ __forceinline__ void fold_mirror(const CgemmArgs<T> &p, int bi, int bj,
+                                            T (*s_re)[BM + 1], T (*s_im)[BM + 1]) {
+  for (int idx = threadIdx.x; idx < BM * BM; idx += kThreads) {
+    const int a = idx / BM, b = idx - (idx / BM) * BM;
+    if (bi == bj && b <= a) continue;
+    const int64_t o = (int64_t(bj) * BM + a) * p.ld + int64_t(bi) * BM + b;
+    p.c_re[o] = s_re[b][a];
+    p.c_im[o] = -s_im[b][a];
+  }
+}
+
 // ----------------------------------------------------------------- FP32
 // v_mfma_f32_32x32x2_f32: A 32x2 (lane l: row l%32, k-slot l/32), B 2x32
 // (lane l: k-slot l/32, col l%32), D 32x32 in 16 registers (lane l: col l%32,
@@ -148,7 +210,9 @@ constexpr int cgemm_f64_smem() {
   return 4 * BM * LDK + 4 * BSZ;
 }
 
-template <int BM, int OPS>
+// FOLD: the kernel may apply the folded decoherence epilogue (lower-triangle
+// launches; see CgemmArgs::fold_d).
+template <int BM, int OPS, bool FOLD = false>
 __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi, int bj, float *smem,
                                                int kb = 0, int ke = -1, float *part = nullptr) {
   constexpr bool BROW = OPS & kBRow;
@@ -301,26 +365,53 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
         }
     return;
   }
-  // epilogue: C = alpha * acc + beta * X
+  // epilogue: C = alpha * acc + beta * X (or the folded decoherence step);
+  // the operand LDS is free after the k loop's last barrier
   const bool has_x = p.beta != 0.0f;
+  // the tile staged for the mirror (2 BM (BM + 1) elements) and the factors
+  // d of its rows and columns (2 BM doubles) fit the operand LDS
+  constexpr bool kCanFold =
+      FOLD && 2 * BM * (BM + 1) * sizeof(float) + 2 * BM * sizeof(double) <=
+                  cgemm_f32_smem<BM, OPS>() * sizeof(float);
+  const bool fold = kCanFold && p.fold_d != nullptr;
+  float (*f_re)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem);
+  float (*f_im)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem + BM * (BM + 1));
+  double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
+  // the scale read once, before the stores (which could alias it)
+  const bool scaled = p.scale != nullptr;
+  const double sc = scaled ? *p.scale : 1.0;
+  if (fold) {
+    if (tid < 2 * BM) {
+      const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
+      f_d[tid] = u < p.fold_n ? p.fold_d[u] : 0.0;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int a = 0; a < F; ++a) {
 #pragma unroll
     for (int b = 0; b < F; ++b) {
-      const int64_t col = int64_t(bj) * BM + wn * WM + b * 32 + li;
+      const int cl = wn * WM + b * 32 + li;
+      const int64_t col = int64_t(bj) * BM + cl;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t row = int64_t(bi) * BM + wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int rl = wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int64_t row = int64_t(bi) * BM + rl;
         const int64_t o = row * ld + col;
-        float vr = p.alpha * cr[a][b][r], vi = p.alpha * ci[a][b][r];
-        if (has_x) {
-          vr += p.beta * p.x_re[o];
-          vi += p.beta * p.x_im[o];
+        float vr, vi;
+        epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
+        if (fold) {
+          fold_elem<float, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
+        } else {
+          p.c_re[o] = vr;
+          p.c_im[o] = vi;
         }
-        p.c_re[o] = vr;
-        p.c_im[o] = vi;
       }
     }
+  }
+  if (fold) {
+    __syncthreads();
+    fold_mirror<float, BM>(p, bi, bj, f_re, f_im);
   }
 }
 
@@ -329,7 +420,7 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
 // (lane l: k-slot l/16, col l%16), D 16x16 in 4 doubles (lane l: col l%16,
 // register r: row l/16 + 4*r).
 
-template <int BM, int OPS>
+template <int BM, int OPS, bool FOLD = false>
 __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int bi, int bj, double *smem,
                                                int kb = 0, int ke = -1, double *part = nullptr) {
   constexpr bool BROW = OPS & kBRow;
@@ -476,24 +567,45 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
     return;
   }
   const bool has_x = p.beta != 0.0;
+  constexpr bool kCanFold = FOLD && 2 * BM * (BM + 1) + 2 * BM <= cgemm_f64_smem<BM, OPS>();
+  const bool fold = kCanFold && p.fold_d != nullptr;
+  double (*f_re)[BM + 1] = reinterpret_cast<double (*)[BM + 1]>(smem);
+  double (*f_im)[BM + 1] = reinterpret_cast<double (*)[BM + 1]>(smem + BM * (BM + 1));
+  double *f_d = smem + 2 * BM * (BM + 1);
+  const bool scaled = p.scale != nullptr;
+  const double sc = scaled ? *p.scale : 1.0;
+  if (fold) {
+    if (tid < 2 * BM) {
+      const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
+      f_d[tid] = u < p.fold_n ? p.fold_d[u] : 0.0;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int a = 0; a < F; ++a) {
 #pragma unroll
     for (int b = 0; b < F; ++b) {
-      const int64_t col = int64_t(bj) * BM + wn * WM + b * 16 + li;
+      const int cl = wn * WM + b * 16 + li;
+      const int64_t col = int64_t(bj) * BM + cl;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = int64_t(bi) * BM + wm * WM + a * 16 + h + 4 * r;
+        const int rl = wm * WM + a * 16 + h + 4 * r;
+        const int64_t row = int64_t(bi) * BM + rl;
         const int64_t o = row * ld + col;
-        double vr = p.alpha * cr[a][b][r], vi = p.alpha * ci[a][b][r];
-        if (has_x) {
-          vr += p.beta * p.x_re[o];
-          vi += p.beta * p.x_im[o];
+        double vr, vi;
+        epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
+        if (fold) {
+          fold_elem<double, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
+        } else {
+          p.c_re[o] = vr;
+          p.c_im[o] = vi;
         }
-        p.c_re[o] = vr;
-        p.c_im[o] = vi;
       }
     }
+  }
+  if (fold) {
+    __syncthreads();
+    fold_mirror<double, BM>(p, bi, bj, f_re, f_im);
   }
 }
 

@@ -141,10 +141,80 @@ bool uses_small_path(const qme_ctx *c) {
   return c->fused && c->n <= kSmallN && c->precision != QME_BF16X3;
 }
 
+// The folded step applies when no decoherence operator maps a basis state
+// onto another (no gather channels: the decoherence step is a factor per
+// element), in FP32 with 64-tiles for the lower product or in FP64.
+bool uses_fold(const qme_ctx *c) {
+  if (!c->fold || c->jt.n_gather != 0) return false;
+  if (c->precision == QME_FP32) return c->tile2 == 64;
+  return c->precision == QME_FP64;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Folded steps: the lower-triangle product writes the decoherence step of
+// its tiles (unscaled, both triangles) straight into the state and the
+// diagonal of Z into the workspace; the trace pass reads that diagonal and
+// stores the renormalisation factor, which the next step's first product
+// applies (alpha = beta = factor); after the last step one pass applies it.
+template <typename T>
+static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws, hipStream_t s) {
+  const size_t pe = plane_elems(c);
+  T *x_re = static_cast<T *>(state), *x_im = x_re + pe;
+  double *aux = reinterpret_cast<double *>(x_im + pe);
+  T *y_re = static_cast<T *>(ws), *y_im = y_re + pe;
+  T *z_re = y_im + pe;                      // chunk partials of the split tail
+  double *zdiag = reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                             align256(4 * pe * sizeof(T)));
+  const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
+  const double dt = c->model.dt;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    CgemmArgs<T> g1{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
+    if (k > 0) g1.scale = aux + 4;
+    CgemmArgs<T> g2{y_re, y_im, u_re, u_im, y_re, y_im, x_re, x_im, c->ld, T(1), T(1)};
+    g2.fold_d = c->d;
+    g2.fold_dt = dt;
+    g2.fold_n = c->n;
+    g2.zdiag = zdiag;
+    if (c->tail_split) {
+      const SplitPlan sp = plan_tail_split(int(c->ld / c->tile2), c->tile2, 16, c->ld, c->cus, 2 * pe);
+      g2.full = sp.full;
+      g2.split = sp.split;
+      g2.part = z_re;
+    }
+    DissArgs<T> da{nullptr, nullptr, x_re, x_im, c->ld, c->n, dt, c->d, c->leak,
+                   c->pi, c->cg, 0, aux, aux, c->trw, zdiag};
+    GemmOps o1, o2;
+    o1.conj_b = o2.conj_b = true;
+    o2.lower = true;
+    auto gemm = [&](const CgemmArgs<T> &g, int tile, const GemmOps &o) {
+      if constexpr (sizeof(T) == 4) return launch_cgemm_f32(g, tile, o, s);
+      else return launch_cgemm_f64(g, tile, o, s);
+    };
+    hipError_t e = mark(c, s, -1);
+    if (e == hipSuccess) e = gemm(g1, c->tile1, o1);
+    if (e == hipSuccess) e = mark(c, s, 0);
+    if (e == hipSuccess) e = gemm(g2, c->tile2, o2);
+    if (e == hipSuccess) e = mark(c, s, 1);
+    if (e == hipSuccess) e = launch_trace<T>(da, s);
+    if (e == hipSuccess) e = mark(c, s, 2);
+    if (e != hipSuccess) return e;
+  }
+  return n_steps > 0 ? launch_apply_scale<T>(x_re, x_im, int64_t(pe), aux + 4, s) : hipSuccess;
+}
+
 template <typename T>
 static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
                             hipStream_t s) {
   const size_t pe = plane_elems(c);
+  if (!uses_small_path(c) && uses_fold(c)) {
+    hipError_t e = fold_steps<T>(c, state, n_steps, ws, s);
+    if (e != hipSuccess) {
+      set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return QME_E_DEVICE;
+    }
+    return QME_OK;
+  }
   if (uses_small_path(c)) {
     if (n_steps == 0) return QME_OK;
     T *re = static_cast<T *>(state);
@@ -470,7 +540,8 @@ extern "C" qme_status qme_state_layout(const qme_ctx *c, int64_t *n, int64_t *ld
 extern "C" qme_status qme_workspace_size(const qme_ctx *c, size_t *bytes) {
   set_error("");
   if (!c || !bytes) { set_error("NULL argument"); return QME_E_ARG; }
-  *bytes = 4 * plane_elems(c) * c->elem;
+  // the step's product planes, and the diagonal of Z for folded steps
+  *bytes = align256(4 * plane_elems(c) * c->elem) + align256(sizeof(double) * size_t(c->n));
   return QME_OK;
 }
 
@@ -638,6 +709,14 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
   if (e != hipSuccess) { set_error(std::string("launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
   return QME_OK;
   QME_GUARD_END
+}
+
+extern "C" qme_status qme_set_fold(qme_ctx *c, int32_t enable) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->fold = enable != 0;
+  return QME_OK;
 }
 
 extern "C" qme_status qme_set_fused(qme_ctx *c, int32_t enable) {

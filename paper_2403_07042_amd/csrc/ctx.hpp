@@ -21,6 +21,7 @@ struct qme_ctx {
   int tile1 = 64, tile2 = 64;         // tiles of the two products of a step
   bool tail_split = true;             // qme_set_split
   bool fused = true;                  // qme_set_fused (single-workgroup path, n <= 32)
+  bool fold = true;                   // qme_set_fold (decoherence folded into the products)
   int device = 0;
   int cus = 0;                        // compute units of the device
   // device tables (owned)
@@ -74,4 +75,5 @@ qme_status check_device(const qme_ctx *c);
 template <typename T>
 hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s);
 bool uses_small_path(const qme_ctx *c);
+bool uses_fold(const qme_ctx *c);
 }  // namespace qme

@@ -34,6 +34,19 @@ struct CgemmArgs {
   // (m_split) given as six bf16 planes [re hi, re mid, re lo, im hi, im mid,
   // im lo] of ld x ld, split once instead of per tile
   const void *a_split = nullptr, *m_split = nullptr;
+  // FP32 / FP64 products only.  scale: when set, alpha = beta = *scale,
+  // applied in FP64 (the renormalisation of the previous step folded into
+  // the first product).  fold_d: when set (lower-triangle products with
+  // 64-tiles in FP32, 32- or 64-tiles in FP64), the epilogue applies the
+  // decoherence step of a model without gather channels to
+  // Z = alpha acc + beta X (rounded to T): C[u][v] = (1 - dt (d[u] + d[v]) / 2)
+  // Z[u][v] for v <= u and its conjugate mirror for v > u, and writes
+  // zdiag[u] = Z[u][u] (FP64) for u < fold_n.
+  const double *scale = nullptr;
+  const double *fold_d = nullptr;
+  double fold_dt = 0.0;
+  int64_t fold_n = 0;
+  double *zdiag = nullptr;
 };
 
 // Plan of a tail split for a lower-triangle product of `tiles` tile rows
@@ -45,6 +58,9 @@ struct SplitPlan {
 SplitPlan plan_tail_split(int tiles, int bm, int kt, int64_t ld, int cus, size_t cap_elems);
 template <typename T>
 hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, hipStream_t s);
+// state planes (ld x ld each) *= *scale, in FP64 (the last step of a folded run)
+template <typename T>
+hipError_t launch_apply_scale(T *re, T *im, int64_t elems, const double *scale, hipStream_t s);
 
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o,
                             hipStream_t s);
@@ -77,6 +93,8 @@ struct DissArgs {
   // trace weights: tr rho_d = sum_w trw[w] Z[w,w] with
   // trw[w] = 1 - dt d[w] + dt sum_{j,u: pi_j[u] = w} cg_j[u]^2
   const double *trw = nullptr;
+  // when set, the diagonal of Z is read from this array (FP64, [n])
+  const double *zdiag = nullptr;
 };
 
 template <typename T>

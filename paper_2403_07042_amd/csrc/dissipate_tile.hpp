@@ -56,7 +56,7 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
     for (int gi = 0; gi < G; ++gi) {
       const int64_t u = u0 + int64_t(gi) * NT;
       const bool ok = u < p.n;
-      z[gi] = ok ? double(p.z_re[u * p.ld + u]) : 0.0;
+      z[gi] = !ok ? 0.0 : p.zdiag ? p.zdiag[u] : double(p.z_re[u * p.ld + u]);
       wk[gi] = ok ? p.trw[u] : 0.0;
       lk[gi] = ok ? p.leak[u] : 0.0;
     }

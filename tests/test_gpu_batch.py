@@ -1,6 +1,6 @@
 """Batched steps of uneven instances (one launch per phase over every
 instance's tiles, replayed from a captured hipGraph): every instance must
-equal its own qme_step run bitwise (same tile arithmetic), with and without
+equal its own unfolded qme_step run bitwise (same tile arithmetic), with and without
 the graph and for both instance orders; graph replays interleaved with eager
 work; oracle parity; argument errors."""
 import numpy as np
@@ -34,6 +34,7 @@ def make_solvers(wls):
 
 def solo_rho(wl, steps):
     s = P.Solver(wl, "fp32")
+    s.set_fold(False)            # the batched step does not fold its decoherence pass
     s.set_rho(W.initial_rho(wl, P.basis(wl)))
     s.step(steps)
     rho, sink = s.get_rho()

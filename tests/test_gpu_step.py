@@ -226,6 +226,41 @@ def test_tail_split_of_the_lower_product(precision, tol):
     assert abs(sa - sb) < 1e-12
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_folded_steps_match_unfolded(precision, tol):
+    """N = 2048 lattice (every decoherence operator leaves the basis, so the
+    decoherence step is a factor per element): folded steps (decoherence in
+    the lower product's epilogue, renormalisation in the next first product,
+    one closing pass per call) against the four-kernel step, from a dense
+    state, over several qme_step calls; exact Hermiticity and the trace."""
+    wl = dict(W.photon_lattice(gamma=0.05), init={"kind": "haar", "seed": 9})
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, precision)
+    out = {}
+    for fold in (True, False):
+        sol.set_fold(fold)
+        sol.set_rho(rho0)
+        print(f"fold={fold} {precision}", flush=True)
+        sol.profile(True)
+        sol.step(3)
+        sol.step(20)
+        sol.step(1)
+        torch.cuda.synchronize()
+        counts = [c for _, c in sol.profile_read().values()]
+        sol.profile(False)
+        rho, sink = sol.get_rho()
+        pops, trace, _ = sol.observe()
+        out[fold] = (rho, sink, trace, counts)
+    sol.close()
+    (a, sa, ta, ca), (b, sb, tb, cb) = out[True], out[False]
+    assert ca == [24, 24, 24, 0] and cb == [24, 24, 24, 24]
+    assert np.abs(a - b).max() < tol * np.abs(b).max()
+    assert abs(sa - sb) < TRACE_TOL[precision] and sa > 1e-6       # real sink
+    assert abs(ta - (1.0 - sa)) < TRACE_TOL[precision]
+    assert np.array_equal(a, a.conj().T)
+
+
 def test_state_roundtrip_and_zero_steps():
     wl = W.tch_2x2()
     sol = P.Solver(wl, "fp64")
