@@ -163,7 +163,9 @@ qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
 qme_status qme_state_layout(const qme_ctx *ctx, int64_t *n, int64_t *ld,
                             int64_t *elem_bytes, size_t *state_bytes);
 
-/* Device workspace qme_step needs (caller-allocated, 256-byte aligned). */
+/* Device workspace qme_step needs (caller-allocated, 256-byte aligned):
+ * four product planes of ld x ld elements and N FP64 values (the diagonal
+ * kept by folded steps, qme_set_fold). */
 qme_status qme_workspace_size(const qme_ctx *ctx, size_t *bytes);
 
 /* Write a state: rho (host, row-major n x n FP64 planes, converted to the
@@ -179,8 +181,12 @@ qme_status qme_get_state(const qme_ctx *ctx, const void *state_dev,
                          void *hip_stream);
 
 /* Advance the state by n_steps >= 0 time steps on hip_stream.  The state
- * buffer holds rho_{k+n} afterwards (never a pending scale).  Asynchronous;
- * the workspace must stay allocated until the stream reaches this point. */
+ * buffer holds rho_{k+n} afterwards (never a pending scale: folded steps
+ * apply their last renormalisation before the call's work ends).
+ * Asynchronous; the workspace must stay allocated until the stream reaches
+ * this point.  Between its own kernels the call may keep intermediate
+ * values in the state buffer, so the state must not be read by other work
+ * on other streams until the stream reaches this point. */
 qme_status qme_step(qme_ctx *ctx, void *state_dev, int64_t n_steps,
                     void *workspace_dev, void *hip_stream);
 

@@ -226,8 +226,9 @@ def test_tail_split_of_the_lower_product(precision, tol):
     assert abs(sa - sb) < 1e-12
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_folded_steps_match_unfolded(precision, tol):
+@pytest.mark.parametrize("precision,tol,tiles", [("fp64", 1e-12, None), ("fp32", 1e-5, None),
+                                                ("fp64", 1e-12, (64, 64))])
+def test_folded_steps_match_unfolded(precision, tol, tiles):
     """N = 2048 lattice (every decoherence operator leaves the basis, so the
     decoherence step is a factor per element): folded steps (decoherence in
     the lower product's epilogue, renormalisation in the next first product,
@@ -237,6 +238,8 @@ def test_folded_steps_match_unfolded(precision, tol):
     occ = P.basis(wl)
     rho0 = W.initial_rho(wl, occ)
     sol = P.Solver(wl, precision)
+    if tiles:
+        sol.set_tiles(*tiles)
     out = {}
     for fold in (True, False):
         sol.set_fold(fold)
