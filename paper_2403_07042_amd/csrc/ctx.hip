@@ -145,6 +145,8 @@ bool uses_small_path(const qme_ctx *c) {
 // onto another (no gather channels: the decoherence step is a factor per
 // element), in FP32 with 64-tiles for the lower product or in FP64.
 bool uses_fold(const qme_ctx *c) {
+  // BF16X3 keeps the separate decoherence pass: its lower product runs two
+  // workgroups per CU, too few to hide the folded epilogue (measured slower)
   if (!c->fold || c->jt.n_gather != 0) return false;
   if (c->precision == QME_FP32) return c->tile2 == 64;
   return c->precision == QME_FP64;
