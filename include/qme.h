@@ -373,6 +373,16 @@ qme_status qme_set_fused(qme_ctx *ctx, int32_t enable);
  * only.  enable: 0 or 1, else QME_E_ARG. */
 qme_status qme_set_fold(qme_ctx *ctx, int32_t enable);
 
+/* Tile body of the FP32 products whose second operand is read by rows (all
+ * products of qme_step and the first two of the adjoint step): mode 1 loads
+ * the operand tiles from HBM straight into LDS (no register staging), 0
+ * stages them through registers, -1 (default) takes the direct body for
+ * launches with fewer than four blocks per compute unit, where the few
+ * resident workgroups cannot hide the load latency by their number.  The two
+ * bodies accumulate every output in the same order: results are bitwise
+ * identical.  Other values: QME_E_ARG. */
+qme_status qme_set_direct_loads(qme_ctx *ctx, int32_t mode);
+
 /* Per-kernel timing of qme_step with HIP events recorded on the caller's
  * stream around every launch (the tracing facility used by the benchmark).
  * enable != 0 starts recording (and clears earlier records); 0 stops it. */

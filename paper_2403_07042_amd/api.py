@@ -250,6 +250,12 @@ class Solver:
         renormalisation in the next product) on (default) or off."""
         L.check(self.lib.qme_set_fold(self.ctx, int(bool(enable))))
 
+    def set_direct_loads(self, mode: int):
+        """FP32 product tile body: 1 direct HBM-to-LDS loads, 0 register
+        staging, -1 (default) direct for launches with fewer than four
+        blocks per compute unit.  Bitwise-neutral."""
+        L.check(self.lib.qme_set_direct_loads(self.ctx, int(mode)))
+
     def set_fused(self, enable: bool):
         """Single-workgroup path for N <= 32 (FP32 / FP64) on (default) or off."""
         L.check(self.lib.qme_set_fused(self.ctx, int(bool(enable))))

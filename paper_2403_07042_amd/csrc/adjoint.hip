@@ -477,6 +477,8 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
   ox.conj_b = true;
   ol.lower = true;    // lam = X + X dU          (dU^T = dU)
   og.b_rows = true;   // G += rho X
+  ox.direct = ol.direct = og.direct = c->direct;
+  ox.cus = ol.cus = og.cus = c->cus;
 
   for (int64_t g = L.nseg - 1; g >= 0; --g) {
     const int64_t len = std::min<int64_t>(L.seg, n_steps - g * L.seg);

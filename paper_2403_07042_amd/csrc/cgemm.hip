@@ -32,19 +32,27 @@
 
 namespace qme {
 
-template <int BM, int OPS, bool LOWER>
+// DIRECT: operands loaded straight into LDS (NT forms only).
+template <int BM, int OPS, bool LOWER, bool DIRECT = false>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
   __shared__ float smem[cgemm_f32_smem<BM, OPS>()];
+  static_assert(!DIRECT || !(OPS & kBRow), "direct loads serve the NT forms");
   int bi, bj;
   if (LOWER) {
     const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
     tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
-    cgemm_f32_tile<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke,
-                                  w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
+    float *part = w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM;
+    if constexpr (DIRECT)
+      cgemm_f32_tile_dma<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke, part);
+    else
+      cgemm_f32_tile<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke, part);
     return;
   }
   tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
-  cgemm_f32_tile<BM, OPS>(p, bi, bj, smem);
+  if constexpr (DIRECT)
+    cgemm_f32_tile_dma<BM, OPS>(p, bi, bj, smem);
+  else
+    cgemm_f32_tile<BM, OPS>(p, bi, bj, smem);
 }
 
 template <int BM, int OPS, bool LOWER>
@@ -236,10 +244,41 @@ static int ops_of(const GemmOps &o) {
   return (o.conj_a ? kConjA : 0) | (o.conj_b ? kConjB : 0) | (o.b_rows ? kBRow : 0);
 }
 
+template <int BM>
+static hipError_t cgemm_f32_direct_dispatch(const CgemmArgs<float> &a, int ops, bool lower,
+                                            hipStream_t s) {
+  switch (ops * 2 + (lower ? 1 : 0)) {
+    case 0: return launch(cgemm_f32_kernel<BM, 0, false, true>, a, BM, false, s);
+    case 1: return launch(cgemm_f32_kernel<BM, 0, true, true>, a, BM, true, s);
+    case 2: return launch(cgemm_f32_kernel<BM, 1, false, true>, a, BM, false, s);
+    case 3: return launch(cgemm_f32_kernel<BM, 1, true, true>, a, BM, true, s);
+    case 4: return launch(cgemm_f32_kernel<BM, 2, false, true>, a, BM, false, s);
+    case 5: return launch(cgemm_f32_kernel<BM, 2, true, true>, a, BM, true, s);
+    case 6: return launch(cgemm_f32_kernel<BM, 3, false, true>, a, BM, false, s);
+    case 7: return launch(cgemm_f32_kernel<BM, 3, true, true>, a, BM, true, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Whether a launch takes the direct-load tile body (see GemmOps::direct).
+static bool use_direct(const CgemmArgs<float> &a, int tile, const GemmOps &o) {
+  if (o.b_rows || o.direct == 0) return false;
+  if (o.direct > 0) return true;
+  const int64_t tiles = a.ld / tile;
+  int64_t blocks = o.lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
+  if (o.lower && a.split > 1) blocks = a.full + (blocks - a.full) * a.split;
+  return o.cus > 0 && blocks < 4 * int64_t(o.cus);
+}
+
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o, hipStream_t s) {
   if (a.ld % tile != 0) return hipErrorInvalidValue;
-  if (tile == 128) return cgemm_f32_kernel_dispatch<128>(a, ops_of(o), o.lower, s);
-  if (tile == 64) return cgemm_f32_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
+  const bool direct = use_direct(a, tile, o);
+  if (tile == 128)
+    return direct ? cgemm_f32_direct_dispatch<128>(a, ops_of(o), o.lower, s)
+                  : cgemm_f32_kernel_dispatch<128>(a, ops_of(o), o.lower, s);
+  if (tile == 64)
+    return direct ? cgemm_f32_direct_dispatch<64>(a, ops_of(o), o.lower, s)
+                  : cgemm_f32_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
   return hipErrorInvalidValue;
 }
 

@@ -196,6 +196,11 @@ __device__ __forceinline__ void fold_mirror(const CgemmArgs<T> &p, int bi, int b
 // register r: row 8*(r/4) + 4*(l/32) + r%4).
 
 
+// Slot of the k-chunks (4 floats) of LDS row r in the unpadded A / NT-B
+// layout of the direct-load tile (16 floats per row): chunk c sits at slot
+// c ^ dma_swz(r).
+__device__ __forceinline__ int dma_swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+
 // LDS elements a tile body needs (A and B tiles, double-buffered, re/im).
 template <int BM, int OPS>
 constexpr int cgemm_f32_smem() {
@@ -208,6 +213,81 @@ constexpr int cgemm_f64_smem() {
   constexpr int KT = 16, LDK = KT + 2, LDJ = BM + 2;
   constexpr int BSZ = (OPS & kBRow) ? KT * LDJ : BM * LDK;
   return 4 * BM * LDK + 4 * BSZ;
+}
+
+// Writes a finished FP32 tile: the raw accumulator into a split partial, or
+// C = alpha * acc + beta * X, or the folded decoherence step (the operand LDS
+// is free after the k loop's last barrier).
+template <int BM, int OPS, bool FOLD, int F, int WM>
+__device__ __forceinline__ void f32_tile_epilogue(const CgemmArgs<float> &p, int bi, int bj,
+                                                  float *smem, const floatx16 (&cr)[F][F],
+                                                  const floatx16 (&ci)[F][F], float *part) {
+  const int64_t ld = p.ld;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 31, h = lane >> 5;
+  if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
+#pragma unroll
+    for (int a = 0; a < F; ++a)
+#pragma unroll
+      for (int b = 0; b < F; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int o = (wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) * BM + wn * WM + b * 32 + li;
+          part[o] = cr[a][b][r];
+          part[BM * BM + o] = ci[a][b][r];
+        }
+    return;
+  }
+  // epilogue: C = alpha * acc + beta * X (or the folded decoherence step);
+  // the operand LDS is free after the k loop's last barrier
+  const bool has_x = p.beta != 0.0f;
+  // the tile staged for the mirror (2 BM (BM + 1) elements) and the factors
+  // d of its rows and columns (2 BM doubles) fit the operand LDS
+  constexpr bool kCanFold =
+      FOLD && 2 * BM * (BM + 1) * sizeof(float) + 2 * BM * sizeof(double) <=
+                  cgemm_f32_smem<BM, OPS>() * sizeof(float);
+  const bool fold = kCanFold && p.fold_d != nullptr;
+  float (*f_re)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem);
+  float (*f_im)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem + BM * (BM + 1));
+  double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
+  // the scale read once, before the stores (which could alias it)
+  const bool scaled = p.scale != nullptr;
+  const double sc = scaled ? *p.scale : 1.0;
+  if (fold) {
+    if (tid < 2 * BM) {
+      const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
+      f_d[tid] = u < p.fold_n ? p.fold_d[u] : 0.0;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < F; ++a) {
+#pragma unroll
+    for (int b = 0; b < F; ++b) {
+      const int cl = wn * WM + b * 32 + li;
+      const int64_t col = int64_t(bj) * BM + cl;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rl = wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int64_t row = int64_t(bi) * BM + rl;
+        const int64_t o = row * ld + col;
+        float vr, vi;
+        epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
+        if (fold) {
+          fold_elem<float, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
+        } else {
+          p.c_re[o] = vr;
+          p.c_im[o] = vi;
+        }
+      }
+    }
+  }
+  if (fold) {
+    __syncthreads();
+    fold_mirror<float, BM>(p, bi, bj, f_re, f_im);
+  }
 }
 
 // FOLD: the kernel may apply the folded decoherence epilogue (lower-triangle
@@ -352,67 +432,131 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
 #pragma unroll
     for (int b = 0; b < F; ++b) combine3<OPS>(p1[a][b], p2[a][b], p3[a][b], cr[a][b], ci[a][b]);
 
-  if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
+  f32_tile_epilogue<BM, OPS, FOLD, F, WM>(p, bi, bj, smem, cr, ci, part);
+}
+
+// NT forms with direct global -> LDS loads (global_load_lds_dwordx4: each
+// wave instruction writes 64 lanes x 16 bytes to one contiguous 1 KB of LDS,
+// lane L at base + 16 L).  A stage holds, per operand and plane, BM rows of
+// KT = 16 floats without padding; the k-chunk c (4 floats) of row r sits at
+// slot c ^ dma_swz(r), which puts the 8 (or 16) consecutive rows that one
+// 128-bit read phase serves on distinct 16-byte bank groups of a 32-bank (or
+// 64-bank) LDS; the swizzle is applied on the load side by choosing which
+// global chunk each lane fetches.  Per K tile a wave reads its fragments,
+// starts the loads of the next K tile into the other stage (its reads of that
+// stage ended before the last barrier), runs its products, waits for its
+// loads and meets the others at one barrier.  Each lane's fragments hold the same k values as in
+// cgemm_f32_tile, so the two bodies give bitwise-identical results.
+template <int BM, int OPS, bool FOLD = false>
+__device__ __forceinline__ void cgemm_f32_tile_dma(const CgemmArgs<float> &p, int bi, int bj,
+                                                   float *smem, int kb = 0, int ke = -1,
+                                                   float *part = nullptr) {
+  static_assert(!(OPS & kBRow), "direct loads serve the NT forms");
+  constexpr int KT = 16;
+  constexpr int WM = BM / 2;
+  constexpr int F = WM / 32;
+  constexpr int PLANE = BM * KT;                  // floats per operand plane per stage
+  constexpr int STAGE = 4 * PLANE;                // A re, A im, B re, B im
+  static_assert(2 * STAGE <= cgemm_f32_smem<BM, OPS>(), "stages exceed the LDS allocation");
+  typedef __attribute__((address_space(1))) void gvoid;
+  typedef __attribute__((address_space(3))) void lvoid;
+
+  const int64_t ld = p.ld;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 31, h = lane >> 5;
+
+  // this lane's load: row (16 per wave instruction, BM / 64 instructions per
+  // plane and wave) and the logical chunk that belongs at its slot
+  const int lrow = lane >> 2;
+  const int lchunk = (lane & 3) ^ dma_swz(lrow);     // rows come in aligned 16s
+  constexpr int PASS = BM / 64;                   // rows 16 * (4 * q + wave) + lrow, q < PASS
+  auto issue = [&](int st, int k0) {
+    float *base = smem + st * STAGE;
 #pragma unroll
-    for (int a = 0; a < F; ++a)
-#pragma unroll
-      for (int b = 0; b < F; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int o = (wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) * BM + wn * WM + b * 32 + li;
-          part[o] = cr[a][b][r];
-          part[BM * BM + o] = ci[a][b][r];
-        }
-    return;
-  }
-  // epilogue: C = alpha * acc + beta * X (or the folded decoherence step);
-  // the operand LDS is free after the k loop's last barrier
-  const bool has_x = p.beta != 0.0f;
-  // the tile staged for the mirror (2 BM (BM + 1) elements) and the factors
-  // d of its rows and columns (2 BM doubles) fit the operand LDS
-  constexpr bool kCanFold =
-      FOLD && 2 * BM * (BM + 1) * sizeof(float) + 2 * BM * sizeof(double) <=
-                  cgemm_f32_smem<BM, OPS>() * sizeof(float);
-  const bool fold = kCanFold && p.fold_d != nullptr;
-  float (*f_re)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem);
-  float (*f_im)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem + BM * (BM + 1));
-  double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
-  // the scale read once, before the stores (which could alias it)
-  const bool scaled = p.scale != nullptr;
-  const double sc = scaled ? *p.scale : 1.0;
-  if (fold) {
-    if (tid < 2 * BM) {
-      const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
-      f_d[tid] = u < p.fold_n ? p.fold_d[u] : 0.0;
+    for (int q = 0; q < PASS; ++q) {
+      const int r = 16 * (4 * q + wave) + lrow;
+      const int64_t ga = (int64_t(bi) * BM + r) * ld + k0 + 4 * lchunk;
+      const int64_t gb = (int64_t(bj) * BM + r) * ld + k0 + 4 * lchunk;
+      const int lo = 16 * (4 * q + wave) * KT;    // this wave's 1 KB block
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.a_re + ga), (lvoid *)(base + lo), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.a_im + ga), (lvoid *)(base + PLANE + lo), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.m_re + gb), (lvoid *)(base + 2 * PLANE + lo), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.m_im + gb), (lvoid *)(base + 3 * PLANE + lo), 16, 0, 0);
     }
-    __syncthreads();
-  }
+  };
+
+  floatx16 p1[F][F], p2[F][F], p3[F][F];
 #pragma unroll
-  for (int a = 0; a < F; ++a) {
+  for (int a = 0; a < F; ++a)
 #pragma unroll
-    for (int b = 0; b < F; ++b) {
-      const int cl = wn * WM + b * 32 + li;
-      const int64_t col = int64_t(bj) * BM + cl;
+    for (int b = 0; b < F; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int rl = wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const int64_t row = int64_t(bi) * BM + rl;
-        const int64_t o = row * ld + col;
-        float vr, vi;
-        epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
-        if (fold) {
-          fold_elem<float, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
-        } else {
-          p.c_re[o] = vr;
-          p.c_im[o] = vi;
-        }
+      for (int r = 0; r < 16; ++r) { p1[a][b][r] = 0.0f; p2[a][b][r] = 0.0f; p3[a][b][r] = 0.0f; }
+  auto mfma = [](float x, float y, floatx16 acc) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
+  };
+
+  const int nk = ke < 0 ? int(ld / KT) : ke;
+  issue(0, kb * KT);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int kt = kb; kt < nk; ++kt) {
+    const int st = (kt - kb) & 1;
+    const float *base = smem + st * STAGE;
+    float ar[F][8], ai[F][8], br[F][8], bi_[F][8];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const int ra_ = wm * WM + f * 32 + li, swa = dma_swz(ra_);
+      const int rb_ = wn * WM + f * 32 + li, swb = dma_swz(rb_);
+      const int a0 = ra_ * KT + 4 * ((2 * h) ^ swa), a1 = ra_ * KT + 4 * ((2 * h + 1) ^ swa);
+      const int b0 = rb_ * KT + 4 * ((2 * h) ^ swb), b1 = rb_ * KT + 4 * ((2 * h + 1) ^ swb);
+      const floatx4 x0 = *reinterpret_cast<const floatx4 *>(base + a0);
+      const floatx4 x1 = *reinterpret_cast<const floatx4 *>(base + a1);
+      const floatx4 y0 = *reinterpret_cast<const floatx4 *>(base + PLANE + a0);
+      const floatx4 y1 = *reinterpret_cast<const floatx4 *>(base + PLANE + a1);
+      const floatx4 z0 = *reinterpret_cast<const floatx4 *>(base + 2 * PLANE + b0);
+      const floatx4 z1 = *reinterpret_cast<const floatx4 *>(base + 2 * PLANE + b1);
+      const floatx4 w0 = *reinterpret_cast<const floatx4 *>(base + 3 * PLANE + b0);
+      const floatx4 w1 = *reinterpret_cast<const floatx4 *>(base + 3 * PLANE + b1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ar[f][e] = x0[e]; ar[f][e + 4] = x1[e];
+        ai[f][e] = y0[e]; ai[f][e + 4] = y1[e];
+        br[f][e] = z0[e]; br[f][e + 4] = z1[e];
+        bi_[f][e] = w0[e]; bi_[f][e + 4] = w1[e];
       }
     }
-  }
-  if (fold) {
+    if (kt + 1 < nk) issue(st ^ 1, (kt + 1) * KT);
+    float as_[F][8], bs_[F][8];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        as_[f][s] = opsum_a<OPS>(ar[f][s], ai[f][s]);
+        bs_[f][s] = opsum_b<OPS>(br[f][s], bi_[f][s]);
+      }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int a = 0; a < F; ++a)
+#pragma unroll
+        for (int b = 0; b < F; ++b)
+          cmac3(p1[a][b], p2[a][b], p3[a][b], ar[a][s], ai[a][s], as_[a][s], br[b][s], bi_[b][s],
+                bs_[b][s], mfma);
+    // keep the products ahead of the wait (the scheduler would hoist the
+    // barrier over them and expose the load latency)
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    fold_mirror<float, BM>(p, bi, bj, f_re, f_im);
   }
+  floatx16 cr[F][F], ci[F][F];
+#pragma unroll
+  for (int a = 0; a < F; ++a)
+#pragma unroll
+    for (int b = 0; b < F; ++b) combine3<OPS>(p1[a][b], p2[a][b], p3[a][b], cr[a][b], ci[a][b]);
+  f32_tile_epilogue<BM, OPS, FOLD, F, WM>(p, bi, bj, smem, cr, ci, part);
 }
 
 // ----------------------------------------------------------------- FP64

@@ -98,6 +98,8 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   GemmOps o1, o2;
   o1.conj_b = o2.conj_b = true;
   o2.lower = true;
+  o1.direct = o2.direct = c->direct;
+  o1.cus = o2.cus = c->cus;
   if (c->tail_split) {
     // chunk partials go to the output planes: dead until the decoherence pass
     const int kt = c->precision == QME_BF16X3 ? 32 : 16;
@@ -189,6 +191,8 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     GemmOps o1, o2;
     o1.conj_b = o2.conj_b = true;
     o2.lower = true;
+    o1.direct = o2.direct = c->direct;
+    o1.cus = o2.cus = c->cus;
     auto gemm = [&](const CgemmArgs<T> &g, int tile, const GemmOps &o) {
       if constexpr (sizeof(T) == 4) return launch_cgemm_f32(g, tile, o, s);
       else return launch_cgemm_f64(g, tile, o, s);
@@ -718,6 +722,14 @@ extern "C" qme_status qme_set_fold(qme_ctx *c, int32_t enable) {
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
   c->fold = enable != 0;
+  return QME_OK;
+}
+
+extern "C" qme_status qme_set_direct_loads(qme_ctx *c, int32_t mode) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (mode < -1 || mode > 1) { set_error("mode must be -1, 0 or 1"); return QME_E_ARG; }
+  c->direct = mode;
   return QME_OK;
 }
 

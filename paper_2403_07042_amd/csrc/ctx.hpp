@@ -22,6 +22,7 @@ struct qme_ctx {
   bool tail_split = true;             // qme_set_split
   bool fused = true;                  // qme_set_fused (single-workgroup path, n <= 32)
   bool fold = true;                   // qme_set_fold (decoherence folded into the products)
+  int direct = -1;                    // qme_set_direct_loads (-1 auto, 0 off, 1 on)
   int device = 0;
   int cus = 0;                        // compute units of the device
   // device tables (owned)

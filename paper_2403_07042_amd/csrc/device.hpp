@@ -12,8 +12,14 @@ namespace qme {
 // passed as m_re/m_im: with b_rows it is B itself (row-major [k][j]),
 // otherwise it is M with B = M^T (B[k][j] = M[j][k]).  conj_a / conj_b
 // conjugate A / B.  lower: only the tiles on or below the diagonal.
+// direct (FP32 forms with M given by rows only): 1 uses the tile body that
+// loads operands straight into LDS, 0 the register-staged one, -1 picks the
+// direct body when the launch has fewer blocks than 4 per compute unit
+// (`cus`), i.e. when resident workgroups cannot hide load latency by their
+// number.  Both bodies give bitwise-identical results.
 struct GemmOps {
   bool conj_a = false, conj_b = false, b_rows = false, lower = false;
+  int direct = 0, cus = 0;
 };
 
 // Tail split (lower-triangle launches only): when split > 1, tiles

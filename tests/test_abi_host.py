@@ -165,3 +165,10 @@ def test_select_states_errors():
     with pytest.raises(L.QmeError) as e:
         P.select_states(p, p, 0.1, 1e-3)         # nothing moves: every state removed
     assert "QME_E_STATE" in str(e.value)
+
+
+def test_knob_setters_reject_null_context():
+    lib = L.load()
+    for name, arg in (("qme_set_fold", 1), ("qme_set_split", 1), ("qme_set_fused", 1),
+                      ("qme_set_direct_loads", -1)):
+        assert getattr(lib, name)(None, arg) == L.QME_E_ARG, name
