@@ -385,7 +385,10 @@ qme_status qme_set_direct_loads(qme_ctx *ctx, int32_t mode);
 
 /* Per-kernel timing of qme_step with HIP events recorded on the caller's
  * stream around every launch (the tracing facility used by the benchmark).
- * enable != 0 starts recording (and clears earlier records); 0 stops it. */
+ * enable > 0 starts recording (and clears earlier records) on every
+ * enable-th step counted from this call (1: every step; a larger stride
+ * keeps the events' own cost out of the other steps); 0 stops it; negative:
+ * QME_E_ARG. */
 qme_status qme_profile_enable(qme_ctx *ctx, int32_t enable);
 
 /* Synchronises on the recorded events and returns, per kernel kind, the

@@ -263,7 +263,9 @@ class Solver:
     # ---------------------------------------------------------- profiling
     KINDS = ("product_full", "product_lower", "trace", "dissipate")
 
-    def profile(self, enable: bool = True):
+    def profile(self, enable=True):
+        """Per-kernel event timing: True / 1 on every step, an int k > 1 on
+        every k-th step, False / 0 off."""
         L.check(self.lib.qme_profile_enable(self.ctx, int(enable)))
 
     def profile_read(self):

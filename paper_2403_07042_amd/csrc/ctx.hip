@@ -66,9 +66,11 @@ qme_status check_device(const qme_ctx *c) {
 }
 
 // Records an event on s after a launch of `kind` (-1 marks the start of a
-// sequence) when profiling is on.
+// step) when profiling is on and the step is one of the sampled ones.
 static hipError_t mark(qme_ctx *c, hipStream_t s, int kind) {
   if (!c->profiling) return hipSuccess;
+  if (kind < 0) c->profile_this_step = c->profile_step++ % c->profile_every == 0;
+  if (!c->profile_this_step) return hipSuccess;
   if (c->events_used == c->events.size()) {
     hipEvent_t e;
     hipError_t err = hipEventCreate(&e);
@@ -770,7 +772,11 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
 extern "C" qme_status qme_profile_enable(qme_ctx *c, int32_t enable) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (enable < 0) { set_error("enable must be >= 0"); return QME_E_ARG; }
   c->profiling = enable != 0;
+  c->profile_every = enable > 0 ? enable : 1;
+  c->profile_step = 0;
+  c->profile_this_step = true;
   c->events_used = 0;
   return QME_OK;
 }

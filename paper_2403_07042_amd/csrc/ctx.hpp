@@ -56,6 +56,9 @@ struct qme_ctx {
 
   // per-kernel timing (qme_profile_enable / qme_profile_read)
   bool profiling = false;
+  int profile_every = 1;               // record every profile_every-th step
+  int64_t profile_step = 0;            // steps begun since enabling
+  bool profile_this_step = true;
   std::vector<void *> events;          // hipEvent_t pool
   size_t events_used = 0;
   std::vector<int> event_kind;         // kind of the launch ending at event i (-1: start)

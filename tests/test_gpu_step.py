@@ -304,3 +304,24 @@ def test_tch_chain3_n1728_against_stored_oracle_run(precision):
         assert np.abs(sample - ref).max() < tol
         assert abs(sink - rec["sink"]) < TRACE_TOL[precision]
         assert abs(trace - rec["trace"]) < TRACE_TOL[precision]
+
+
+def test_profile_sampling_stride():
+    """qme_profile_enable(k): events on every k-th step only, counted from
+    the enabling call across qme_step calls."""
+    wl = W.photon_lattice(16, 16)
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(W.initial_rho(wl, P.basis(wl)))
+    sol.profile(4)
+    sol.step(5)
+    sol.step(7)                     # steps 0, 4, 8 are sampled
+    counts = [c for _, c in sol.profile_read().values()]
+    assert counts[:3] == [3, 3, 3]
+    sol.profile(1)
+    sol.step(2)
+    counts = [c for _, c in sol.profile_read().values()]
+    assert counts[:3] == [2, 2, 2]
+    with pytest.raises(Exception):
+        sol.profile(-1)
+    sol.profile(False)
+    sol.close()
