@@ -687,6 +687,14 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
   o.conj_b = conj_b != 0;
   o.b_rows = b_rows != 0;
   o.lower = lower != 0;
+  {   // tile body chosen by launch size, as in the steps
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      o.direct = -1;
+      o.cus = cus;
+    }
+  }
   if (precision == QME_FP32) {
     if (tile != 128 && tile != 64) { set_error("FP32 tile must be 128 or 64"); return QME_E_ARG; }
     CgemmArgs<float> g{static_cast<const float *>(a_re), static_cast<const float *>(a_im),
