@@ -50,7 +50,8 @@ __device__ __forceinline__ floatx16 mac3(const bf16x8 *x, const bf16x8 *y, float
 
 // One workgroup per 64 x 64 output tile, 4 waves (2 x 2), each a 32 x 32
 // block.  K tile 32 (two MFMA k-steps of 16).  LDS holds six bf16 planes
-// (re/im x hi/mid/lo) per operand, single-buffered; the next K tile is
+// (re/im x hi/mid/lo) per operand, single-buffered, rows unpadded with the
+// k-chunks swizzled (48 KB: three workgroups per CU); the next K tile is
 // prefetched into registers during the products.
 // v_mfma_f32_32x32x16_bf16: A 32x16 (lane l: row l%32, k 8*(l/32)..+7),
 // B 16x32 (lane l: k 8*(l/32)..+7, col l%32), D as for the FP32 32x32 MFMA.
@@ -60,7 +61,9 @@ template <bool CONJA, bool CONJB, bool LOWER, int PRE>
 __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float> p) {
   constexpr int BM = 64;
   constexpr int KT = 32;
-  constexpr int LDK = KT + 8;   // padded LDS row (bf16)
+  // LDS row (bf16): four 16-byte k-chunks, chunk c of row r at slot c ^ dma_swz(r)
+  constexpr int LDK = KT;
+  auto slot = [](int row, int c) { return 8 * (c ^ dma_swz(row)); };
   __shared__ __bf16 sA[6][BM * LDK];
   __shared__ __bf16 sB[6][BM * LDK];
 
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
 #pragma unroll
       for (int pl = 0; pl < 6; ++pl) {
         __bf16 *base = PRE == 1 ? &sA[pl][0] : &sB[pl][0];
-        *reinterpret_cast<bf16x8 *>(base + pr * LDK + pk) = preg[pl];
+        *reinterpret_cast<bf16x8 *>(base + pr * LDK + slot(pr, pk >> 3)) = preg[pl];
       }
     }
 #pragma unroll
@@ -137,7 +140,8 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
           split3(reg[o][q][e], a, b, c);
           vh[e] = a; vm[e] = b; vl[e] = c;
         }
-        const int off = (q * 32 + lr) * LDK + lk;
+        const int row = q * 32 + lr;
+        const int off = row * LDK + slot(row, lk >> 3) + (lk & 7);
         *reinterpret_cast<bf16x4 *>(base + 0 * BM * LDK + off) = vh;
         *reinterpret_cast<bf16x4 *>(base + 1 * BM * LDK + off) = vm;
         *reinterpret_cast<bf16x4 *>(base + 2 * BM * LDK + off) = vl;
@@ -158,8 +162,9 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       bf16x8 ar[3], ai[3], br[3], bim[3];
-      const int oa = (wm * 32 + li) * LDK + s * 16 + h * 8;
-      const int ob = (wn * 32 + li) * LDK + s * 16 + h * 8;
+      const int ra_ = wm * 32 + li, rb_ = wn * 32 + li;
+      const int oa = ra_ * LDK + slot(ra_, 2 * s + h);
+      const int ob = rb_ * LDK + slot(rb_, 2 * s + h);
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         ar[t] = *reinterpret_cast<const bf16x8 *>(&sA[t][oa]);
@@ -180,6 +185,9 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
       ci = mac3(t1, br, ci);
       cr = mac3(t2, bim, cr);
       ci = mac3(t3, bim, ci);
+      // one k-step's fragments live at a time (hoisting the next step's
+      // reads over these products costs 44 registers and a wave per SIMD)
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 
