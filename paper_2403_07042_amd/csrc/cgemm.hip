@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
 }
 
 template <int BM, int OPS, bool LOWER>
-__global__ __launch_bounds__(kThreads) void cgemm_f64_kernel(CgemmArgs<double> p) {
+__global__ __launch_bounds__(kThreads, BM == 32 ? 5 : 1) void cgemm_f64_kernel(CgemmArgs<double> p) {
   __shared__ double smem[cgemm_f64_smem<BM, OPS>()];
   int bi, bj;
   if (LOWER) {
@@ -270,8 +270,23 @@ static bool use_direct(const CgemmArgs<float> &a, int tile, const GemmOps &o) {
   return o.cus > 0 && blocks < 4 * int64_t(o.cus);
 }
 
+// Whether a tile's LDS holds the folded epilogue's staging (the condition
+// the tile bodies test as kCanFold); a fold request elsewhere is an error,
+// never a silent unfolded product.
+template <int BM>
+constexpr bool f32_folds() {
+  return 2 * BM * (BM + 1) * sizeof(float) + 2 * BM * sizeof(double) <=
+         cgemm_f32_smem<BM, kConjB>() * sizeof(float);
+}
+template <int BM>
+constexpr bool f64_folds() {
+  return 2 * BM * (BM + 1) + 2 * BM <= cgemm_f64_smem<BM, kConjB>();
+}
+
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o, hipStream_t s) {
   if (a.ld % tile != 0) return hipErrorInvalidValue;
+  if (a.fold_d && (!o.lower || o.b_rows || !(tile == 64 ? f32_folds<64>() : f32_folds<128>())))
+    return hipErrorInvalidValue;
   const bool direct = use_direct(a, tile, o);
   if (tile == 128)
     return direct ? cgemm_f32_direct_dispatch<128>(a, ops_of(o), o.lower, s)
@@ -284,6 +299,8 @@ hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &
 
 hipError_t launch_cgemm_f64(const CgemmArgs<double> &a, int tile, const GemmOps &o, hipStream_t s) {
   if (a.ld % tile != 0) return hipErrorInvalidValue;
+  if (a.fold_d && (!o.lower || o.b_rows || !(tile == 64 ? f64_folds<64>() : f64_folds<32>())))
+    return hipErrorInvalidValue;
   if (tile == 64) return cgemm_f64_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
   if (tile == 32) return cgemm_f64_kernel_dispatch<32>(a, ops_of(o), o.lower, s);
   return hipErrorInvalidValue;

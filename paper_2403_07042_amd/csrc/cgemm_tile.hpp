@@ -201,6 +201,11 @@ __device__ __forceinline__ void fold_mirror(const CgemmArgs<T> &p, int bi, int b
 // c ^ dma_swz(r).
 __device__ __forceinline__ int dma_swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
 
+// The FP64 tiles' rows of 16 doubles (eight 16-byte chunks): chunk c of row
+// r at slot c ^ f64_swz(r), distinct bank groups for the 8 (or 16)
+// consecutive rows one 128-bit read phase serves on a 32- (or 64-) bank LDS.
+__device__ __forceinline__ int f64_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
 // LDS elements a tile body needs (A and B tiles, double-buffered, re/im).
 template <int BM, int OPS>
 constexpr int cgemm_f32_smem() {
@@ -208,11 +213,14 @@ constexpr int cgemm_f32_smem() {
   constexpr int BSZ = (OPS & kBRow) ? KT * LDJ : BM * LDK;
   return 4 * BM * LDK + 4 * BSZ;
 }
+// (at least the folded epilogue's staging: the tile, BM + 1 per row, and
+// the row and column factors)
 template <int BM, int OPS>
 constexpr int cgemm_f64_smem() {
-  constexpr int KT = 16, LDK = KT + 2, LDJ = BM + 2;
+  constexpr int KT = 16, LDK = KT, LDJ = BM + 2;
   constexpr int BSZ = (OPS & kBRow) ? KT * LDJ : BM * LDK;
-  return 4 * BM * LDK + 4 * BSZ;
+  constexpr int stages = 4 * BM * LDK + 4 * BSZ, fold = 2 * BM * (BM + 1) + 2 * BM;
+  return stages > fold ? stages : fold;
 }
 
 // Writes a finished FP32 tile: the raw accumulator into a split partial, or
@@ -569,7 +577,7 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
                                                int kb = 0, int ke = -1, double *part = nullptr) {
   constexpr bool BROW = OPS & kBRow;
   constexpr int KT = 16;
-  constexpr int LDK = KT + 2;          // padded LDS row (doubles)
+  constexpr int LDK = KT;              // LDS row of A / NT-B (doubles), 16-byte chunks swizzled
   constexpr int LDJ = BM + 2;
   constexpr int WM = BM / 2;
   constexpr int F = WM / 16;           // 16x16 blocks per wave side
@@ -613,14 +621,14 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
   auto lstore = [&](int st) {
 #pragma unroll
     for (int q = 0; q < PASSES; ++q) {
-      const int o = (q * 32 + lr) * LDK + lk;
+      const int o = (q * 32 + lr) * LDK + 2 * ((lk >> 1) ^ f64_swz(q * 32 + lr));
       *reinterpret_cast<doublex2 *>(&sA[st][0][o]) = ra[q][0];
       *reinterpret_cast<doublex2 *>(&sA[st][1][o]) = ra[q][1];
     }
 #pragma unroll
     for (int q = 0; q < BPASS; ++q) {
       const int o = BROW ? (br_k + q * (kThreads / (BM / 2))) * LDJ + br_j
-                         : (q * 32 + lr) * LDK + lk;
+                         : (q * 32 + lr) * LDK + 2 * ((lk >> 1) ^ f64_swz(q * 32 + lr));
       *reinterpret_cast<doublex2 *>(&sB[st][0][o]) = rb[q][0];
       *reinterpret_cast<doublex2 *>(&sB[st][1][o]) = rb[q][1];
     }
@@ -645,49 +653,53 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
   for (int kt = kb; kt < nk; ++kt) {
     const int st = (kt - kb) & 1;
     if (kt + 1 < nk) gload((kt + 1) * KT);
-    double ar[F][4], ai[F][4], br[F][4], bi_[F][4];
+    // two halves of the K tile (k-steps 0-1, then 2-3), one half's
+    // fragments live at a time
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const int oa = (wm * WM + f * 16 + li) * LDK + h * 4;
-      doublex2 x0 = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa]);
-      doublex2 x1 = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa + 2]);
-      doublex2 y0 = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa]);
-      doublex2 y1 = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa + 2]);
-      ar[f][0] = x0[0]; ar[f][1] = x0[1]; ar[f][2] = x1[0]; ar[f][3] = x1[1];
-      ai[f][0] = y0[0]; ai[f][1] = y0[1]; ai[f][2] = y1[0]; ai[f][3] = y1[1];
-      if constexpr (BROW) {
-        const int col = wn * WM + f * 16 + li;
+    for (int hf = 0; hf < 2; ++hf) {
+      double ar[F][2], ai[F][2], br[F][2], bi_[F][2];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          br[f][s] = sB[st][0][(h * 4 + s) * LDJ + col];
-          bi_[f][s] = sB[st][1][(h * 4 + s) * LDJ + col];
+      for (int f = 0; f < F; ++f) {
+        const int ra_ = wm * WM + f * 16 + li;
+        const int oa = ra_ * LDK + 2 * ((2 * h + hf) ^ f64_swz(ra_));
+        const doublex2 x = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa]);
+        const doublex2 y = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa]);
+        ar[f][0] = x[0]; ar[f][1] = x[1];
+        ai[f][0] = y[0]; ai[f][1] = y[1];
+        if constexpr (BROW) {
+          const int col = wn * WM + f * 16 + li;
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            br[f][e] = sB[st][0][(h * 4 + 2 * hf + e) * LDJ + col];
+            bi_[f][e] = sB[st][1][(h * 4 + 2 * hf + e) * LDJ + col];
+          }
+        } else {
+          const int rb_ = wn * WM + f * 16 + li;
+          const int om = rb_ * LDK + 2 * ((2 * h + hf) ^ f64_swz(rb_));
+          const doublex2 z = *reinterpret_cast<const doublex2 *>(&sB[st][0][om]);
+          const doublex2 w = *reinterpret_cast<const doublex2 *>(&sB[st][1][om]);
+          br[f][0] = z[0]; br[f][1] = z[1];
+          bi_[f][0] = w[0]; bi_[f][1] = w[1];
         }
-      } else {
-        const int om = (wn * WM + f * 16 + li) * LDK + h * 4;
-        doublex2 z0 = *reinterpret_cast<const doublex2 *>(&sB[st][0][om]);
-        doublex2 z1 = *reinterpret_cast<const doublex2 *>(&sB[st][0][om + 2]);
-        doublex2 w0 = *reinterpret_cast<const doublex2 *>(&sB[st][1][om]);
-        doublex2 w1 = *reinterpret_cast<const doublex2 *>(&sB[st][1][om + 2]);
-        br[f][0] = z0[0]; br[f][1] = z0[1]; br[f][2] = z1[0]; br[f][3] = z1[1];
-        bi_[f][0] = w0[0]; bi_[f][1] = w0[1]; bi_[f][2] = w1[0]; bi_[f][3] = w1[1];
       }
+      double as_[F][2], bs_[F][2];
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          as_[f][e] = opsum_a<OPS>(ar[f][e], ai[f][e]);
+          bs_[f][e] = opsum_b<OPS>(br[f][e], bi_[f][e]);
+        }
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+          for (int b = 0; b < F; ++b)
+            cmac3(p1[a][b], p2[a][b], p3[a][b], ar[a][e], ai[a][e], as_[a][e], br[b][e], bi_[b][e],
+                  bs_[b][e], mfma);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    double as_[F][4], bs_[F][4];
-#pragma unroll
-    for (int f = 0; f < F; ++f)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        as_[f][s] = opsum_a<OPS>(ar[f][s], ai[f][s]);
-        bs_[f][s] = opsum_b<OPS>(br[f][s], bi_[f][s]);
-      }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int a = 0; a < F; ++a)
-#pragma unroll
-        for (int b = 0; b < F; ++b)
-          cmac3(p1[a][b], p2[a][b], p3[a][b], ar[a][s], ai[a][s], as_[a][s], br[b][s], bi_[b][s],
-                bs_[b][s], mfma);
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
