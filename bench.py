@@ -36,8 +36,8 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": 378416.7 * 1024,
-                        "sha256": "dcc855c3dc1932d7261bb8eee76b9acfc337a15abe676b8fa13b7353df038a0b",
+TRAFFIC_FP32_PRODUCT = {"bytes": 378736.3 * 1024,
+                        "sha256": "74c7256264d8a38824af04914f096b8504a0a9496a9ffbbe21571d66f27a29dd",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
 KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 
