@@ -20,12 +20,20 @@
 //     NN-B) with 16-byte global loads, staged through double-buffered LDS;
 //   * for A and NT-B the k index inside a K tile is permuted per lane group
 //     so each lane fetches its k values with two ds_read_b128;
+//   * FP32 has two tile bodies with the same arithmetic: loads staged
+//     through registers into padded LDS rows, or loaded straight into
+//     swizzled LDS rows (global_load_lds); launches with fewer blocks than
+//     four per CU take the second (GemmOps::direct);
+//   * FP64 rows are swizzled, unpadded, and each K tile's fragments are
+//     read in two halves, which fits five waves per SIMD at 32-tiles;
 //   * a complex multiply-add is three real MFMA products (Gauss's 3M form:
 //     Ar Br, Ai Bi and (Ar + sA Ai)(Br + sB Bi), combined after the k loop),
 //     25 % fewer matrix-core operations than the four-product form; the
 //     conjugations fold into the operand sums and the final combination;
 //   * LOWER launches only the tiles on or below the diagonal (Hermitian
-//     output), enumerated triangularly.
+//     output), in an XCD-aware order, with the tiles past the last full
+//     wave of CUs cut along k (tail split) and, for folded steps, the
+//     decoherence factor applied in the epilogue (CgemmArgs::fold_d).
 #include "cgemm_tile.hpp"
 
 #include <algorithm>

@@ -48,8 +48,8 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
   // c_j[u]^2 Z[pi_j u, pi_j u] regrouped by the state w = pi_j u they read
   double tr = 0.0, lost = 0.0, rot = 0.0;
   // u = threadIdx.x + k NT in increasing k; the loads of G values of k are
-  // issued together, the sums keep that order
-  constexpr int G = 4;
+  // issued together (one batch at N = 2048), the sums keep that order
+  constexpr int G = 8;
   for (int64_t u0 = threadIdx.x; u0 < p.n; u0 += int64_t(G) * NT) {
     double z[G], wk[G], lk[G];
 #pragma unroll
@@ -67,26 +67,33 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
       rot += z[gi];
     }
   }
-  s_tr[threadIdx.x] = tr;
-  s_lost[threadIdx.x] = lost;
-  s_rot[threadIdx.x] = rot;
-  __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) {
-      s_tr[threadIdx.x] += s_tr[threadIdx.x + w];
-      s_lost[threadIdx.x] += s_lost[threadIdx.x + w];
-      s_rot[threadIdx.x] += s_rot[threadIdx.x + w];
-    }
-    __syncthreads();
+  // wave sums by butterfly (every lane ends with the same value), then the
+  // NT / 64 wave sums in wave order
+  for (int off = 32; off > 0; off >>= 1) {
+    tr += __shfl_xor(tr, off);
+    lost += __shfl_xor(lost, off);
+    rot += __shfl_xor(rot, off);
   }
+  if ((threadIdx.x & 63) == 0) {
+    s_tr[threadIdx.x >> 6] = tr;
+    s_lost[threadIdx.x >> 6] = lost;
+    s_rot[threadIdx.x >> 6] = rot;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double sink = p.aux_in[0] + p.dt * s_lost[0];
+    double t = s_tr[0], l = s_lost[0], r = s_rot[0];
+    for (int w = 1; w < NT / 64; ++w) {
+      t += s_tr[w];
+      l += s_lost[w];
+      r += s_rot[w];
+    }
+    const double sink = p.aux_in[0] + p.dt * l;
     const double steps = p.aux_in[3] + 1.0;
     p.aux_out[0] = sink;
-    p.aux_out[1] = s_rot[0];
-    p.aux_out[2] = s_lost[0];
+    p.aux_out[1] = r;
+    p.aux_out[2] = l;
     p.aux_out[3] = steps;
-    p.aux_out[4] = (1.0 - sink) / s_tr[0];
+    p.aux_out[4] = (1.0 - sink) / t;
   }
 }
 
