@@ -336,22 +336,41 @@ def cpu_baseline(W, wl, gpu_leg, steps):
     populations with the lattice's closed form."""
     from oracle import closed_forms as cf
     from oracle import evolve as ev
+    blas = "unknown"
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        info = [p for p in threadpool_info() if p.get("user_api") == "blas"] or threadpool_info()
+        threads = max([p.get("num_threads", 1) for p in info] or [1])
+        if info:
+            blas = f"{info[0].get('internal_api', '?')} {info[0].get('version', '')}".strip()
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+    except Exception:
+        pass
     s = ev.System(wl)
-    rho = W.initial_rho(wl, s.occ)
-    t0 = time.perf_counter()
-    sink = 0.0
-    for _ in range(steps):
-        rho, sink = ev.step(rho, sink, s.u, s.jumps, s.dt)
-    t1 = time.perf_counter()
-    base = {"value": steps / (t1 - t0), "unit": "steps/s", "cores": int(threads),
+    rho0 = W.initial_rho(wl, s.occ)
+
+    def run(k):
+        rho, sink = rho0, 0.0
+        t0 = time.perf_counter()
+        for _ in range(k):
+            rho, sink = ev.step(rho, sink, s.u, s.jumps, s.dt)
+        return k / (time.perf_counter() - t0)
+
+    rate = run(steps)
+    base = {"value": rate, "unit": "steps/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{steps} time steps of the N=2048 lattice workload (NumPy complex128, "
-                      f"BLAS threads={threads}); propagator build excluded"}
+                      f"BLAS threads={threads}); propagator build excluded",
+            "host": {"cpu_model": cpu_model, "nproc": os.cpu_count(), "blas": blas}}
+    if threadpool_limits is not None and steps > 0:
+        with threadpool_limits(limits=1, user_api="blas"):
+            base["single_thread"] = {"value": run(1), "unit": "steps/s", "steps": 1}
     parity = None
     if gpu_leg is not None:
         k = gpu_leg["k"]
