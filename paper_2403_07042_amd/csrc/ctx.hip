@@ -113,9 +113,10 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   hipError_t e = mark(c, s, -1);
   if constexpr (sizeof(T) == 4) {
     if (c->precision == QME_BF16X3) {
-      // dU pre-split for the first product; the lower product splits its
-      // dU tiles while staging them (measured faster there at N = 2048)
+      // dU pre-split (six bf16 planes, split once per context) for both
+      // products: the first reads it as A, the lower-triangle one as M
       g1.a_split = c->du_split;
+      g2.m_split = c->du_split;
       if (e == hipSuccess) e = launch_cgemm_bf16x3(g1, o1, s);
       if (e == hipSuccess) e = mark(c, s, 0);
       if (e == hipSuccess) e = launch_cgemm_bf16x3(g2, o2, s);
