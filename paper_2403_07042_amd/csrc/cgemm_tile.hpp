@@ -453,8 +453,9 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
 // global chunk each lane fetches.  Per K tile a wave reads its fragments,
 // starts the loads of the next K tile into the other stage (its reads of that
 // stage ended before the last barrier), runs its products, waits for its
-// loads and meets the others at one barrier.  Each lane's fragments hold the same k values as in
-// cgemm_f32_tile, so the two bodies give bitwise-identical results.
+// loads and meets the others at one barrier.  Each lane's fragments hold the
+// same k values as in cgemm_f32_tile, so the two bodies give bitwise-identical
+// results.
 template <int BM, int OPS, bool FOLD = false>
 __device__ __forceinline__ void cgemm_f32_tile_dma(const CgemmArgs<float> &p, int bi, int bj,
                                                    float *smem, int kb = 0, int ke = -1,
