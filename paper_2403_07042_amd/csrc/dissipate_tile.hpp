@@ -23,7 +23,7 @@
 
 namespace qme {
 
-static constexpr int TD = 64;          // tile edge of the decoherence pass
+static constexpr int TD = 32;          // tile edge of the decoherence pass
 static constexpr int kDissThreads = 256;
 
 template <typename T>
@@ -137,48 +137,85 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
 
   double dv = 0.0;
   if (v < p.n) dv = p.d[v];
-  for (int rr = r0; rr < TD; rr += kDissThreads / TD) {
-    const int64_t u = int64_t(bi) * TD + rr;
-    if (u >= p.n || v >= p.n || (diag_tile && v > u)) continue;
-    const int64_t o = u * p.ld + v;
-    const double zr = double(p.z_re[o]), zi = double(p.z_im[o]);
-    const double f = 1.0 - 0.5 * dt * (p.d[u] + dv);
-    double xr = f * zr, xi = f * zi;
-    for (int j = 0; j < p.n_gather; ++j) {
-      int32_t pu, pv;
-      double cu, cv;
-      if (staged) {
-        pu = g->pu[j][rr];
-        pv = g->pv[j][c];
-        cu = g->cu[j][rr];
-        cv = g->cv[j][c];
-      } else {
-        pu = p.pi[int64_t(j) * p.n + u];
-        pv = p.pi[int64_t(j) * p.n + v];
-        cu = p.cg[int64_t(j) * p.n + u];
-        cv = p.cg[int64_t(j) * p.n + v];
+  // G of this thread's rows at a time (rows r0 + kRows * i): all their loads
+  // (the element, its row's rate, then each channel's gathered elements) are
+  // issued before any of them is used, so a thread keeps G requests in
+  // flight; each element's arithmetic is unchanged.
+  constexpr int kRows = kDissThreads / TD;
+  constexpr int G = 4;
+  for (int rb = r0; rb < TD; rb += kRows * G) {
+    bool ok[G];
+    double xr[G], xi[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int rr = rb + q * kRows;
+      const int64_t u = int64_t(bi) * TD + rr;
+      ok[q] = rr < TD && u < p.n && v < p.n && !(diag_tile && v > u);
+      double zr = 0.0, zi = 0.0, du = 0.0;
+      if (ok[q]) {
+        const int64_t o = u * p.ld + v;
+        zr = double(p.z_re[o]);
+        zi = double(p.z_im[o]);
+        du = p.d[u];
       }
-      if (pu >= 0 && pv >= 0) {
-        const double w = dt * cu * cv;
-        double gr, gi;
-        zlower(p, pu, pv, gr, gi);
-        xr += w * gr;
-        xi += w * gi;
+      const double f = 1.0 - 0.5 * dt * (du + dv);
+      xr[q] = f * zr;
+      xi[q] = f * zi;
+    }
+    for (int j = 0; j < p.n_gather; ++j) {
+      double gr[G], gi[G], w[G];
+      bool use[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int rr = rb + q * kRows;
+        const int64_t u = int64_t(bi) * TD + rr;
+        int32_t pu = -1, pv = -1;
+        double cu = 0.0, cv = 0.0;
+        if (ok[q]) {
+          if (staged) {
+            pu = g->pu[j][rr];
+            pv = g->pv[j][c];
+            cu = g->cu[j][rr];
+            cv = g->cv[j][c];
+          } else {
+            pu = p.pi[int64_t(j) * p.n + u];
+            pv = p.pi[int64_t(j) * p.n + v];
+            cu = p.cg[int64_t(j) * p.n + u];
+            cv = p.cg[int64_t(j) * p.n + v];
+          }
+        }
+        use[q] = pu >= 0 && pv >= 0;
+        w[q] = dt * cu * cv;
+        gr[q] = gi[q] = 0.0;
+        if (use[q]) zlower(p, pu, pv, gr[q], gi[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        if (use[q]) {
+          xr[q] += w[q] * gr[q];
+          xi[q] += w[q] * gi[q];
+        }
       }
     }
-    xr *= scale;
-    xi *= scale;
-    if (u == v) xi = 0.0;
-    p.x_re[o] = T(xr);
-    p.x_im[o] = T(xi);
-    if (diag_tile) {
-      if (u != v) {
-        p.x_re[v * p.ld + u] = T(xr);
-        p.x_im[v * p.ld + u] = T(-xi);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      if (!ok[q]) continue;
+      const int rr = rb + q * kRows;
+      const int64_t u = int64_t(bi) * TD + rr;
+      const int64_t o = u * p.ld + v;
+      double yr = xr[q] * scale, yi = xi[q] * scale;
+      if (u == v) yi = 0.0;
+      p.x_re[o] = T(yr);
+      p.x_im[o] = T(yi);
+      if (diag_tile) {
+        if (u != v) {
+          p.x_re[v * p.ld + u] = T(yr);
+          p.x_im[v * p.ld + u] = T(-yi);
+        }
+      } else {
+        s_re[rr][c] = T(yr);
+        s_im[rr][c] = T(yi);
       }
-    } else {
-      s_re[rr][c] = T(xr);
-      s_im[rr][c] = T(xi);
     }
   }
   if (diag_tile) return;
