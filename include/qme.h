@@ -164,8 +164,11 @@ qme_status qme_state_layout(const qme_ctx *ctx, int64_t *n, int64_t *ld,
                             int64_t *elem_bytes, size_t *state_bytes);
 
 /* Device workspace qme_step needs (caller-allocated, 256-byte aligned):
- * four product planes of ld x ld elements and N FP64 values (the diagonal
- * kept by folded steps, qme_set_fold). */
+ * four product planes of ld x ld elements, N FP64 values (the diagonal kept
+ * by folded steps, qme_set_fold) and, for FP32 and FP64 contexts whose
+ * products are too small to occupy the device, the partial slots of their
+ * k-split (qme_set_split; at most 12 planes, sized for every tile edge
+ * qme_set_tiles accepts). */
 qme_status qme_workspace_size(const qme_ctx *ctx, size_t *bytes);
 
 /* Write a state: rho (host, row-major n x n FP64 planes, converted to the
@@ -338,13 +341,16 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
  * leading dimension ld (qme_state_layout), else QME_E_ARG. */
 qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
 
-/* Tail split of the lower-triangle product (on by default).  When that
- * product's tile count exceeds a multiple of the device's compute-unit count
- * by a small remainder, the remainder tiles are computed in k-chunks that
- * fill the otherwise idle units, and a reduce pass sums each tile's chunks in
- * k order.  The chunk partials live in the output state's planes, which the
- * step overwrites afterwards, so no memory is added.  Results differ from the
- * unsplit product only by FP rounding (the k sum is regrouped) and are
+/* Split of the products along k (on by default).  Tail split: when the
+ * lower-triangle product's tile count exceeds a multiple of the device's
+ * compute-unit count by a small remainder, the remainder tiles are computed
+ * in k-chunks that fill the otherwise idle units, their partials in the
+ * output state's planes, which the step overwrites afterwards.  Small-launch
+ * split (FP32 and FP64 contexts): a product with at most half as many tiles
+ * as compute units has every tile computed in k-chunks of at least two K
+ * tiles, their partials in the workspace's slots (qme_workspace_size).  A
+ * reduce pass sums each tile's chunks in k order.  Results differ from the
+ * unsplit products only by FP rounding (the k sum is regrouped) and are
  * deterministic for a given (ld, tile, device).  enable: 0 or 1, else
  * QME_E_ARG. */
 qme_status qme_set_split(qme_ctx *ctx, int32_t enable);

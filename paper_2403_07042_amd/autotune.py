@@ -1,7 +1,8 @@
 """Autotuner for the solver's launch knobs, with a JSON cache.
 
 Knobs: the tile edges of the two products of a step (qme_set_tiles) and the
-tail split of the lower-triangle product (qme_set_split) for a single
+k-splits of the products (qme_set_split: the tail of the lower-triangle
+product, every tile of a launch too small for the device) for a single
 instance, and graph replay / instance order for a batch.  Every
 candidate is timed on the real step (median of several trials of a few steps,
 on a scratch copy of the state so the caller's state does not advance) and
@@ -10,7 +11,7 @@ precision, N, ld) in $QME_TUNE_CACHE (default ~/.cache/qme_mi355x/tune.json).
 
 With the split off, tile choice never changes results: every tile size
 accumulates each output element over k in the same order, so the products are
-bitwise identical.  A tail split regroups the k sum of the split tiles (FP
+bitwise identical.  A split regroups the k sum of the split tiles (FP
 rounding only, deterministic for a given configuration).
 """
 from __future__ import annotations

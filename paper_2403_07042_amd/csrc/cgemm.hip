@@ -45,43 +45,31 @@ template <int BM, int OPS, bool LOWER, bool DIRECT = false>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
   __shared__ float smem[cgemm_f32_smem<BM, OPS>()];
   static_assert(!DIRECT || !(OPS & kBRow), "direct loads serve the NT forms");
+  // whole tile, or (split launches) one k-chunk of a tile into its partial slot
+  const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
   int bi, bj;
-  if (LOWER) {
-    const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
-    tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
-    float *part = w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM;
-    if constexpr (DIRECT)
-      cgemm_f32_tile_dma<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke, part);
-    else
-      cgemm_f32_tile<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke, part);
-    return;
-  }
-  tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
+  tile_coords(w.tile, int(p.ld / BM), LOWER, bi, bj);
+  float *part = w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM;
   if constexpr (DIRECT)
-    cgemm_f32_tile_dma<BM, OPS>(p, bi, bj, smem);
+    cgemm_f32_tile_dma<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
   else
-    cgemm_f32_tile<BM, OPS>(p, bi, bj, smem);
+    cgemm_f32_tile<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
 }
 
 template <int BM, int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads, BM == 32 ? 5 : 1) void cgemm_f64_kernel(CgemmArgs<double> p) {
   __shared__ double smem[cgemm_f64_smem<BM, OPS>()];
+  const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
   int bi, bj;
-  if (LOWER) {
-    const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
-    tile_coords(w.tile, int(p.ld / BM), true, bi, bj);
-    cgemm_f64_tile<BM, OPS, true>(p, bi, bj, smem, w.kb, w.ke,
-                                  w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
-    return;
-  }
-  tile_coords(blockIdx.x, int(p.ld / BM), false, bi, bj);
-  cgemm_f64_tile<BM, OPS>(p, bi, bj, smem);
+  tile_coords(w.tile, int(p.ld / BM), LOWER, bi, bj);
+  cgemm_f64_tile<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke,
+                                 w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM);
 }
 
 // C = alpha * sum_s part[tile, s] + beta * X over the split tiles: one
 // 64-thread block per (split tile, 64 * V elements).  The chunk loads are
 // issued in groups of 8 ahead of the additions, which run in chunk (k) order.
-template <typename T, int BM>
+template <typename T, int BM, bool LOWER>
 __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
   constexpr int V = 16 / sizeof(T);
   constexpr int PER_TILE = BM * BM / (64 * V);
@@ -90,7 +78,7 @@ __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
   const int tl = blockIdx.x / PER_TILE;
   const int e = (blockIdx.x % PER_TILE) * 64 * V + threadIdx.x * V;
   int bi, bj;
-  tile_coords(p.full + tl, int(p.ld / BM), true, bi, bj);
+  tile_coords(p.full + tl, int(p.ld / BM), LOWER, bi, bj);
   vec sr = vec(T(0)), si = vec(T(0));
   const T *src = p.part + size_t(tl) * p.split * 2 * BM * BM + e;
   for (int c0 = 0; c0 < p.split; c0 += G) {
@@ -181,26 +169,44 @@ SplitPlan plan_tail_split(int tiles, int bm, int kt, int64_t ld, int cus, size_t
   return sp;
 }
 
-template <typename T>
-hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, hipStream_t s) {
-  if (a.split < 2) return hipSuccess;
-  const int tiles = int(a.ld / tile);
-  const int tail = tiles * (tiles + 1) / 2 - a.full;
-  const int per_tile = tile * tile / (64 * int(16 / sizeof(T)));
-  if (tail <= 0 || per_tile <= 0) return hipErrorInvalidValue;
-  const dim3 grid(unsigned(tail * per_tile)), block(64);
+SplitPlan plan_small_split(int blocks, int bm, int kt, int64_t ld, int cus, size_t cap_elems) {
+  SplitPlan sp;
+  if (cus <= 0 || blocks <= 0 || 2 * blocks > cus) return sp;
+  int s = std::min<int>(cus / blocks, int(ld / kt) / 2);
+  while (s >= 2 && size_t(blocks) * s * 2 * bm * bm > cap_elems) --s;
+  if (s < 2) return sp;
+  sp.full = 0;
+  sp.split = s;
+  return sp;
+}
+
+template <typename T, bool LOWER>
+static hipError_t split_reduce_tile(const CgemmArgs<T> &a, int tile, dim3 grid, hipStream_t s) {
+  const dim3 block(64);
   if (tile == 128)
-    hipLaunchKernelGGL((split_reduce_kernel<T, 128>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((split_reduce_kernel<T, 128, LOWER>), grid, block, 0, s, a);
   else if (tile == 64)
-    hipLaunchKernelGGL((split_reduce_kernel<T, 64>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((split_reduce_kernel<T, 64, LOWER>), grid, block, 0, s, a);
   else if (tile == 32)
-    hipLaunchKernelGGL((split_reduce_kernel<T, 32>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((split_reduce_kernel<T, 32, LOWER>), grid, block, 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
-template hipError_t launch_split_reduce<float>(const CgemmArgs<float> &, int, hipStream_t);
-template hipError_t launch_split_reduce<double>(const CgemmArgs<double> &, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, bool lower, hipStream_t s) {
+  if (a.split < 2) return hipSuccess;
+  const int tiles = int(a.ld / tile);
+  const int tail = (lower ? tiles * (tiles + 1) / 2 : tiles * tiles) - a.full;
+  const int per_tile = tile * tile / (64 * int(16 / sizeof(T)));
+  if (tail <= 0 || per_tile <= 0) return hipErrorInvalidValue;
+  const dim3 grid(unsigned(tail * per_tile));
+  return lower ? split_reduce_tile<T, true>(a, tile, grid, s)
+               : split_reduce_tile<T, false>(a, tile, grid, s);
+}
+template hipError_t launch_split_reduce<float>(const CgemmArgs<float> &, int, bool, hipStream_t);
+template hipError_t launch_split_reduce<double>(const CgemmArgs<double> &, int, bool, hipStream_t);
 
 // ------------------------------------------------------------- launchers
 
@@ -209,14 +215,14 @@ static hipError_t launch(K kernel, const Args &a, int tile, bool lower, hipStrea
   const int tiles = int(a.ld / tile);
   int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
   if (blocks == 0) return hipSuccess;
-  const bool split = lower && a.split > 1;
+  const bool split = a.split > 1;
   if (split) {
     if (!a.part || a.full < 0 || a.full >= blocks) return hipErrorInvalidValue;
     blocks = a.full + (blocks - a.full) * a.split;
   }
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && split) e = launch_split_reduce(a, tile, s);
+  if (e == hipSuccess && split) e = launch_split_reduce(a, tile, lower, s);
   return e;
 }
 
@@ -274,7 +280,7 @@ static bool use_direct(const CgemmArgs<float> &a, int tile, const GemmOps &o) {
   if (o.direct > 0) return true;
   const int64_t tiles = a.ld / tile;
   int64_t blocks = o.lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
-  if (o.lower && a.split > 1) blocks = a.full + (blocks - a.full) * a.split;
+  if (a.split > 1) blocks = a.full + (blocks - a.full) * a.split;
   return o.cus > 0 && blocks < 4 * int64_t(o.cus);
 }
 

@@ -228,7 +228,7 @@ static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipSt
   }
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && split) e = launch_split_reduce(a, 64, s);
+  if (e == hipSuccess && split) e = launch_split_reduce(a, 64, true, s);
   return e;
 }
 

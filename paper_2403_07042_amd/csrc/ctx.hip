@@ -82,8 +82,59 @@ static hipError_t mark(qme_ctx *c, hipStream_t s, int kind) {
   return hipEventRecord(static_cast<hipEvent_t>(c->events[c->events_used++]), s);
 }
 
+// Products whose launches cannot occupy the device are split along k (all
+// their tiles, FP32 and FP64 contexts); the partials need their own slots.
+// Room for the largest plan over the tile edges the context may be set to,
+// at most 12 planes.
+static bool small_split_applies(const qme_ctx *c) {
+  return c->precision != QME_BF16X3 && c->tail_split;
+}
+
+static size_t small_split_elems(const qme_ctx *c) {
+  if (c->precision == QME_BF16X3) return 0;
+  const int edges[2] = {c->precision == QME_FP64 ? 32 : 64, c->precision == QME_FP64 ? 64 : 128};
+  size_t need = 0;
+  for (int bm : edges) {
+    if (c->ld % bm != 0) continue;
+    const int t = int(c->ld / bm);
+    for (int blocks : {t * t, t * (t + 1) / 2}) {
+      const SplitPlan sp = plan_small_split(blocks, bm, 16, c->ld, c->cus, SIZE_MAX);
+      need = std::max(need, size_t(blocks) * sp.split * 2 * bm * bm);
+    }
+  }
+  return std::min(need, 12 * plane_elems(c));
+}
+
+// The split of one product: every tile when the launch is small and the
+// partial slots exist, else (lower-triangle products) the tail beyond the
+// last full wave of compute units, its partials in `tail_part` (room for
+// `tail_cap` elements).
 template <typename T>
-hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s) {
+static void plan_product(const qme_ctx *c, CgemmArgs<T> &g, int tile, bool lower, T *area,
+                         T *tail_part, size_t tail_cap) {
+  if (!c->tail_split) return;
+  const int t = int(c->ld / tile);
+  const int blocks = lower ? t * (t + 1) / 2 : t * t;
+  if (area && small_split_applies(c)) {
+    const SplitPlan sp = plan_small_split(blocks, tile, 16, c->ld, c->cus, c->split_elems);
+    if (sp.split > 1) {
+      g.full = sp.full;
+      g.split = sp.split;
+      g.part = area;
+      return;
+    }
+  }
+  if (!lower) return;
+  const int kt = c->precision == QME_BF16X3 ? 32 : 16;
+  const SplitPlan sp = plan_tail_split(t, tile, kt, c->ld, c->cus, tail_cap);
+  g.full = sp.full;
+  g.split = sp.split;
+  g.part = tail_part;
+}
+
+template <typename T>
+hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s,
+                     void *split_area) {
   const size_t pe = plane_elems(c);
   const T *x_re = static_cast<const T *>(in), *x_im = x_re + pe;
   const double *aux_in = reinterpret_cast<const double *>(x_im + pe);
@@ -102,14 +153,12 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   o2.lower = true;
   o1.direct = o2.direct = c->direct;
   o1.cus = o2.cus = c->cus;
-  if (c->tail_split) {
-    // chunk partials go to the output planes: dead until the decoherence pass
-    const int kt = c->precision == QME_BF16X3 ? 32 : 16;
-    const SplitPlan sp = plan_tail_split(int(c->ld / c->tile2), c->tile2, kt, c->ld, c->cus, 2 * pe);
-    g2.full = sp.full;
-    g2.split = sp.split;
-    g2.part = o_re;
-  }
+  // split launches: small ones into the workspace's partial slots (when the
+  // caller has them); the lower product's tail into the output planes, dead
+  // until the decoherence pass
+  T *area = static_cast<T *>(split_area);
+  plan_product<T>(c, g1, c->tile1, false, area, nullptr, 0);
+  plan_product<T>(c, g2, c->tile2, true, area, o_re, 2 * pe);
   hipError_t e = mark(c, s, -1);
   if constexpr (sizeof(T) == 4) {
     if (c->precision == QME_BF16X3) {
@@ -138,8 +187,10 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   return e;
 }
 
-template hipError_t step_once<float>(qme_ctx *, const void *, void *, void *, void *, hipStream_t);
-template hipError_t step_once<double>(qme_ctx *, const void *, void *, void *, void *, hipStream_t);
+template hipError_t step_once<float>(qme_ctx *, const void *, void *, void *, void *, hipStream_t,
+                                     void *);
+template hipError_t step_once<double>(qme_ctx *, const void *, void *, void *, void *, hipStream_t,
+                                      void *);
 
 // The single-workgroup path applies to FP32 / FP64 contexts with n <= kSmallN.
 bool uses_small_path(const qme_ctx *c) {
@@ -159,6 +210,15 @@ bool uses_fold(const qme_ctx *c) {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// The step workspace: 4 product planes, the diagonal of Z (N FP64), the
+// partial slots of small-launch splits.
+template <typename T>
+static T *split_area_of(const qme_ctx *c, void *ws) {
+  if (c->split_elems == 0) return nullptr;
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + align256(4 * plane_elems(c) * sizeof(T)) +
+                               align256(sizeof(double) * size_t(c->n)));
+}
+
 // Folded steps: the lower-triangle product writes the decoherence step of
 // its tiles (unscaled, both triangles) straight into the state and the
 // diagonal of Z into the workspace; the trace pass reads that diagonal and
@@ -173,6 +233,7 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   T *z_re = y_im + pe;                      // chunk partials of the split tail
   double *zdiag = reinterpret_cast<double *>(static_cast<char *>(ws) +
                                              align256(4 * pe * sizeof(T)));
+  T *area = split_area_of<T>(c, ws);
   const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
   const double dt = c->model.dt;
   for (int64_t k = 0; k < n_steps; ++k) {
@@ -183,12 +244,8 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     g2.fold_dt = dt;
     g2.fold_n = c->n;
     g2.zdiag = zdiag;
-    if (c->tail_split) {
-      const SplitPlan sp = plan_tail_split(int(c->ld / c->tile2), c->tile2, 16, c->ld, c->cus, 2 * pe);
-      g2.full = sp.full;
-      g2.split = sp.split;
-      g2.part = z_re;
-    }
+    plan_product<T>(c, g1, c->tile1, false, area, nullptr, 0);
+    plan_product<T>(c, g2, c->tile2, true, area, z_re, 2 * pe);
     DissArgs<T> da{nullptr, nullptr, x_re, x_im, c->ld, c->n, dt, c->d, c->leak,
                    c->pi, c->cg, 0, aux, aux, c->trw, zdiag};
     GemmOps o1, o2;
@@ -243,7 +300,7 @@ static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   T *y = static_cast<T *>(ws);
   T *z = y + 2 * pe;
   for (int64_t k = 0; k < n_steps; ++k) {
-    hipError_t e = step_once<T>(c, state, state, y, z, s);
+    hipError_t e = step_once<T>(c, state, state, y, z, s, split_area_of<T>(c, ws));
     if (e != hipSuccess) {
       set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
       return QME_E_DEVICE;
@@ -275,6 +332,7 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
   HIP_OK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const size_t pe = plane_elems(c);
+  c->split_elems = small_split_elems(c);
   // propagator planes, padded with zeros, in the storage type
   std::vector<char> buf(pe * c->elem);
   for (int plane = 0; plane < 2; ++plane) {
@@ -549,8 +607,10 @@ extern "C" qme_status qme_state_layout(const qme_ctx *c, int64_t *n, int64_t *ld
 extern "C" qme_status qme_workspace_size(const qme_ctx *c, size_t *bytes) {
   set_error("");
   if (!c || !bytes) { set_error("NULL argument"); return QME_E_ARG; }
-  // the step's product planes, and the diagonal of Z for folded steps
-  *bytes = align256(4 * plane_elems(c) * c->elem) + align256(sizeof(double) * size_t(c->n));
+  // the step's product planes, the diagonal of Z for folded steps and the
+  // partial slots of products split along k
+  *bytes = align256(4 * plane_elems(c) * c->elem) + align256(sizeof(double) * size_t(c->n)) +
+           align256(c->split_elems * c->elem);
   return QME_OK;
 }
 

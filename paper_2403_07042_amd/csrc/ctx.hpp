@@ -23,6 +23,7 @@ struct qme_ctx {
   bool fused = true;                  // qme_set_fused (single-workgroup path, n <= 32)
   bool fold = true;                   // qme_set_fold (decoherence folded into the products)
   int direct = -1;                    // qme_set_direct_loads (-1 auto, 0 off, 1 on)
+  size_t split_elems = 0;             // partial slots of small-launch splits (elements)
   int device = 0;
   int cus = 0;                        // compute units of the device
   // device tables (owned)
@@ -77,7 +78,10 @@ qme_status check_device(const qme_ctx *c);
 // One time step from state `in` to state `out` (may alias) with the two
 // workspace plane pairs y (product T) and z (rotated state, lower tiles).
 template <typename T>
-hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s);
+// split_area: the step workspace's partial slots for small-launch splits
+// (nullptr: no such splits, as in the adjoint's recomputation)
+hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s,
+                     void *split_area = nullptr);
 bool uses_small_path(const qme_ctx *c);
 bool uses_fold(const qme_ctx *c);
 }  // namespace qme

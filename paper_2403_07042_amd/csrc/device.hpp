@@ -22,10 +22,11 @@ struct GemmOps {
   int direct = 0, cus = 0;
 };
 
-// Tail split (lower-triangle launches only): when split > 1, tiles
-// [full, all) are computed in `split` k-chunks each, into partial slots of
-// 2 * tile^2 elements at `part` (re then im, tile-local row-major), and a
-// reduce pass writes C = alpha * (sum of the chunks in order) + beta * X.
+// Split launches (FP32 / FP64; BF16x3: lower-triangle launches only): when
+// split > 1, tiles [full, all) are computed in `split` k-chunks each, into
+// partial slots of 2 * tile^2 elements at `part` (re then im, tile-local
+// row-major), and a reduce pass writes C = alpha * (sum of the chunks in
+// order) + beta * X.
 template <typename T>
 struct CgemmArgs {
   const T *a_re, *a_im;
@@ -62,8 +63,15 @@ struct SplitPlan {
   int32_t full = 0, split = 0;
 };
 SplitPlan plan_tail_split(int tiles, int bm, int kt, int64_t ld, int cus, size_t cap_elems);
+// Plan of a split of every tile of a launch too small to occupy the device:
+// `blocks` tiles (at most half as many as compute units) each cut along k
+// into `split` chunks of at least two K tiles (full = 0), with room for
+// `cap_elems` partial elements.  split = 0: no split.
+SplitPlan plan_small_split(int blocks, int bm, int kt, int64_t ld, int cus, size_t cap_elems);
+// Reduce pass of a split launch: tiles [full, all) of the launch's tile
+// enumeration (lower triangle or full grid).
 template <typename T>
-hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, hipStream_t s);
+hipError_t launch_split_reduce(const CgemmArgs<T> &a, int tile, bool lower, hipStream_t s);
 // state planes (ld x ld each) *= *scale, in FP64 (the last step of a folded run)
 template <typename T>
 hipError_t launch_apply_scale(T *re, T *im, int64_t elems, const double *scale, hipStream_t s);

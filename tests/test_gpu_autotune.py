@@ -20,6 +20,7 @@ def test_tile_choice_is_bitwise_neutral_and_tuner_picks_valid(precision, tmp_pat
     rho0 = W.initial_rho(wl, occ)
     sol = P.Solver(wl, precision)
     sol.set_fold(False)          # folding depends on the lower tile; compare tiles alone
+    sol.set_split(False)         # so do the k-splits of small launches
     outs = []
     for tiles in A.candidates(precision, sol.ld):
         sol.set_tiles(*tiles)

@@ -325,3 +325,46 @@ def test_profile_sampling_stride():
         sol.profile(-1)
     sol.profile(False)
     sol.close()
+
+
+@pytest.mark.parametrize("make,precision,tol", [
+    (W.tch_2x2, "fp32", 1e-5),                                   # N = 144: 9 + 6 tiles
+    (W.tch_2x2, "fp64", 1e-12),
+    (lambda: W.photon_lattice(16, 16, gamma=0.05), "fp32", 1e-5),   # N = 512, folded steps
+    (lambda: W.photon_lattice(16, 16, gamma=0.05), "fp64", 1e-12),
+])
+def test_small_launch_split(make, precision, tol):
+    """Products too small to occupy the device are cut along k: the split
+    step against the unsplit one and (N = 144) the oracle, over several
+    qme_step calls, with 64- and 128-tiles (FP32) or 32- and 64-tiles (FP64)."""
+    wl = dict(make(), init={"kind": "haar", "seed": 11})
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, precision)
+    tiles = [(64, 64), (128, 128)] if precision == "fp32" else [(32, 32), (64, 64)]
+    outs = {}
+    for t in tiles:
+        if sol.ld % t[0]:
+            continue
+        sol.set_tiles(*t)
+        for split in (True, False):
+            print(f"N={sol.n} {precision} tiles={t} split={split}", flush=True)
+            sol.set_split(split)
+            sol.set_rho(rho0)
+            sol.step(7)
+            sol.step(13)
+            rho, sink = sol.get_rho()
+            _, trace, _ = sol.observe()
+            outs[(t, split)] = (rho, sink, trace)
+    sol.close()
+    ref_rho = outs[(tiles[0], False)][0]
+    scale = np.abs(ref_rho).max()
+    for key, (rho, sink, trace) in outs.items():
+        assert np.abs(rho - ref_rho).max() < tol * scale, key
+        assert abs(trace - (1.0 - sink)) < TRACE_TOL[precision], key
+        assert np.array_equal(rho, rho.conj().T), key
+    if sol.n == 144:
+        s = ev.System(wl)
+        ref, _ = ev.evolve(s, rho0, 20)
+        for key, (rho, _, _) in outs.items():
+            assert np.abs(rho - ref).max() < tol, key
