@@ -389,6 +389,17 @@ qme_status qme_set_fold(qme_ctx *ctx, int32_t enable);
  * identical.  Other values: QME_E_ARG. */
 qme_status qme_set_direct_loads(qme_ctx *ctx, int32_t mode);
 
+/* Graph replay of qme_step (off by default): with enable = 1, a call of
+ * n_steps on a given (state, workspace) pair is captured once into a
+ * hipGraph on a private stream and replayed onto the caller's stream with
+ * one launch, which removes the host's per-kernel launch cost from
+ * launch-bound sizes; results are bitwise those of the eager call.  Any knob
+ * change (tiles, split, fold, fused, direct loads, this one) drops the
+ * captures after synchronising the device; with profiling enabled the call
+ * runs eagerly.  Calls that overlap on one context race (as eager ones do).
+ * enable: 0 or 1, else QME_E_ARG. */
+qme_status qme_set_graph(qme_ctx *ctx, int32_t enable);
+
 /* Per-kernel timing of qme_step with HIP events recorded on the caller's
  * stream around every launch (the tracing facility used by the benchmark).
  * enable > 0 starts recording (and clears earlier records) on every

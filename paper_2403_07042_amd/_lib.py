@@ -80,6 +80,7 @@ SIGNATURES = {
     "qme_set_fused": (c_int32, [c_void_p, c_int32]),
     "qme_set_fold": (c_int32, [c_void_p, c_int32]),
     "qme_set_direct_loads": (c_int32, [c_void_p, c_int32]),
+    "qme_set_graph": (c_int32, [c_void_p, c_int32]),
     "qme_hamiltonian_general": (c_int32, [c_int64, c_int64, POINTER(c_int32), POINTER(c_int32),
                                           POINTER(c_double), c_int32, POINTER(GeneralJump), c_double,
                                           c_int32, c_void_p, POINTER(c_void_p)]),

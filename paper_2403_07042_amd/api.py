@@ -256,6 +256,10 @@ class Solver:
         blocks per compute unit.  Bitwise-neutral."""
         L.check(self.lib.qme_set_direct_loads(self.ctx, int(mode)))
 
+    def set_graph(self, enable: bool):
+        """Replay qme_step runs from captured hipGraphs (off by default)."""
+        L.check(self.lib.qme_set_graph(self.ctx, int(bool(enable))))
+
     def set_fused(self, enable: bool):
         """Single-workgroup path for N <= 32 (FP32 / FP64) on (default) or off."""
         L.check(self.lib.qme_set_fused(self.ctx, int(bool(enable))))

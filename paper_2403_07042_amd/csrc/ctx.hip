@@ -691,9 +691,48 @@ extern "C" qme_status qme_step(qme_ctx *c, void *state, int64_t n_steps, void *w
   qme_status st = check_device(c);
   if (st != QME_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (c->elem == 8) return step_impl<double>(c, state, n_steps, ws, s);
-  return step_impl<float>(c, state, n_steps, ws, s);
+  auto run = [&](hipStream_t on) {
+    return c->elem == 8 ? step_impl<double>(c, state, n_steps, ws, on)
+                        : step_impl<float>(c, state, n_steps, ws, on);
+  };
+  if (!c->use_graph || c->profiling || n_steps == 0) return run(s);
+  const auto key = std::make_tuple(n_steps, state, ws);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    // capture the run's launches once, on a private default-priority stream
+    if (!c->capture_stream) HIP_OK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    const qme_status r = run(c->capture_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+    if (r != QME_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (r != QME_OK) return r;
+      set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+      return QME_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+      return QME_E_DEVICE;
+    }
+    c->graph_defs.push_back(g);
+    it = c->graphs.emplace(key, ex).first;
+  }
+  HIP_OK(hipGraphLaunch(it->second, s));
+  return QME_OK;
   QME_GUARD_END
+}
+
+extern "C" qme_status qme_set_graph(qme_ctx *c, int32_t enable) {
+  set_error("");
+  if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
+  if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->drop_graphs();
+  c->use_graph = enable != 0;
+  return QME_OK;
 }
 
 extern "C" qme_status qme_observe(const qme_ctx *c, const void *state, double *pops,
@@ -792,6 +831,7 @@ extern "C" qme_status qme_set_fold(qme_ctx *c, int32_t enable) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->drop_graphs();
   c->fold = enable != 0;
   return QME_OK;
 }
@@ -800,6 +840,7 @@ extern "C" qme_status qme_set_direct_loads(qme_ctx *c, int32_t mode) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   if (mode < -1 || mode > 1) { set_error("mode must be -1, 0 or 1"); return QME_E_ARG; }
+  c->drop_graphs();
   c->direct = mode;
   return QME_OK;
 }
@@ -808,6 +849,7 @@ extern "C" qme_status qme_set_fused(qme_ctx *c, int32_t enable) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->drop_graphs();
   c->fused = enable != 0;
   return QME_OK;
 }
@@ -816,6 +858,7 @@ extern "C" qme_status qme_set_split(qme_ctx *c, int32_t enable) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  c->drop_graphs();
   c->tail_split = enable != 0;
   return QME_OK;
 }
@@ -833,6 +876,7 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
     set_error("tile not supported for this precision or does not divide ld");
     return QME_E_ARG;
   }
+  c->drop_graphs();
   c->tile1 = tile1;
   c->tile2 = tile2;
   return QME_OK;
@@ -875,7 +919,18 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
   QME_GUARD_END
 }
 
+void qme_ctx::drop_graphs() {
+  if (graphs.empty() && graph_defs.empty()) return;
+  (void)hipDeviceSynchronize();   // no replay may still run
+  for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+  for (hipGraph_t g : graph_defs) (void)hipGraphDestroy(g);
+  graph_defs.clear();
+}
+
 qme_ctx::~qme_ctx() {
+  drop_graphs();
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
   for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)trw, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,

@@ -2,7 +2,9 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -24,6 +26,13 @@ struct qme_ctx {
   bool fold = true;                   // qme_set_fold (decoherence folded into the products)
   int direct = -1;                    // qme_set_direct_loads (-1 auto, 0 off, 1 on)
   size_t split_elems = 0;             // partial slots of small-launch splits (elements)
+  // qme_set_graph: a run of n steps captured once per (n, state, workspace)
+  // into a hipGraph and replayed; any knob change drops the captures
+  bool use_graph = false;
+  std::map<std::tuple<int64_t, void *, void *>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+  hipStream_t capture_stream = nullptr;
+  void drop_graphs();
   int device = 0;
   int cus = 0;                        // compute units of the device
   // device tables (owned)

@@ -170,5 +170,5 @@ def test_select_states_errors():
 def test_knob_setters_reject_null_context():
     lib = L.load()
     for name, arg in (("qme_set_fold", 1), ("qme_set_split", 1), ("qme_set_fused", 1),
-                      ("qme_set_direct_loads", -1)):
+                      ("qme_set_direct_loads", -1), ("qme_set_graph", 1)):
         assert getattr(lib, name)(None, arg) == L.QME_E_ARG, name
