@@ -242,7 +242,9 @@ class Solver:
         L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
 
     def set_split(self, enable: bool):
-        """Tail split of the lower-triangle product on (default) or off."""
+        """k-splits of the products on (default) or off: the tail of the
+        lower-triangle product, and every tile of a launch too small for the
+        device (FP32 / FP64)."""
         L.check(self.lib.qme_set_split(self.ctx, int(bool(enable))))
 
     def set_fold(self, enable: bool):

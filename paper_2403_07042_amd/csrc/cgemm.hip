@@ -33,7 +33,10 @@
 //   * LOWER launches only the tiles on or below the diagonal (Hermitian
 //     output), in an XCD-aware order, with the tiles past the last full
 //     wave of CUs cut along k (tail split) and, for folded steps, the
-//     decoherence factor applied in the epilogue (CgemmArgs::fold_d).
+//     decoherence factor applied in the epilogue (CgemmArgs::fold_d);
+//   * a launch with at most half as many tiles as CUs has every tile cut
+//     along k (small-launch split); split tiles are summed in chunk order by
+//     a reduce pass.
 #include "cgemm_tile.hpp"
 
 #include <algorithm>

@@ -84,7 +84,7 @@ __device__ __forceinline__ void tile_coords(int t, int tiles, bool lower, int &b
 }
 
 // Work of one block of a product launch.  Blocks [0, full) are whole tiles
-// (tile index = block).  With a tail split (S > 1) the remaining tiles are cut
+// (tile index = block).  With a split (S > 1) the remaining tiles are cut
 // along k: block full + q computes k-chunk q % S (K-tile iterations
 // [s*nk/S, (s+1)*nk/S)) of tile full + q / S and writes its raw accumulator
 // to partial slot q; a reduce pass sums the S slots of a tile in chunk order.
