@@ -294,6 +294,24 @@ def selection_leg(P, W, torch, steps=1000, eps=1e-20):
             "compact_2048_to_1024_us": us, "compact_gbs": moved / (us * 1e-6) / 1e9}
 
 
+def configs_leg(P, W, torch, warmup=10):
+    """FP32, split-BF16x3 and plain FP64 steps/s, with the speedups over FP64,
+    on the other parity configurations: the 2 x 2 Tavis-Cummings-Hubbard
+    model (N = 144, 2000 steps) and the three-cavity chain (N = 1728, 200
+    steps)."""
+    out = {}
+    for name, wl, steps in (("tch_2x2_n144", W.tch_2x2(), 2000),
+                            ("tch_chain3_n1728", W.tch_chain3(), 200)):
+        rates = {}
+        for prec in ("fp32", "bf16x3", "fp64"):
+            leg = timed_leg(P, W, torch, wl, prec, steps, warmup)
+            rates[prec] = leg["steps_per_s"]
+        out[name] = {"steps": steps, "steps_per_s": rates,
+                     "fp32_speedup_over_fp64": rates["fp32"] / rates["fp64"],
+                     "bf16x3_speedup_over_fp64": rates["bf16x3"] / rates["fp64"]}
+    return out
+
+
 def plane_leg(P, W, torch, steps=100, warmup=5):
     """The paper's own 2D photon-motion plane (81 x 51 cavities, one photon,
     N = 4131, ld = 4160), FP32, symmetric start: steps/s and per-kernel
@@ -424,6 +442,7 @@ def main():
 
     batch = batch_leg(P, W, torch, args.batch_steps) if args.batch_steps > 0 else None
     latency = latency_leg(P, W, torch) if args.latency else None
+    configs = configs_leg(P, W, torch) if args.latency else None
     selection = selection_leg(P, W, torch) if args.selection else None
     plane = plane_leg(P, W, torch, args.plane_steps) if args.plane_steps > 0 else None
     hbond = hydrogen_bond_leg(P, torch, args.hb_steps) if args.hb_steps > 0 else None
@@ -495,6 +514,7 @@ def main():
         "adjoint": adj,
         "batch_sweep": batch,
         "latency_bound": latency,
+        "other_configs": configs,
         "state_selection": selection,
         "photon_plane": plane,
         "hydrogen_bond": hbond,
