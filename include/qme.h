@@ -324,7 +324,7 @@ void qme_batch_destroy(qme_batch *batch);
  * read row-major; otherwise it is M and B = M^T, i.e. the operand is read by
  * rows j.  opB = conj(B) if conj_b else B (so b_rows = 0, conj_b = 1 gives
  * M^H).  lower != 0 computes only the tile x tile blocks on or below the
- * diagonal.  tile: 128 or 64 (FP32), 64 or 32 (FP64), 64 (QME_BF16X3: FP32
+ * diagonal.  tile: 128, 64 or 32 (FP32), 64 or 32 (FP64), 64 (QME_BF16X3: FP32
  * planes, split-bf16 products, b_rows must be 0); ld must be a multiple of
  * tile.  C must not overlap A or B; C may equal X (accumulation).
  * Asynchronous on hip_stream. */
@@ -337,8 +337,10 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
 
 /* Tile edge of the two products of each step (the autotuner's knob):
  * tile1 for T = rho + dU rho, tile2 for the lower-triangle product.
- * FP32 tiles: 128 or 64; FP64 tiles: 64 or 32; BF16X3: 64.  Each must divide the state's
- * leading dimension ld (qme_state_layout), else QME_E_ARG. */
+ * FP32 tiles: 128, 64 or 32; FP64 tiles: 64 or 32; BF16X3: 64.  Each must divide the
+ * state's leading dimension ld (qme_state_layout), else QME_E_ARG.  Defaults:
+ * FP64 32; FP32 32 when the full product in 64-tiles would give fewer than
+ * four workgroups per compute unit, else 64; BF16X3 64. */
 qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
 
 /* Split of the products along k (on by default).  Tail split: when the

@@ -9,10 +9,13 @@ on a scratch copy of the state so the caller's state does not advance) and
 the fastest is applied.  Results are cached per (GPU architecture,
 precision, N, ld) in $QME_TUNE_CACHE (default ~/.cache/qme_mi355x/tune.json).
 
-With the split off, tile choice never changes results: every tile size
-accumulates each output element over k in the same order, so the products are
-bitwise identical.  A split regroups the k sum of the split tiles (FP
-rounding only, deterministic for a given configuration).
+With the split off, tile choice among tiles of one matrix-core shape never
+changes results: FP32 64- and 128-tiles (32x32 MFMA) and FP64 32- and
+64-tiles (16x16 MFMA) accumulate each output element over k in the same
+order, so their products are bitwise identical; FP32 32-tiles use the 16x16
+MFMA, which groups the k sum differently (FP rounding only).  A split
+regroups the k sum of the split tiles (FP rounding only, deterministic for a
+given configuration).
 """
 from __future__ import annotations
 
@@ -24,7 +27,7 @@ import time
 CACHE_ENV = "QME_TUNE_CACHE"
 
 TILES = {
-    "fp32": [(64, 64), (64, 128), (128, 64), (128, 128)],
+    "fp32": [(32, 32), (32, 64), (64, 32), (64, 64), (64, 128), (128, 64), (128, 128)],
     "fp64": [(32, 32), (32, 64), (64, 32), (64, 64)],
     "bf16x3": [(64, 64)],
 }

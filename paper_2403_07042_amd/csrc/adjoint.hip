@@ -385,7 +385,8 @@ static hipError_t gemm(const qme_ctx *c, int tile, const GemmOps &o, const T *a_
                        T *c_im, hipStream_t s, T *part = nullptr) {
   CgemmArgs<T> g{a_re, a_im, m_re, m_im, x_re, x_im, c_re, c_im, c->ld, T(1), T(1)};
   if (o.lower && part && c->tail_split) {
-    const SplitPlan sp = plan_tail_split(int(c->ld / tile), tile, 16, c->ld, c->cus, 2 * plane_elems(c));
+    const int kt = c->precision == QME_FP32 && tile == 32 ? 32 : 16;
+    const SplitPlan sp = plan_tail_split(int(c->ld / tile), tile, kt, c->ld, c->cus, 2 * plane_elems(c));
     g.full = sp.full;
     g.split = sp.split;
     g.part = part;

@@ -46,14 +46,18 @@ namespace qme {
 // DIRECT: operands loaded straight into LDS (NT forms only).
 template <int BM, int OPS, bool LOWER, bool DIRECT = false>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
-  __shared__ float smem[cgemm_f32_smem<BM, OPS>()];
-  static_assert(!DIRECT || !(OPS & kBRow), "direct loads serve the NT forms");
+  // 32-tiles: the 16x16-MFMA body (K tile 32); 64/128: the 32x32 bodies (K tile 16)
+  constexpr int kSmem = BM == 32 ? cgemm_s_smem<float, 32, OPS>() : cgemm_f32_smem<BM, OPS>();
+  __shared__ float smem[kSmem];
+  static_assert(!DIRECT || (!(OPS & kBRow) && BM != 32), "direct loads serve the NT forms");
   // whole tile, or (split launches) one k-chunk of a tile into its partial slot
-  const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
+  const TileWork w = tile_work(blockIdx.x, int(p.ld / (BM == 32 ? 32 : 16)), p.full, p.split);
   int bi, bj;
   tile_coords(w.tile, int(p.ld / BM), LOWER, bi, bj);
   float *part = w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM;
-  if constexpr (DIRECT)
+  if constexpr (BM == 32)
+    cgemm_s_tile<float, 32, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
+  else if constexpr (DIRECT)
     cgemm_f32_tile_dma<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
   else
     cgemm_f32_tile<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
@@ -279,7 +283,7 @@ static hipError_t cgemm_f32_direct_dispatch(const CgemmArgs<float> &a, int ops, 
 
 // Whether a launch takes the direct-load tile body (see GemmOps::direct).
 static bool use_direct(const CgemmArgs<float> &a, int tile, const GemmOps &o) {
-  if (o.b_rows || o.direct == 0) return false;
+  if (o.b_rows || o.direct == 0 || tile == 32) return false;
   if (o.direct > 0) return true;
   const int64_t tiles = a.ld / tile;
   int64_t blocks = o.lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
@@ -293,7 +297,7 @@ static bool use_direct(const CgemmArgs<float> &a, int tile, const GemmOps &o) {
 template <int BM>
 constexpr bool f32_folds() {
   return 2 * BM * (BM + 1) * sizeof(float) + 2 * BM * sizeof(double) <=
-         cgemm_f32_smem<BM, kConjB>() * sizeof(float);
+         (BM == 32 ? cgemm_s_smem<float, 32, kConjB>() : cgemm_f32_smem<BM, kConjB>()) * sizeof(float);
 }
 template <int BM>
 constexpr bool f64_folds() {
@@ -302,7 +306,8 @@ constexpr bool f64_folds() {
 
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o, hipStream_t s) {
   if (a.ld % tile != 0) return hipErrorInvalidValue;
-  if (a.fold_d && (!o.lower || o.b_rows || !(tile == 64 ? f32_folds<64>() : f32_folds<128>())))
+  if (a.fold_d && (!o.lower || o.b_rows ||
+                   !(tile == 32 ? f32_folds<32>() : tile == 64 ? f32_folds<64>() : f32_folds<128>())))
     return hipErrorInvalidValue;
   const bool direct = use_direct(a, tile, o);
   if (tile == 128)
@@ -311,6 +316,7 @@ hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &
   if (tile == 64)
     return direct ? cgemm_f32_direct_dispatch<64>(a, ops_of(o), o.lower, s)
                   : cgemm_f32_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
+  if (tile == 32) return cgemm_f32_kernel_dispatch<32>(a, ops_of(o), o.lower, s);
   return hipErrorInvalidValue;
 }
 

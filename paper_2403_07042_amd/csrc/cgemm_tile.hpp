@@ -215,13 +215,17 @@ constexpr int cgemm_f32_smem() {
 }
 // (at least the folded epilogue's staging: the tile, BM + 1 per row, and
 // the row and column factors)
-template <int BM, int OPS>
-constexpr int cgemm_f64_smem() {
-  constexpr int KT = 16, LDK = KT, LDJ = BM + 2;
+// (16x16-MFMA tiles: rows of 128 bytes, KT = 16 doubles or 32 floats)
+template <typename T, int BM, int OPS>
+constexpr int cgemm_s_smem() {
+  constexpr int E = 16 / sizeof(T), KT = 8 * E, LDK = KT, LDJ = BM + E;
   constexpr int BSZ = (OPS & kBRow) ? KT * LDJ : BM * LDK;
-  constexpr int stages = 4 * BM * LDK + 4 * BSZ, fold = 2 * BM * (BM + 1) + 2 * BM;
+  constexpr int stages = 4 * BM * LDK + 4 * BSZ;
+  constexpr int fold = 2 * BM * (BM + 1) + 2 * BM * int(sizeof(double) / sizeof(T));
   return stages > fold ? stages : fold;
 }
+template <int BM, int OPS>
+constexpr int cgemm_f64_smem() { return cgemm_s_smem<double, BM, OPS>(); }
 
 // Writes a finished FP32 tile: the raw accumulator into a split partial, or
 // C = alpha * acc + beta * X, or the folded decoherence step (the operand LDS
@@ -568,25 +572,37 @@ __device__ __forceinline__ void cgemm_f32_tile_dma(const CgemmArgs<float> &p, in
   f32_tile_epilogue<BM, OPS, FOLD, F, WM>(p, bi, bj, smem, cr, ci, part);
 }
 
-// ----------------------------------------------------------------- FP64
-// v_mfma_f64_16x16x4_f64: A 16x4 (lane l: row l%16, k-slot l/16), B 4x16
-// (lane l: k-slot l/16, col l%16), D 16x16 in 4 doubles (lane l: col l%16,
-// register r: row l/16 + 4*r).
+// ------------------------------------------- 16x16-MFMA tiles (FP64, FP32)
+// v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32: A 16x4 (lane l: row l%16,
+// k-slot l/16), B 4x16 (lane l: k-slot l/16, col l%16), D 16x16 in 4
+// registers (lane l: col l%16; register r: row l/16 + 4*r for f64, row
+// 4*(l/16) + r for f32).  LDS rows are 128 bytes (16 doubles or 32 floats:
+// eight 16-byte chunks, swizzled); each lane reads two chunks per K tile, in
+// two halves with one half's fragments live.
 
-template <int BM, int OPS, bool FOLD = false>
-__device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int bi, int bj, double *smem,
-                                               int kb = 0, int ke = -1, double *part = nullptr) {
+template <typename T>
+__device__ __forceinline__ int s_row(int h, int r) {
+  return sizeof(T) == 8 ? h + 4 * r : 4 * h + r;
+}
+
+template <typename T, int BM, int OPS, bool FOLD = false>
+__device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int bj, T *smem,
+                                             int kb = 0, int ke = -1, T *part = nullptr) {
   constexpr bool BROW = OPS & kBRow;
-  constexpr int KT = 16;
-  constexpr int LDK = KT;              // LDS row of A / NT-B (doubles), 16-byte chunks swizzled
-  constexpr int LDJ = BM + 2;
+  constexpr int E = 16 / sizeof(T);    // elements per 16-byte chunk
+  constexpr int KT = 8 * E;            // K tile: one 128-byte row
+  constexpr int LDK = KT;              // LDS row of A / NT-B, 16-byte chunks swizzled
+  constexpr int LDJ = BM + E;
   constexpr int WM = BM / 2;
   constexpr int F = WM / 16;           // 16x16 blocks per wave side
-  constexpr int PASSES = BM / 32;      // 32 rows per pass (8 x doublex2 per row)
+  constexpr int PASSES = BM / 32;      // 32 rows per pass (8 chunks per row)
   constexpr int BSZ = BROW ? KT * LDJ : BM * LDK;
-  constexpr int BPASS = BROW ? (KT * BM / 2) / kThreads : PASSES;
-  double (*sA)[2][BM * LDK] = reinterpret_cast<double (*)[2][BM * LDK]>(smem);
-  double (*sB)[2][BSZ] = reinterpret_cast<double (*)[2][BSZ]>(smem + 4 * BM * LDK);
+  constexpr int BPASS = BROW ? (KT * BM / E) / kThreads : PASSES;
+  constexpr int BSTEP = kThreads / (BM / E);   // NN-B rows per load pass
+  typedef T vec __attribute__((ext_vector_type(E)));
+  typedef T acc4 __attribute__((ext_vector_type(4)));
+  T (*sA)[2][BM * LDK] = reinterpret_cast<T (*)[2][BM * LDK]>(smem);
+  T (*sB)[2][BSZ] = reinterpret_cast<T (*)[2][BSZ]>(smem + 4 * BM * LDK);
 
   const int64_t ld = p.ld;
   const int tid = threadIdx.x;
@@ -594,57 +610,59 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, h = lane >> 4;
 
-  const int lr = tid >> 3, lk = (tid & 7) * 2;
-  const double *ga_re = p.a_re + (int64_t(bi) * BM + lr) * ld + lk;
-  const double *ga_im = p.a_im + (int64_t(bi) * BM + lr) * ld + lk;
-  const int br_k = tid / (BM / 2), br_j = (tid % (BM / 2)) * 2;
-  const double *gb_re = BROW ? p.m_re + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
-                             : p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
-  const double *gb_im = BROW ? p.m_im + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
-                             : p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
+  const int lr = tid >> 3, lk = (tid & 7) * E;
+  const T *ga_re = p.a_re + (int64_t(bi) * BM + lr) * ld + lk;
+  const T *ga_im = p.a_im + (int64_t(bi) * BM + lr) * ld + lk;
+  const int br_k = tid / (BM / E), br_j = (tid % (BM / E)) * E;
+  const T *gb_re = BROW ? p.m_re + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
+                        : p.m_re + (int64_t(bj) * BM + lr) * ld + lk;
+  const T *gb_im = BROW ? p.m_im + int64_t(br_k) * ld + int64_t(bj) * BM + br_j
+                        : p.m_im + (int64_t(bj) * BM + lr) * ld + lk;
 
-  doublex2 ra[PASSES][2], rb[BPASS > 0 ? BPASS : 1][2];
+  vec ra[PASSES][2], rb[BPASS > 0 ? BPASS : 1][2];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < PASSES; ++q) {
       const int64_t off = int64_t(q) * 32 * ld + k0;
-      ra[q][0] = *reinterpret_cast<const doublex2 *>(ga_re + off);
-      ra[q][1] = *reinterpret_cast<const doublex2 *>(ga_im + off);
+      ra[q][0] = *reinterpret_cast<const vec *>(ga_re + off);
+      ra[q][1] = *reinterpret_cast<const vec *>(ga_im + off);
     }
 #pragma unroll
     for (int q = 0; q < BPASS; ++q) {
-      const int64_t off = BROW ? (int64_t(k0) + q * (kThreads / (BM / 2))) * ld
-                               : int64_t(q) * 32 * ld + k0;
-      rb[q][0] = *reinterpret_cast<const doublex2 *>(gb_re + off);
-      rb[q][1] = *reinterpret_cast<const doublex2 *>(gb_im + off);
+      const int64_t off = BROW ? (int64_t(k0) + q * BSTEP) * ld : int64_t(q) * 32 * ld + k0;
+      rb[q][0] = *reinterpret_cast<const vec *>(gb_re + off);
+      rb[q][1] = *reinterpret_cast<const vec *>(gb_im + off);
     }
   };
   auto lstore = [&](int st) {
 #pragma unroll
     for (int q = 0; q < PASSES; ++q) {
-      const int o = (q * 32 + lr) * LDK + 2 * ((lk >> 1) ^ f64_swz(q * 32 + lr));
-      *reinterpret_cast<doublex2 *>(&sA[st][0][o]) = ra[q][0];
-      *reinterpret_cast<doublex2 *>(&sA[st][1][o]) = ra[q][1];
+      const int o = (q * 32 + lr) * LDK + E * ((lk / E) ^ f64_swz(q * 32 + lr));
+      *reinterpret_cast<vec *>(&sA[st][0][o]) = ra[q][0];
+      *reinterpret_cast<vec *>(&sA[st][1][o]) = ra[q][1];
     }
 #pragma unroll
     for (int q = 0; q < BPASS; ++q) {
-      const int o = BROW ? (br_k + q * (kThreads / (BM / 2))) * LDJ + br_j
-                         : (q * 32 + lr) * LDK + 2 * ((lk >> 1) ^ f64_swz(q * 32 + lr));
-      *reinterpret_cast<doublex2 *>(&sB[st][0][o]) = rb[q][0];
-      *reinterpret_cast<doublex2 *>(&sB[st][1][o]) = rb[q][1];
+      const int o = BROW ? (br_k + q * BSTEP) * LDJ + br_j
+                         : (q * 32 + lr) * LDK + E * ((lk / E) ^ f64_swz(q * 32 + lr));
+      *reinterpret_cast<vec *>(&sB[st][0][o]) = rb[q][0];
+      *reinterpret_cast<vec *>(&sB[st][1][o]) = rb[q][1];
     }
   };
 
-  doublex4 p1[F][F], p2[F][F], p3[F][F];
+  acc4 p1[F][F], p2[F][F], p3[F][F];
 #pragma unroll
   for (int a = 0; a < F; ++a)
 #pragma unroll
     for (int b = 0; b < F; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) { p1[a][b][r] = 0.0; p2[a][b][r] = 0.0; p3[a][b][r] = 0.0; }
+      for (int r = 0; r < 4; ++r) { p1[a][b][r] = T(0); p2[a][b][r] = T(0); p3[a][b][r] = T(0); }
 
-  auto mfma = [](double x, double y, doublex4 acc) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+  auto mfma = [](T x, T y, acc4 acc) {
+    if constexpr (sizeof(T) == 8)
+      return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc, 0, 0, 0);
   };
 
   const int nk = ke < 0 ? int(ld / KT) : ke;
@@ -654,45 +672,51 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
   for (int kt = kb; kt < nk; ++kt) {
     const int st = (kt - kb) & 1;
     if (kt + 1 < nk) gload((kt + 1) * KT);
-    // two halves of the K tile (k-steps 0-1, then 2-3), one half's
-    // fragments live at a time
+    // two halves of the K tile (lane k values 2hE .. 2hE + E - 1, then the
+    // next E), one half's fragments live at a time
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf) {
-      double ar[F][2], ai[F][2], br[F][2], bi_[F][2];
+      T ar[F][E], ai[F][E], br[F][E], bi_[F][E];
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         const int ra_ = wm * WM + f * 16 + li;
-        const int oa = ra_ * LDK + 2 * ((2 * h + hf) ^ f64_swz(ra_));
-        const doublex2 x = *reinterpret_cast<const doublex2 *>(&sA[st][0][oa]);
-        const doublex2 y = *reinterpret_cast<const doublex2 *>(&sA[st][1][oa]);
-        ar[f][0] = x[0]; ar[f][1] = x[1];
-        ai[f][0] = y[0]; ai[f][1] = y[1];
+        const int oa = ra_ * LDK + E * ((2 * h + hf) ^ f64_swz(ra_));
+        const vec x = *reinterpret_cast<const vec *>(&sA[st][0][oa]);
+        const vec y = *reinterpret_cast<const vec *>(&sA[st][1][oa]);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          ar[f][e] = x[e];
+          ai[f][e] = y[e];
+        }
         if constexpr (BROW) {
           const int col = wn * WM + f * 16 + li;
 #pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            br[f][e] = sB[st][0][(h * 4 + 2 * hf + e) * LDJ + col];
-            bi_[f][e] = sB[st][1][(h * 4 + 2 * hf + e) * LDJ + col];
+          for (int e = 0; e < E; ++e) {
+            br[f][e] = sB[st][0][(h * 2 * E + hf * E + e) * LDJ + col];
+            bi_[f][e] = sB[st][1][(h * 2 * E + hf * E + e) * LDJ + col];
           }
         } else {
           const int rb_ = wn * WM + f * 16 + li;
-          const int om = rb_ * LDK + 2 * ((2 * h + hf) ^ f64_swz(rb_));
-          const doublex2 z = *reinterpret_cast<const doublex2 *>(&sB[st][0][om]);
-          const doublex2 w = *reinterpret_cast<const doublex2 *>(&sB[st][1][om]);
-          br[f][0] = z[0]; br[f][1] = z[1];
-          bi_[f][0] = w[0]; bi_[f][1] = w[1];
+          const int om = rb_ * LDK + E * ((2 * h + hf) ^ f64_swz(rb_));
+          const vec z = *reinterpret_cast<const vec *>(&sB[st][0][om]);
+          const vec w = *reinterpret_cast<const vec *>(&sB[st][1][om]);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            br[f][e] = z[e];
+            bi_[f][e] = w[e];
+          }
         }
       }
-      double as_[F][2], bs_[F][2];
+      T as_[F][E], bs_[F][E];
 #pragma unroll
       for (int f = 0; f < F; ++f)
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < E; ++e) {
           as_[f][e] = opsum_a<OPS>(ar[f][e], ai[f][e]);
           bs_[f][e] = opsum_b<OPS>(br[f][e], bi_[f][e]);
         }
 #pragma unroll
-      for (int e = 0; e < 2; ++e)
+      for (int e = 0; e < E; ++e)
 #pragma unroll
         for (int a = 0; a < F; ++a)
 #pragma unroll
@@ -704,7 +728,7 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
-  doublex4 cr[F][F], ci[F][F];
+  acc4 cr[F][F], ci[F][F];
 #pragma unroll
   for (int a = 0; a < F; ++a)
 #pragma unroll
@@ -717,18 +741,19 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
       for (int b = 0; b < F; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int o = (wm * WM + a * 16 + h + 4 * r) * BM + wn * WM + b * 16 + li;
+          const int o = (wm * WM + a * 16 + s_row<T>(h, r)) * BM + wn * WM + b * 16 + li;
           part[o] = cr[a][b][r];
           part[BM * BM + o] = ci[a][b][r];
         }
     return;
   }
-  const bool has_x = p.beta != 0.0;
-  constexpr bool kCanFold = FOLD && 2 * BM * (BM + 1) + 2 * BM <= cgemm_f64_smem<BM, OPS>();
+  const bool has_x = p.beta != T(0);
+  constexpr bool kCanFold =
+      FOLD && 2 * BM * (BM + 1) + 2 * BM * int(sizeof(double) / sizeof(T)) <= cgemm_s_smem<T, BM, OPS>();
   const bool fold = kCanFold && p.fold_d != nullptr;
-  double (*f_re)[BM + 1] = reinterpret_cast<double (*)[BM + 1]>(smem);
-  double (*f_im)[BM + 1] = reinterpret_cast<double (*)[BM + 1]>(smem + BM * (BM + 1));
-  double *f_d = smem + 2 * BM * (BM + 1);
+  T (*f_re)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
+  T (*f_im)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem + BM * (BM + 1));
+  double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
   const bool scaled = p.scale != nullptr;
   const double sc = scaled ? *p.scale : 1.0;
   if (fold) {
@@ -746,13 +771,13 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
       const int64_t col = int64_t(bj) * BM + cl;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rl = wm * WM + a * 16 + h + 4 * r;
+        const int rl = wm * WM + a * 16 + s_row<T>(h, r);
         const int64_t row = int64_t(bi) * BM + rl;
         const int64_t o = row * ld + col;
-        double vr, vi;
+        T vr, vi;
         epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
         if (fold) {
-          fold_elem<double, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
+          fold_elem<T, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
         } else {
           p.c_re[o] = vr;
           p.c_im[o] = vi;
@@ -762,8 +787,14 @@ __device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int b
   }
   if (fold) {
     __syncthreads();
-    fold_mirror<double, BM>(p, bi, bj, f_re, f_im);
+    fold_mirror<T, BM>(p, bi, bj, f_re, f_im);
   }
+}
+
+template <int BM, int OPS, bool FOLD = false>
+__device__ __forceinline__ void cgemm_f64_tile(const CgemmArgs<double> &p, int bi, int bj, double *smem,
+                                               int kb = 0, int ke = -1, double *part = nullptr) {
+  cgemm_s_tile<double, BM, OPS, FOLD>(p, bi, bj, smem, kb, ke, part);
 }
 
 }  // namespace qme

@@ -46,12 +46,20 @@ void pick_tiles(qme_ctx *c) {
   // beat 128 x 128 (one wave per SIMD) on both products, and 32 x 32 FP64
   // tiles beat 64 x 64.  The padded leading dimension is a multiple of the
   // tile; qme_set_tiles may pick a larger tile when it divides ld.
+  // FP32 systems whose full product in 64-tiles would leave fewer than four
+  // workgroups per compute unit take 32-tiles: four times as many
+  // workgroups, which beat the larger tiles' operand reuse up to N = 1152
+  // and lose to it at N = 2048 (ld stays a multiple of 64, so every FP32
+  // tile edge divides it).
+  const int64_t rows64 = round_up(c->n, 64) / 64;
   if (c->precision == QME_FP64) {
+    c->tile1 = c->tile2 = 32;
+  } else if (c->precision == QME_FP32 && rows64 * rows64 < 4 * int64_t(c->cus)) {
     c->tile1 = c->tile2 = 32;
   } else {
     c->tile1 = c->tile2 = 64;
   }
-  c->ld = round_up(c->n, std::max(c->tile1, c->tile2));
+  c->ld = round_up(c->n, c->precision == QME_FP64 ? std::max(c->tile1, c->tile2) : 64);
 }
 
 size_t plane_elems(const qme_ctx *c) { return size_t(c->ld) * size_t(c->ld); }
@@ -86,19 +94,26 @@ static hipError_t mark(qme_ctx *c, hipStream_t s, int kind) {
 // their tiles, FP32 and FP64 contexts); the partials need their own slots.
 // Room for the largest plan over the tile edges the context may be set to,
 // at most 12 planes.
+// K tile (elements of k per iteration) of a product tile body
+static int k_tile(const qme_ctx *c, int tile) {
+  if (c->precision == QME_BF16X3) return 32;
+  return c->precision == QME_FP32 && tile == 32 ? 32 : 16;
+}
+
 static bool small_split_applies(const qme_ctx *c) {
   return c->precision != QME_BF16X3 && c->tail_split;
 }
 
 static size_t small_split_elems(const qme_ctx *c) {
   if (c->precision == QME_BF16X3) return 0;
-  const int edges[2] = {c->precision == QME_FP64 ? 32 : 64, c->precision == QME_FP64 ? 64 : 128};
+  const std::vector<int> edges =
+      c->precision == QME_FP64 ? std::vector<int>{32, 64} : std::vector<int>{32, 64, 128};
   size_t need = 0;
   for (int bm : edges) {
     if (c->ld % bm != 0) continue;
     const int t = int(c->ld / bm);
     for (int blocks : {t * t, t * (t + 1) / 2}) {
-      const SplitPlan sp = plan_small_split(blocks, bm, 16, c->ld, c->cus, SIZE_MAX);
+      const SplitPlan sp = plan_small_split(blocks, bm, k_tile(c, bm), c->ld, c->cus, SIZE_MAX);
       need = std::max(need, size_t(blocks) * sp.split * 2 * bm * bm);
     }
   }
@@ -116,7 +131,7 @@ static void plan_product(const qme_ctx *c, CgemmArgs<T> &g, int tile, bool lower
   const int t = int(c->ld / tile);
   const int blocks = lower ? t * (t + 1) / 2 : t * t;
   if (area && small_split_applies(c)) {
-    const SplitPlan sp = plan_small_split(blocks, tile, 16, c->ld, c->cus, c->split_elems);
+    const SplitPlan sp = plan_small_split(blocks, tile, k_tile(c, tile), c->ld, c->cus, c->split_elems);
     if (sp.split > 1) {
       g.full = sp.full;
       g.split = sp.split;
@@ -125,8 +140,7 @@ static void plan_product(const qme_ctx *c, CgemmArgs<T> &g, int tile, bool lower
     }
   }
   if (!lower) return;
-  const int kt = c->precision == QME_BF16X3 ? 32 : 16;
-  const SplitPlan sp = plan_tail_split(t, tile, kt, c->ld, c->cus, tail_cap);
+  const SplitPlan sp = plan_tail_split(t, tile, k_tile(c, tile), c->ld, c->cus, tail_cap);
   g.full = sp.full;
   g.split = sp.split;
   g.part = tail_part;
@@ -204,7 +218,7 @@ bool uses_fold(const qme_ctx *c) {
   // BF16X3 keeps the separate decoherence pass: its lower product runs two
   // workgroups per CU, too few to hide the folded epilogue (measured slower)
   if (!c->fold || c->jt.n_gather != 0) return false;
-  if (c->precision == QME_FP32) return c->tile2 == 64;
+  if (c->precision == QME_FP32) return c->tile2 == 64 || c->tile2 == 32;
   return c->precision == QME_FP64;
 }
 
@@ -316,7 +330,6 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
   c->precision = precision;
   c->elem = precision == QME_FP64 ? 8 : 4;
   c->n = c->model.n;
-  pick_tiles(c);
   std::vector<int32_t> r, cc;
   std::vector<double> v;
   hamiltonian_coo(c->model, r, cc, v);
@@ -330,6 +343,7 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
 
   HIP_OK(hipGetDevice(&c->device));
   HIP_OK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  pick_tiles(c);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const size_t pe = plane_elems(c);
   c->split_elems = small_split_elems(c);
@@ -796,7 +810,7 @@ extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
     }
   }
   if (precision == QME_FP32) {
-    if (tile != 128 && tile != 64) { set_error("FP32 tile must be 128 or 64"); return QME_E_ARG; }
+    if (tile != 128 && tile != 64 && tile != 32) { set_error("FP32 tile must be 128, 64 or 32"); return QME_E_ARG; }
     CgemmArgs<float> g{static_cast<const float *>(a_re), static_cast<const float *>(a_im),
                        static_cast<const float *>(m_re), static_cast<const float *>(m_im),
                        static_cast<const float *>(x_re), static_cast<const float *>(x_im),
@@ -868,7 +882,7 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   auto ok = [&](int t) {
     bool valid = c->precision == QME_FP64   ? (t == 64 || t == 32)
-                 : c->precision == QME_FP32 ? (t == 128 || t == 64)
+                 : c->precision == QME_FP32 ? (t == 128 || t == 64 || t == 32)
                                             : t == 64;
     return valid && c->ld % t == 0;
   };

@@ -6,8 +6,9 @@ from paper_2403_07042_amd import autotune as A
 
 
 def test_candidates_respect_ld_and_precision():
-    assert A.candidates("fp32", 2048) == [(64, 64), (64, 128), (128, 64), (128, 128)]
-    assert A.candidates("fp32", 1728) == [(64, 64)]
+    assert A.candidates("fp32", 2048) == [(32, 32), (32, 64), (64, 32), (64, 64), (64, 128),
+                                          (128, 64), (128, 128)]
+    assert A.candidates("fp32", 1728) == [(32, 32), (32, 64), (64, 32), (64, 64)]
     assert A.candidates("fp64", 96) == [(32, 32)]
     assert A.candidates("bf16x3", 2048) == [(64, 64)]
 

@@ -22,7 +22,10 @@ def test_tile_choice_is_bitwise_neutral_and_tuner_picks_valid(precision, tmp_pat
     sol.set_fold(False)          # folding depends on the lower tile; compare tiles alone
     sol.set_split(False)         # so do the k-splits of small launches
     outs = []
-    for tiles in A.candidates(precision, sol.ld):
+    # one matrix-core shape: FP32 64/128-tiles (32x32 MFMA), FP64 32/64 (16x16)
+    same_shape = [t for t in A.candidates(precision, sol.ld)
+                  if precision != "fp32" or 32 not in t]
+    for tiles in same_shape:
         sol.set_tiles(*tiles)
         sol.set_rho(rho0)
         sol.step(20)

@@ -36,6 +36,7 @@ def solo_rho(wl, steps):
     s = P.Solver(wl, "fp32")
     s.set_fold(False)            # the batched step does not fold its decoherence pass
     s.set_split(False)           # nor split its products along k
+    s.set_tiles(64, 64)          # and it runs 64-tiles at every size
     s.set_rho(W.initial_rho(wl, P.basis(wl)))
     s.step(steps)
     rho, sink = s.get_rho()

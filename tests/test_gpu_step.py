@@ -341,7 +341,7 @@ def test_small_launch_split(make, precision, tol):
     occ = P.basis(wl)
     rho0 = W.initial_rho(wl, occ)
     sol = P.Solver(wl, precision)
-    tiles = [(64, 64), (128, 128)] if precision == "fp32" else [(32, 32), (64, 64)]
+    tiles = [(64, 64), (128, 128), (32, 32)] if precision == "fp32" else [(32, 32), (64, 64)]
     outs = {}
     for t in tiles:
         if sol.ld % t[0]:
