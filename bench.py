@@ -36,8 +36,8 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": 372269.5 * 1024,
-                        "sha256": "19e5c1d01bd943a595de202542292f8e38a40521e6cfc9460e61cee1e2194991",
+TRAFFIC_FP32_PRODUCT = {"bytes": 372200.3 * 1024,
+                        "sha256": "ac62a39705ff1c7007f4e7646a95da14839bbffe4bbda0d75d1b06f17f75def9",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
 KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 
