@@ -25,6 +25,10 @@ Paper passages followed:
   probability that a decoherence operator moves out of a truncated basis
   (the "sink") and remove rounding drift of the trace and of Hermiticity.
 
+* Sec. IV.B: the photon plane without leakage is closed, so its state stays
+  pure; ``evolve_pure`` takes the same step on psi (rho = psi psi^dag), the
+  O(N^2)-per-step form of the unitary evolution stage for closed models.
+
 The oracle's propagator comes from an eigendecomposition of H, deliberately
 not the Taylor series the library uses.
 """
@@ -173,6 +177,37 @@ def evolve(sysm: System, rho0, n_steps, sink0=0.0, record_every=0):
         if record_every and k % record_every == 0:
             rec.append((k, rho.copy(), sink))
     return (rho, sink, rec) if record_every else (rho, sink)
+
+
+def is_closed(jumps):
+    """True when no decoherence operator acts on the basis: every channel has
+    rate 0 or a projected A_j and A_j^dag A_j with no non-zero element."""
+    return all(gamma == 0.0 or (a.nnz == 0 and ada.nnz == 0) for gamma, a, ada in jumps)
+
+
+def step_pure(psi, u):
+    """One time step of a closed model in pure-state form.
+
+    Sec. IV.B: the photon on the plane of cavities with no leakage is a
+    closed system, so a pure start stays pure.  With rho_k = psi_k psi_k^dag
+    the step above becomes: rotation U psi psi^dag U^dag; the dissipator and
+    the sink are zero; Herm leaves psi psi^dag unchanged; the trace
+    renormalisation divides by tr = |U psi|^2.  Hence rho_{k+1} =
+    psi_{k+1} psi_{k+1}^dag with psi_{k+1} = U psi_k / |U psi_k| (up to a
+    global phase, which rho does not see)."""
+    y = u @ psi
+    return y / np.linalg.norm(y)
+
+
+def evolve_pure(sysm: System, psi0, n_steps):
+    """n_steps pure-state steps from psi0 ([n]); raises ValueError for a model
+    with decoherence (its state does not stay pure)."""
+    if not is_closed(sysm.jumps):
+        raise ValueError("pure-state steps need a closed model")
+    psi = np.asarray(psi0, dtype=np.complex128).copy()
+    for _ in range(n_steps):
+        psi = step_pure(psi, sysm.u)
+    return psi
 
 
 def observe(rho, sink):
