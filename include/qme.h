@@ -285,6 +285,49 @@ qme_status qme_subspace(const qme_ctx *ctx, const int32_t *keep, int64_t n_keep,
 qme_status qme_compact_state(const qme_ctx *from, const void *state_from_dev,
                              const qme_ctx *to, void *state_to_dev, void *hip_stream);
 
+/* ----------------------------------------------- pure states, closed models */
+
+/* Sec. IV.B: the single photon on the plane of cavities is a closed system
+ * (no leakage), so a pure start stays pure.  For a model with no
+ * decoherence operator acting on its basis the step of qme_step maps
+ * rho = psi psi^dag to psi' psi'^dag with psi' = U psi / |psi| (the
+ * dissipator and the sink are zero, the symmetrisation leaves psi psi^dag
+ * unchanged, the trace renormalisation divides by |psi|^2), so these calls
+ * advance psi instead of rho: O(N^2) work per step instead of O(N^3).
+ *
+ * A pure state of n_vec vectors (1 <= n_vec <= QME_PURE_MAX_VECTORS) is
+ * device memory owned by the caller: the real plane [n_vec][ld] then the
+ * imaginary plane [n_vec][ld] in the context's storage precision (ld from
+ * qme_state_layout, entries >= N zero).  The vectors evolve independently.
+ * FP32 and FP64 contexts only (QME_E_UNSUPPORTED for QME_BF16X3). */
+#define QME_PURE_MAX_VECTORS 4
+
+/* Bytes of a pure state of n_vec vectors and of the workspace qme_pure_step
+ * needs (each a multiple of 256; either pointer may be NULL). */
+qme_status qme_pure_layout(const qme_ctx *ctx, int32_t n_vec, size_t *state_bytes,
+                           size_t *workspace_bytes);
+
+/* Write a pure state from host arrays psi_re / psi_im (n_vec x N, vector v
+ * at [v * N], FP64), converted to the storage precision, padding zeroed.
+ * QME_E_ARG for non-finite values or a zero vector.  Synchronous. */
+qme_status qme_pure_set(const qme_ctx *ctx, void *state_dev, int32_t n_vec,
+                        const double *psi_re, const double *psi_im, void *hip_stream);
+
+/* Read a pure state into host arrays (n_vec x N, FP64; either may be NULL).
+ * Synchronous. */
+qme_status qme_pure_get(const qme_ctx *ctx, const void *state_dev, int32_t n_vec,
+                        double *psi_re, double *psi_im, void *hip_stream);
+
+/* Advance every vector by n_steps steps psi <- (psi + dU psi) / |psi|, with
+ * dU = U - I the context's propagator and |psi| summed in FP64 from the
+ * stored vector; the stored result is U applied to a unit vector.  One
+ * launch per step.  state_dev and workspace_dev (qme_pure_layout bytes)
+ * are 256-byte aligned and do not overlap.  QME_E_STATE when a decoherence
+ * operator acts on the basis (the state would not stay pure).
+ * Asynchronous on hip_stream. */
+qme_status qme_pure_step(qme_ctx *ctx, void *state_dev, int32_t n_vec, int64_t n_steps,
+                         void *workspace_dev, void *hip_stream);
+
 /* ------------------------------------------------------- batched instances */
 
 typedef struct qme_batch qme_batch;

@@ -90,6 +90,12 @@ SIGNATURES = {
     "qme_compact_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qme_profile_enable": (c_int32, [c_void_p, c_int32]),
     "qme_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
+    "qme_pure_layout": (c_int32, [c_void_p, c_int32, POINTER(c_size_t), POINTER(c_size_t)]),
+    "qme_pure_set": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
+                               c_void_p]),
+    "qme_pure_get": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
+                               c_void_p]),
+    "qme_pure_step": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
     "qme_destroy": (None, [c_void_p]),
     "qme_last_error": (c_char_p, []),
     "qme_version": (c_char_p, []),

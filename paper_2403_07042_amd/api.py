@@ -222,6 +222,40 @@ class Solver:
         del buf
         return val.value, grad[:n_par]
 
+    # ------------------------------------------- pure states (closed models)
+    def set_psi(self, psi):
+        """Pure state(s) for a closed model: psi of shape [N] or [n_vec, N]
+        (complex); allocates the pure-state buffer and its workspace."""
+        psi = np.asarray(psi, dtype=np.complex128)
+        vecs = psi.reshape(1, -1) if psi.ndim == 1 else psi
+        if vecs.ndim != 2 or vecs.shape[1] != self.n:
+            raise ValueError("psi must have N entries per vector")
+        self.psi_shape = psi.shape
+        self.n_vec = int(vecs.shape[0])
+        sb, wb = c_size_t(), c_size_t()
+        L.check(self.lib.qme_pure_layout(self.ctx, self.n_vec, byref(sb), byref(wb)))
+        dev = self.state.device
+        self.psi = self.torch.zeros(sb.value, dtype=self.torch.uint8, device=dev)
+        self.psi_workspace = self.torch.zeros(wb.value, dtype=self.torch.uint8, device=dev)
+        re = np.ascontiguousarray(vecs.real)
+        im = np.ascontiguousarray(vecs.imag)
+        L.check(self.lib.qme_pure_set(self.ctx, c_void_p(self.psi.data_ptr()), self.n_vec,
+                                      _dptr(re), _dptr(im), self._sptr()))
+
+    def step_pure(self, n_steps: int):
+        """n_steps steps psi <- U psi / |psi| of every vector (qme_pure_step)."""
+        L.check(self.lib.qme_pure_step(self.ctx, c_void_p(self.psi.data_ptr()), self.n_vec,
+                                       int(n_steps), c_void_p(self.psi_workspace.data_ptr()),
+                                       self._sptr()))
+
+    def get_psi(self):
+        """The pure state(s), in the shape given to set_psi."""
+        re = np.zeros((self.n_vec, self.n))
+        im = np.zeros((self.n_vec, self.n))
+        L.check(self.lib.qme_pure_get(self.ctx, c_void_p(self.psi.data_ptr()), self.n_vec,
+                                      _dptr(re), _dptr(im), self._sptr()))
+        return (re + 1j * im).reshape(self.psi_shape)
+
     # ------------------------------------------------ state-space selection
     def subspace(self, keep) -> "Solver":
         """A solver on the subset `keep` (ascending indices into this basis);

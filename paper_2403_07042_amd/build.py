@@ -28,7 +28,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-munsafe-fp-atomics"]
 
 SOURCES = ["model.cpp", "abi_host.cpp", "ctx.hip", "cgemm.hip", "dissipate.hip", "adjoint.hip",
-           "cgemm_bf16x3.hip", "batch.hip", "small.hip", "select.hip"]
+           "cgemm_bf16x3.hip", "batch.hip", "small.hip", "select.hip", "pure.hip"]
 
 
 def _compile(src: str) -> str:

@@ -153,6 +153,18 @@ struct CompactArgs {
 template <typename T>
 hipError_t launch_compact(const CompactArgs<T> &a, hipStream_t s);
 
+// One pure-state step of a closed model for nv vectors (planar, [nv][ld]):
+// y_v = (x_v + dU x_v) / |x_v| (see pure.hip).  x and y must not overlap.
+template <typename T>
+struct PureArgs {
+  const T *x_re, *x_im;
+  T *y_re, *y_im;
+  const T *u_re, *u_im;   // dU planes, ld x ld
+  int64_t ld, n;
+};
+template <typename T>
+hipError_t launch_pure_step(const PureArgs<T> &a, int nv, hipStream_t s);
+
 // Adjoint of one step's decoherence, fused with the rate-gradient partials.
 //   mu = lam + dt * sum_j gamma_j (A_j^dag lam A_j - 1/2 {A_j^dag A_j, lam})
 // from the lower triangle of the Hermitian lam (written in full), and, with

@@ -172,3 +172,14 @@ def test_knob_setters_reject_null_context():
     for name, arg in (("qme_set_fold", 1), ("qme_set_split", 1), ("qme_set_fused", 1),
                       ("qme_set_direct_loads", -1), ("qme_set_graph", 1)):
         assert getattr(lib, name)(None, arg) == L.QME_E_ARG, name
+
+
+def test_pure_state_calls_reject_null_context():
+    """The pure-state calls validate before touching the device."""
+    from ctypes import byref, c_size_t
+    lib = L.load()
+    sb, wb = c_size_t(), c_size_t()
+    assert lib.qme_pure_layout(None, 1, byref(sb), byref(wb)) == L.QME_E_ARG
+    assert lib.qme_pure_step(None, None, 1, 1, None, None) == L.QME_E_ARG
+    assert lib.qme_pure_set(None, None, 1, None, None, None) == L.QME_E_ARG
+    assert lib.qme_pure_get(None, None, 1, None, None, None) == L.QME_E_ARG

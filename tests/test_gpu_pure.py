@@ -1,0 +1,160 @@
+"""Pure-state steps of closed models (qme_pure_step) against the oracle.
+
+Closed models (Sec. IV.B) keep a pure start pure, and the library then
+advances psi instead of rho.  Parity: the oracle's pure-state step (pinned to
+the sine-mode closed form, the Rabi formula and the density-matrix step) at
+sizes that span one to three column passes of the kernel with a ragged last
+pass, the paper's 81 x 51 plane at full size against the closed form, the
+library's own density-matrix path on the same closed model, and bitwise
+invariances (vector count, split of a run into calls).  FP32: max|d psi| and
+max|d rho| <= 1e-5 after 1000 steps; FP64: 1e-11."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import closed_forms as cf
+from oracle import evolve as ev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2403_07042_amd")
+from paper_2403_07042_amd import _lib as L  # noqa: E402
+
+TOL = {"fp32": 1e-5, "fp64": 1e-11}
+
+
+def closed_tch():
+    return dict(W.tch_2x2(), jumps=[])
+
+
+def lattice(length, height, atoms):
+    return W.photon_lattice(length, height, mu=0.3, g=0.2, gamma=0.0, dt=0.05,
+                            atoms_per_site=atoms, start=(1, 1))
+
+
+CASES = {
+    "lattice_7x5_photon_only": lambda: lattice(7, 5, 0),     # N = 35: one partial pass
+    "tch_2x2_closed": closed_tch,                             # N = 144, Haar-random start
+    "lattice_24x24_atoms": lambda: lattice(24, 24, 1),       # N = 1152: ragged second pass
+}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_pure_matches_oracle(case, precision):
+    wl = CASES[case]()
+    sysm = ev.System(wl)
+    psi0 = W.initial_psi(wl, sysm.occ)
+    steps = 1000
+    print(f"pure {case} N={sysm.n} {precision} {steps} steps", flush=True)
+    sol = P.Solver(wl, precision)
+    sol.set_psi(psi0)
+    sol.step_pure(steps)
+    got = sol.get_psi()
+    sol.close()
+    ref = ev.evolve_pure(sysm, psi0, steps)
+    tol = TOL[precision]
+    assert np.abs(got - ref).max() < tol
+    assert np.abs(np.outer(got, got.conj()) - np.outer(ref, ref.conj())).max() < tol
+    assert abs(np.linalg.norm(got) - 1.0) < tol
+    assert np.abs(got - psi0).max() > 1e-3                  # the state moved
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("start", [(40, 0), (20, 0)])
+def test_pure_photon_plane_4131_against_closed_form(start, precision):
+    """The paper's plane at full size (ld = 4160: five FP32 passes of 1024
+    columns, the last ragged) against the sine-mode closed form."""
+    wl = W.photon_plane(start=start)
+    occ = P.basis(wl)
+    assert occ.shape[0] == 4131
+    sol = P.Solver(wl, precision)
+    sol.set_psi(W.initial_psi(wl, occ))
+    site = np.argmax(occ, axis=1)
+    done = 0
+    for k in (1, 200, 1000):
+        print(f"pure plane {start} {precision}: step {k}", flush=True)
+        sol.step_pure(k - done)
+        done = k
+        psi = sol.get_psi()
+        photon, _ = cf.lattice_amplitudes(81, 51, wl["hops"][0][2], 0.0, wl["omega_c"][0],
+                                          k * wl["dt"], wl["centre_site"], with_atoms=False)
+        ref = photon[site]
+        assert np.abs(psi - ref).max() < TOL[precision], k
+        grid = np.zeros(81 * 51)
+        grid[site] = np.abs(psi) ** 2
+        grid = grid.reshape(81, 51)
+        mirror = np.abs(grid - grid[::-1, :]).max()
+        if start == (40, 0):
+            assert mirror < 10 * TOL[precision]
+        elif k >= 200:
+            assert mirror > 1e-3
+    sol.close()
+
+
+def test_pure_equals_density_path_on_gpu():
+    """The library's two paths on one closed model: rho from qme_step and
+    psi psi^dag from qme_pure_step agree after 500 steps."""
+    wl = closed_tch()
+    occ = P.basis(wl)
+    psi0 = W.initial_psi(wl, occ)
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(np.outer(psi0, psi0.conj()))
+    sol.step(500)
+    rho, sink = sol.get_rho()
+    sol.set_psi(psi0)
+    sol.step_pure(500)
+    psi = sol.get_psi()
+    sol.close()
+    assert sink == 0.0
+    assert np.abs(np.outer(psi, psi.conj()) - rho).max() < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_vectors_independent_and_runs_split_bitwise(precision):
+    """Three vectors at once equal three one-vector runs bitwise, and 13 steps
+    equal 7 + 6 and 1 + 12 steps bitwise (odd counts start from a copy)."""
+    wl = lattice(24, 24, 1)
+    occ = P.basis(wl)
+    rng = np.random.default_rng(11)
+    vecs = rng.standard_normal((3, occ.shape[0])) + 1j * rng.standard_normal((3, occ.shape[0]))
+    sol = P.Solver(wl, precision)
+    print(f"pure three vectors {precision}", flush=True)
+    sol.set_psi(vecs)
+    sol.step_pure(13)
+    together = sol.get_psi()
+    assert together.shape == (3, occ.shape[0])
+    for v in range(3):
+        for parts in ((13,), (7, 6), (1, 12)):
+            sol.set_psi(vecs[v])
+            for k in parts:
+                sol.step_pure(k)
+            assert np.array_equal(sol.get_psi(), together[v]), (v, parts)
+    sol.set_psi(vecs[0])
+    sol.step_pure(0)
+    assert np.array_equal(sol.get_psi(), vecs[0].astype(np.complex64 if precision == "fp32"
+                                                         else np.complex128))
+    sol.close()
+
+
+def test_pure_rejections():
+    lib = L.load()
+    open_model = P.Solver(W.tch_2x2(), "fp32")
+    open_model.set_psi(W.initial_psi(W.tch_2x2(), P.basis(W.tch_2x2())))
+    with pytest.raises(L.QmeError) as e:
+        open_model.step_pure(1)
+    assert "QME_E_STATE" in str(e.value)
+    with pytest.raises(L.QmeError) as e:
+        open_model.set_psi(np.zeros(open_model.n))
+    assert "QME_E_ARG" in str(e.value)
+    with pytest.raises(L.QmeError) as e:
+        open_model.set_psi(np.ones((5, open_model.n)))
+    assert "QME_E_ARG" in str(e.value)
+    open_model.close()
+    b3 = P.Solver(closed_tch(), "bf16x3")
+    with pytest.raises(L.QmeError) as e:
+        b3.set_psi(np.ones(b3.n))
+    assert "QME_E_UNSUPPORTED" in str(e.value)
+    b3.close()
+    assert lib.qme_pure_step(None, None, 1, 1, None, None) == L.QME_E_ARG
