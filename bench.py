@@ -71,6 +71,8 @@ def parse():
                     help="time the state-space selection loop on the N = 2048 lattice (0: skip)")
     ap.add_argument("--plane-steps", type=int, default=100,
                     help="steps timed on the N = 4131 photon plane (0: skip)")
+    ap.add_argument("--pure-steps", type=int, default=2000,
+                    help="steps timed on the N = 4131 plane in pure-state form (0: skip)")
     ap.add_argument("--hb-steps", type=int, default=100,
                     help="steps timed on the N = 4096 hydrogen-bond model (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
@@ -326,6 +328,42 @@ def plane_leg(P, W, torch, steps=100, warmup=5):
             "executed_frac_of_fp32_peak": flops * out["steps_per_s"] / 1e12 / PEAK_FP32_MFMA}
 
 
+def pure_leg(P, W, torch, steps=2000, warmup=20):
+    """The same plane as a pure state (qme_pure_step: psi <- U psi / |psi|,
+    one launch per step), FP32 and FP64: steps/s from HIP events on the
+    launch stream, and the dU bytes each step streams (algorithmic: 2 planes
+    of N x N, the padding columns of each row excluded) against the HBM
+    peak.  The final states are kept (key "_psi") for the parity check of the
+    CPU-baseline leg."""
+    wl = W.photon_plane()
+    occ = P.basis(wl)
+    site = np.argmax(occ, axis=1)
+    psi0 = W.initial_psi(wl, occ)
+    out = {"workload": "photon_plane_81x51_n4131_pure_state", "steps": steps}
+    for prec in ("fp32", "fp64"):
+        sol = P.Solver(wl, prec)
+        sol.set_psi(psi0)
+        sol.step_pure(warmup)
+        sol.set_psi(psi0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        sol.step_pure(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        us = 1e3 * e0.elapsed_time(e1) / steps
+        per_step = 2.0 * sol.elem * sol.n * sol.n
+        out[prec] = {"steps_per_s": steps / wall, "us_per_step": us,
+                     "du_bytes_per_step": per_step,
+                     "achieved_tb_s": per_step / (us * 1e-6) / 1e12,
+                     "frac_of_hbm_peak": per_step / (us * 1e-6) / 1e9 / PEAK_HBM,
+                     "_psi": (sol.get_psi(), site, wl)}
+        sol.close()
+    return out
+
+
 def hydrogen_bond_leg(P, torch, steps=100, warmup=5):
     """The hydrogen-bond model of Sec. IV.A with two bonds (three molecules,
     N = 4096), built as a general-form model: FP32 steps/s, and the basis
@@ -356,10 +394,11 @@ def hydrogen_bond_leg(P, torch, steps=100, warmup=5):
             "selected_basis_after_200_steps": sizes}
 
 
-def cpu_baseline(W, wl, gpu_leg, steps):
+def cpu_baseline(W, wl, gpu_leg, steps, pure=None):
     """The CPU oracle (NumPy complex128) timed on the host cores on a bounded
     sample of the same workload, plus the parity of the GPU run's final
-    populations with the lattice's closed form."""
+    populations with the lattice's closed form (and of the pure-state plane
+    runs, when given, with the plane's closed form)."""
     from oracle import closed_forms as cf
     from oracle import evolve as ev
     blas = "unknown"
@@ -405,6 +444,14 @@ def cpu_baseline(W, wl, gpu_leg, steps):
         dpop = float(np.abs(gpu_leg["pops"] - np.real(np.diag(ref))).max())
         parity = {"after_steps": k, "max_abs_dpop_vs_closed_form": dpop,
                   "trace_error": abs(gpu_leg["trace"] - (1.0 - gpu_leg["sink"]))}
+    if pure is not None:
+        import numpy as np
+        for prec in ("fp32", "fp64"):
+            psi, site, pwl = pure[prec].pop("_psi")
+            photon, _ = cf.lattice_amplitudes(81, 51, pwl["hops"][0][2], 0.0, pwl["omega_c"][0],
+                                              pure["steps"] * pwl["dt"], pwl["centre_site"],
+                                              with_atoms=False)
+            pure[prec]["max_abs_dpsi_vs_closed_form"] = float(np.abs(psi - photon[site]).max())
     return base, parity
 
 
@@ -445,6 +492,7 @@ def main():
     configs = configs_leg(P, W, torch) if args.latency else None
     selection = selection_leg(P, W, torch) if args.selection else None
     plane = plane_leg(P, W, torch, args.plane_steps) if args.plane_steps > 0 else None
+    pure = pure_leg(P, W, torch, args.pure_steps) if args.pure_steps > 0 else None
     hbond = hydrogen_bond_leg(P, torch, args.hb_steps) if args.hb_steps > 0 else None
 
     adj = None
@@ -483,7 +531,12 @@ def main():
     cpu, parity = None, None
     if args.cpu_steps > 0:
         gl = {"k": args.steps, **main_leg} if prec == "fp32" else {"k": args.fp64_steps, **main_leg}
-        cpu, parity = cpu_baseline(W, wl, gl, args.cpu_steps)
+        cpu, parity = cpu_baseline(W, wl, gl, args.cpu_steps, pure)
+    if pure is not None:
+        for key in ("fp32", "fp64"):
+            pure[key].pop("_psi", None)
+        pure["speedup_over_density_path_fp32"] = (
+            pure["fp32"]["steps_per_s"] / plane["steps_per_s"] if plane else None)
 
     line = {
         "metric": METRIC,
@@ -517,6 +570,7 @@ def main():
         "other_configs": configs,
         "state_selection": selection,
         "photon_plane": plane,
+        "photon_plane_pure_state": pure,
         "hydrogen_bond": hbond,
     }
     if "bf16x3" in res:

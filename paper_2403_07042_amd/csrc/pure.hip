@@ -33,7 +33,7 @@
 namespace qme {
 
 static constexpr int kPureThreads = 256;   // four rows per workgroup
-static constexpr int kPureLoads = 4;       // 16-byte loads per lane, row plane and pass
+static constexpr int kPureLoads = 2;       // 16-byte loads per lane, row plane and pass
 
 template <typename T>
 struct alignas(16) Pack16 {
@@ -49,7 +49,7 @@ template <typename T, int NV>
 __global__ __launch_bounds__(kPureThreads) void pure_step_kernel(PureArgs<T> p) {
   constexpr int E = 16 / int(sizeof(T));
   constexpr int M = kPureLoads;
-  constexpr int PASS = 64 * E * M;   // columns per pass of a wave: 1024 FP32, 512 FP64
+  constexpr int PASS = 64 * E * M;   // columns per pass of a wave: 512 FP32, 256 FP64
   const int lane = threadIdx.x & 63;
   const int64_t row = int64_t(blockIdx.x) * (kPureThreads / 64) + (threadIdx.x >> 6);
   if (row >= p.ld) return;

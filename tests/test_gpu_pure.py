@@ -3,7 +3,7 @@
 Closed models (Sec. IV.B) keep a pure start pure, and the library then
 advances psi instead of rho.  Parity: the oracle's pure-state step (pinned to
 the sine-mode closed form, the Rabi formula and the density-matrix step) at
-sizes that span one to three column passes of the kernel with a ragged last
+sizes that span one to five column passes of the kernel with a ragged last
 pass, the paper's 81 x 51 plane at full size against the closed form, the
 library's own density-matrix path on the same closed model, and bitwise
 invariances (vector count, split of a run into calls).  FP32: max|d psi| and
@@ -36,7 +36,7 @@ def lattice(length, height, atoms):
 CASES = {
     "lattice_7x5_photon_only": lambda: lattice(7, 5, 0),     # N = 35: one partial pass
     "tch_2x2_closed": closed_tch,                             # N = 144, Haar-random start
-    "lattice_24x24_atoms": lambda: lattice(24, 24, 1),       # N = 1152: ragged second pass
+    "lattice_24x24_atoms": lambda: lattice(24, 24, 1),       # N = 1152: 3 / 5 passes, ragged
 }
 
 
@@ -64,7 +64,7 @@ def test_pure_matches_oracle(case, precision):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("start", [(40, 0), (20, 0)])
 def test_pure_photon_plane_4131_against_closed_form(start, precision):
-    """The paper's plane at full size (ld = 4160: five FP32 passes of 1024
+    """The paper's plane at full size (ld = 4160: nine FP32 passes of 512
     columns, the last ragged) against the sine-mode closed form."""
     wl = W.photon_plane(start=start)
     occ = P.basis(wl)
