@@ -32,7 +32,7 @@
 
 namespace qme {
 
-static constexpr int kPureThreads = 256;   // four rows per workgroup
+static constexpr int kPureThreads = 128;   // two rows per workgroup
 static constexpr int kPureLoads = 2;       // 16-byte loads per lane, row plane and pass
 
 template <typename T>
