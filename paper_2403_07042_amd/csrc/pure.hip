@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ctx.hpp"
@@ -262,6 +263,9 @@ extern "C" qme_status qme_pure_set(const qme_ctx *c, void *state, int32_t n_vec,
   } catch (const std::bad_alloc &) {
     set_error("out of host memory");
     return QME_E_SIZE;
+  } catch (const std::exception &e) {
+    set_error(std::string("internal error: ") + e.what());
+    return QME_E_STATE;
   }
 }
 
@@ -293,6 +297,9 @@ extern "C" qme_status qme_pure_get(const qme_ctx *c, const void *state, int32_t 
   } catch (const std::bad_alloc &) {
     set_error("out of host memory");
     return QME_E_SIZE;
+  } catch (const std::exception &e) {
+    set_error(std::string("internal error: ") + e.what());
+    return QME_E_STATE;
   }
 }
 
@@ -320,5 +327,8 @@ extern "C" qme_status qme_pure_step(qme_ctx *c, void *state, int32_t n_vec, int6
   } catch (const std::bad_alloc &) {
     set_error("out of host memory");
     return QME_E_SIZE;
+  } catch (const std::exception &e) {
+    set_error(std::string("internal error: ") + e.what());
+    return QME_E_STATE;
   }
 }
