@@ -158,3 +158,45 @@ def test_pure_rejections():
     assert "QME_E_UNSUPPORTED" in str(e.value)
     b3.close()
     assert lib.qme_pure_step(None, None, 1, 1, None, None) == L.QME_E_ARG
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_pure_general_form_hydrogen_bond_64_against_oracle(precision):
+    """A context given as matrices (qme_hamiltonian_general): the
+    hydrogen-bond model of Sec. IV.A with its decoherence rates set to zero
+    (closed, N = 64), 1000 pure-state steps against the oracle."""
+    from workloads import hydrogen_bond as hb
+    wl = hb.hb_model(1, gamma_photon=0.0, gamma_phonon=0.0)
+    sysm = ev.GeneralSystem(wl)
+    psi0 = np.zeros(wl["n"], complex)
+    psi0[wl["start"]] = 1.0
+    sol = P.Solver(wl, precision)
+    sol.set_psi(psi0)
+    sol.step_pure(1000)
+    got = sol.get_psi()
+    sol.close()
+    ref = ev.evolve_pure(sysm, psi0, 1000)
+    assert np.abs(got - ref).max() < TOL[precision]
+    assert np.abs(got - psi0).max() > 1e-3
+
+
+def test_pure_general_form_hydrogen_bond_4096_is_product_of_one_bond_runs():
+    """Three molecules (two bonds, N = 4096) closed: the bonds do not
+    interact, so a product start stays the Kronecker product of two N = 64
+    oracle runs (FP32, 400 steps, the full-size general-form context)."""
+    from workloads import hydrogen_bond as hb
+    one = hb.hb_model(1, gamma_photon=0.0, gamma_phonon=0.0)
+    two = hb.hb_model(2, gamma_photon=0.0, gamma_phonon=0.0)
+    a0 = np.zeros(64, complex)
+    a0[one["start"]] = 1.0
+    a = ev.evolve_pure(ev.GeneralSystem(one), a0, 400)
+    psi0 = np.zeros(4096, complex)
+    psi0[two["start"]] = 1.0
+    sol = P.Solver(two, "fp32")
+    assert sol.n == 4096
+    print("pure hydrogen bond 4096 fp32: 400 steps", flush=True)
+    sol.set_psi(psi0)
+    sol.step_pure(400)
+    got = sol.get_psi()
+    sol.close()
+    assert np.abs(got - np.kron(a, a)).max() < 2e-5
