@@ -30,13 +30,6 @@ __device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
   l = __bf16(r2);
 }
 
-__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
-  bf16x8 o;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) o[e] = -v[e];
-  return o;
-}
-
 // acc += x * y over the six significant split products; x[3], y[3] = hi, mid, lo
 __device__ __forceinline__ floatx16 mac3(const bf16x8 *x, const bf16x8 *y, floatx16 acc) {
   acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[1], acc, 0, 0, 0);
@@ -149,9 +142,9 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
     }
   };
 
-  floatx16 cr, ci;
+  floatx16 cr, ci, crn, cin;   // crn / cin: the products of negative sign
 #pragma unroll
-  for (int r = 0; r < 16; ++r) { cr[r] = 0.0f; ci[r] = 0.0f; }
+  for (int r = 0; r < 16; ++r) { cr[r] = 0.0f; ci[r] = 0.0f; crn[r] = 0.0f; cin[r] = 0.0f; }
 
   gload(kb * KT);
   for (int kt = kb; kt < ke; ++kt) {
@@ -174,21 +167,22 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
       }
       // (Ar + i sA Ai)(Br + i sB Bi):
       //   Cr += Ar Br - sA sB Ai Bi,  Ci += sB Ar Bi + sA Ai Br
-      bf16x8 t1[3], t2[3], t3[3];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        t1[t] = CONJA ? neg8(ai[t]) : ai[t];                      // sA Ai
-        t2[t] = (CONJA != CONJB) ? ai[t] : neg8(ai[t]);           // -sA sB Ai
-        t3[t] = CONJB ? neg8(ar[t]) : ar[t];                      // sB Ar
-      }
+      // each product goes to the accumulator of its sign (no operand is
+      // negated); the negative ones are subtracted once after the k loop
       cr = mac3(ar, br, cr);
-      ci = mac3(t1, br, ci);
-      cr = mac3(t2, bim, cr);
-      ci = mac3(t3, bim, ci);
+      if constexpr (!CONJA) ci = mac3(ai, br, ci); else cin = mac3(ai, br, cin);
+      if constexpr (CONJA != CONJB) cr = mac3(ai, bim, cr); else crn = mac3(ai, bim, crn);
+      if constexpr (!CONJB) ci = mac3(ar, bim, ci); else cin = mac3(ar, bim, cin);
       // one k-step's fragments live at a time (hoisting the next step's
       // reads over these products costs 44 registers and a wave per SIMD)
       __builtin_amdgcn_sched_barrier(0);
     }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if constexpr (CONJA == CONJB) cr[r] -= crn[r];
+    if constexpr (CONJA || CONJB) ci[r] -= cin[r];
   }
 
   if (part) {   // raw accumulator of the chunk, tile-local row-major
