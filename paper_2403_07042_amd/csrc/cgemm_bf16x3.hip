@@ -22,6 +22,30 @@ namespace qme {
 
 static constexpr int kThreads3 = 256;
 
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two values rounded to bf16 (nearest even) in one packed conversion;
+// element 0 in the low half.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const float2v v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) {
+  return __builtin_bit_cast(float, u & 0xffff0000u);
+}
+
+// split3 of two values at once, as packed pairs (h, m, l): the same
+// roundings as split3 element by element, one conversion per pair and stage.
+__device__ __forceinline__ void split3_pair(float x0, float x1, uint32_t &h, uint32_t &m,
+                                            uint32_t &l) {
+  h = pack_bf16(x0, x1);
+  const float r0 = x0 - bf16_lo(h), r1 = x1 - bf16_hi(h);
+  m = pack_bf16(r0, r1);
+  l = pack_bf16(r0 - bf16_lo(m), r1 - bf16_hi(m));
+}
+
 __device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
   h = __bf16(x);
   const float r1 = x - float(h);
@@ -126,18 +150,14 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
       __bf16 *base = (o < 2) ? &sA[(o & 1) * 3][0] : &sB[(o & 1) * 3][0];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        bf16x4 vh, vm, vl;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          __bf16 a, b, c;
-          split3(reg[o][q][e], a, b, c);
-          vh[e] = a; vm[e] = b; vl[e] = c;
-        }
+        uint32_t vh[2], vm[2], vl[2];
+        split3_pair(reg[o][q][0], reg[o][q][1], vh[0], vm[0], vl[0]);
+        split3_pair(reg[o][q][2], reg[o][q][3], vh[1], vm[1], vl[1]);
         const int row = q * 32 + lr;
         const int off = row * LDK + slot(row, lk >> 3) + (lk & 7);
-        *reinterpret_cast<bf16x4 *>(base + 0 * BM * LDK + off) = vh;
-        *reinterpret_cast<bf16x4 *>(base + 1 * BM * LDK + off) = vm;
-        *reinterpret_cast<bf16x4 *>(base + 2 * BM * LDK + off) = vl;
+        *reinterpret_cast<uint2 *>(base + 0 * BM * LDK + off) = make_uint2(vh[0], vh[1]);
+        *reinterpret_cast<uint2 *>(base + 1 * BM * LDK + off) = make_uint2(vm[0], vm[1]);
+        *reinterpret_cast<uint2 *>(base + 2 * BM * LDK + off) = make_uint2(vl[0], vl[1]);
       }
     }
   };
