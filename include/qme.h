@@ -189,7 +189,11 @@ qme_status qme_get_state(const qme_ctx *ctx, const void *state_dev,
  * Asynchronous; the workspace must stay allocated until the stream reaches
  * this point.  Between its own kernels the call may keep intermediate
  * values in the state buffer, so the state must not be read by other work
- * on other streams until the stream reaches this point. */
+ * on other streams until the stream reaches this point.
+ * Failure injection for recovery tests: when the environment holds
+ * QME_FAULT_AT_STEP=k at context creation, the call that would take the
+ * context past its k-th step (counted over all qme_step calls) runs up to
+ * that step and returns QME_E_DEVICE; the state then holds rho_k. */
 qme_status qme_step(qme_ctx *ctx, void *state_dev, int64_t n_steps,
                     void *workspace_dev, void *hip_stream);
 

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -330,6 +331,11 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
   c->precision = precision;
   c->elem = precision == QME_FP64 ? 8 : 4;
   c->n = c->model.n;
+  if (const char *f = std::getenv("QME_FAULT_AT_STEP")) {
+    char *end = nullptr;
+    const long long k = std::strtoll(f, &end, 10);
+    if (end != f && *end == '\0' && k >= 0) c->fault_at = k;
+  }
   std::vector<int32_t> r, cc;
   std::vector<double> v;
   hamiltonian_coo(c->model, r, cc, v);
@@ -709,6 +715,16 @@ extern "C" qme_status qme_step(qme_ctx *c, void *state, int64_t n_steps, void *w
     return c->elem == 8 ? step_impl<double>(c, state, n_steps, ws, on)
                         : step_impl<float>(c, state, n_steps, ws, on);
   };
+  if (c->fault_at >= 0 && c->steps_done + n_steps > c->fault_at) {
+    // injected failure: run up to the fault step, then report a device error
+    n_steps = std::max<int64_t>(0, c->fault_at - c->steps_done);
+    const qme_status r = n_steps > 0 ? run(s) : QME_OK;
+    c->steps_done += n_steps;
+    if (r != QME_OK) return r;
+    set_error("injected fault (QME_FAULT_AT_STEP) after step " + std::to_string(c->fault_at));
+    return QME_E_DEVICE;
+  }
+  c->steps_done += n_steps;
   if (!c->use_graph || c->profiling || n_steps == 0) return run(s);
   const auto key = std::make_tuple(n_steps, state, ws);
   auto it = c->graphs.find(key);

@@ -59,6 +59,12 @@ struct qme_ctx {
   double *t_val = nullptr;
   std::vector<int64_t> term_offset;   // host: entries of term p are [off[p], off[p+1])
   int squarings = 0;                  // of the propagator build
+  // failure injection for recovery tests: when QME_FAULT_AT_STEP=k is set in
+  // the environment at context creation, qme_step stops after the context's
+  // k-th step and returns QME_E_DEVICE (-1: off); steps_done counts the
+  // steps qme_step has enqueued on this context
+  int64_t fault_at = -1;
+  int64_t steps_done = 0;
   // a context made by qme_subspace: the kept indices into its parent's basis
   int32_t *parent_keep = nullptr;     // device, [n]
   int64_t parent_n = 0, parent_ld = 0;

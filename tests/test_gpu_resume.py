@@ -76,3 +76,41 @@ def test_split_calls_equal_one_call(precision):
     got = sol.get_rho()
     sol.close()
     assert np.array_equal(got[0], ref[0]) and got[1] == ref[1]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_injected_fault_then_resume(monkeypatch, precision):
+    """QME_FAULT_AT_STEP=40: the 100-step call stops after step 40 with
+    QME_E_DEVICE; the state left behind is the checkpoint, and a fresh
+    context resumed from it matches an uninterrupted run with a call
+    boundary at step 40, bitwise."""
+    from paper_2403_07042_amd import _lib as L
+    wl = W.tch_2x2()
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    monkeypatch.setenv("QME_FAULT_AT_STEP", "40")
+    faulty = P.Solver(wl, precision)
+    monkeypatch.delenv("QME_FAULT_AT_STEP")
+    faulty.set_rho(rho0)
+    faulty.step(25)                                  # below the fault step: runs
+    with pytest.raises(L.QmeError) as e:
+        faulty.step(75)
+    assert "QME_E_DEVICE" in str(e.value) and "injected" in str(e.value)
+    chk, chk_sink = faulty.get_rho()
+    with pytest.raises(L.QmeError):
+        faulty.step(1)                               # stays failed past the fault step
+    faulty.close()
+    ref = P.Solver(wl, precision)
+    ref.set_rho(rho0)
+    ref.step(25)
+    ref.step(15)
+    mid, mid_sink = ref.get_rho()
+    ref.step(60)
+    want, want_sink = ref.get_rho()
+    ref.close()
+    assert np.array_equal(chk, mid) and chk_sink == mid_sink
+    res = P.Solver(wl, precision)
+    res.set_rho(chk, chk_sink)
+    res.step(60)
+    got, got_sink = res.get_rho()
+    res.close()
+    assert np.array_equal(got, want) and got_sink == want_sink
