@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -427,6 +428,8 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
 
   // forward pass with checkpoints; the last segment is run straight into the
   // recompute buffers R / Zs, so it is not recomputed in the backward pass
+  std::optional<TraceRange> phase;   // roctx range of the current phase
+  phase.emplace("qme_adjoint: forward with checkpoints");
   char *R = ws + L.R;
   // the decoherence passes write rows/columns < n only: the padding of the
   // recomputed states must be zero for the products that read them
@@ -481,6 +484,8 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
   ox.direct = ol.direct = og.direct = c->direct;
   ox.cus = ol.cus = og.cus = c->cus;
 
+  phase.reset();
+  phase.emplace("qme_adjoint: backward (segment recompute + adjoint steps)");
   for (int64_t g = L.nseg - 1; g >= 0; --g) {
     const int64_t len = std::min<int64_t>(L.seg, n_steps - g * L.seg);
     if (g + 1 < L.nseg) {   // recompute the segment from its checkpoint
@@ -505,6 +510,8 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
     }
   }
 
+  phase.reset();
+  phase.emplace("qme_adjoint: Frechet finalisation");
   std::vector<double> gam(std::max(1, nj));
   ADJ_OK(hipMemcpyAsync(gam.data(), ggam, sizeof(double) * gam.size(), hipMemcpyDeviceToHost, s));
   const size_t n_terms = c->term_offset.size() - 1;
@@ -613,6 +620,7 @@ extern "C" qme_status qme_adjoint(qme_ctx *c, const void *state0, int64_t n_step
                                   int32_t checkpoint_every, const double *obs, double *value,
                                   double *grad, void *ws, size_t ws_bytes, void *hip_stream) {
   try {
+    TraceRange range("qme_adjoint");
     set_error("");
     if (!c || !state0 || !obs || !grad || !ws) { set_error("NULL argument"); return QME_E_ARG; }
     if (c->model.general) {

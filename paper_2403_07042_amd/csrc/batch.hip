@@ -309,6 +309,7 @@ extern "C" qme_status qme_batch_config(qme_batch *b, int32_t use_graph, int32_t 
 extern "C" qme_status qme_batch_step(qme_batch *b, int64_t n_steps, void *ws, size_t ws_bytes,
                                      void *hip_stream) {
   try {
+    TraceRange range("qme_batch_step");
     set_error("");
     if (!b || !ws) { set_error("NULL argument"); return QME_E_ARG; }
     if (n_steps < 0) { set_error("n_steps < 0"); return QME_E_ARG; }

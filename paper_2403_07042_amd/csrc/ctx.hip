@@ -701,6 +701,7 @@ extern "C" qme_status qme_get_state(const qme_ctx *c, const void *state, double 
 extern "C" qme_status qme_step(qme_ctx *c, void *state, int64_t n_steps, void *ws,
                                void *hip_stream) {
   QME_GUARD_BEGIN
+  TraceRange range("qme_step");
   set_error("");
   if (!c || !state || !ws) { set_error("NULL argument"); return QME_E_ARG; }
   if (n_steps < 0) { set_error("n_steps < 0"); return QME_E_ARG; }

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "model.hpp"
 #include "qme.h"
@@ -86,6 +87,14 @@ struct qme_ctx {
 };
 
 namespace qme {
+// A roctx range over a scope (host side: the enqueue, or the whole call for
+// synchronous entry points), shown by `rocprofv3 --marker-trace`.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 int64_t round_up(int64_t x, int64_t m);
 size_t plane_elems(const qme_ctx *c);
 size_t state_bytes(const qme_ctx *c);

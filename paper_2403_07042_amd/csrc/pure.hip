@@ -306,6 +306,7 @@ extern "C" qme_status qme_pure_get(const qme_ctx *c, const void *state, int32_t 
 extern "C" qme_status qme_pure_step(qme_ctx *c, void *state, int32_t n_vec, int64_t n_steps,
                                     void *ws, void *hip_stream) {
   try {
+    TraceRange range("qme_pure_step");
     set_error("");
     qme_status st = pure_check(c, n_vec);
     if (st != QME_OK) return st;
