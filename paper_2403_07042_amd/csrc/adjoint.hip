@@ -115,7 +115,6 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
         if (u != v) colacc += e;
       }
       const double w2 = (u == v) ? 1.0 : 2.0;
-#pragma unroll
       for (int a = 0; a < kMaxArrival; ++a) {
         if (a >= na) break;
         const int64_t base = int64_t(a0 + a) * n;
@@ -136,7 +135,6 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
   if (first) {
     s_col[r0][c] = colacc;
   }
-#pragma unroll
   for (int a = 0; a < kMaxArrival; ++a) {
     if (a >= na) break;
     const double g = wave_sum(gacc[a]);

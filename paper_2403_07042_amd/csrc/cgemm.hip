@@ -64,7 +64,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
 }
 
 template <int BM, int OPS, bool LOWER>
-__global__ __launch_bounds__(kThreads, BM == 32 ? 5 : 1) void cgemm_f64_kernel(CgemmArgs<double> p) {
+// five waves per SIMD for the 32-tile NT forms (the step's products); the
+// forms reading B by rows need more registers and keep the default bound
+__global__ __launch_bounds__(kThreads, (BM == 32 && !(OPS & kBRow)) ? 5 : 1) void cgemm_f64_kernel(
+    CgemmArgs<double> p) {
   __shared__ double smem[cgemm_f64_smem<BM, OPS>()];
   const TileWork w = tile_work(blockIdx.x, int(p.ld / 16), p.full, p.split);
   int bi, bj;
