@@ -36,8 +36,8 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": 372200.3 * 1024,
-                        "sha256": "ac62a39705ff1c7007f4e7646a95da14839bbffe4bbda0d75d1b06f17f75def9",
+TRAFFIC_FP32_PRODUCT = {"bytes": 372062.4 * 1024,
+                        "sha256": "817676d308099c533e33faca406d5515efcc8898cf832e1519eed89350b1e901",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
 KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 

@@ -64,7 +64,8 @@ def run(prec, ld, n, tile, conj_m, lower, alpha, beta, seed=0, conj_a=False, b_r
 
 
 @pytest.mark.parametrize("ld,n,tile", [(64, 64, 64), (192, 150, 64), (256, 256, 128),
-                                       (512, 500, 128), (384, 333, 64)])
+                                       (512, 500, 128), (384, 333, 64),
+                                       (32, 32, 32), (96, 70, 32), (320, 301, 32)])
 @pytest.mark.parametrize("conj_m", [True, False])
 @pytest.mark.parametrize("lower", [False, True])
 def test_cgemm_fp32(ld, n, tile, conj_m, lower):
@@ -125,7 +126,8 @@ def test_cgemm_accumulate_in_place():
 @pytest.mark.parametrize("ld,n", [(64, 64), (192, 150), (512, 500)])
 @pytest.mark.parametrize("conj_a,conj_b,lower", [(False, True, False), (False, True, True),
                                                  (True, True, False), (False, False, True),
-                                                 (True, False, False)])
+                                                 (True, False, False), (False, False, False),
+                                                 (True, True, True), (True, False, True)])
 def test_cgemm_bf16x3(ld, n, conj_a, conj_b, lower):
     """Split-bf16 products of FP32 operands: accurate to FP32 rounding."""
     err, scale = run(L.BF16X3, ld, n, 64, conj_b, lower, 1.0, 1.0, conj_a=conj_a)
