@@ -424,8 +424,8 @@ qme_status qme_set_fused(qme_ctx *ctx, int32_t enable);
  * after the last step of a qme_step call, by one pass over the state.  This
  * is the renormalisation "folded into the next product" and saves the
  * decoherence pass.  Applies to FP32 contexts whose lower-product tile is 64
- * and to FP64 contexts; results differ from the unfolded step by rounding
- * only.  enable: 0 or 1, else QME_E_ARG. */
+ * or 32, and to FP64 and BF16X3 contexts; results differ from the unfolded
+ * step by rounding only.  enable: 0 or 1, else QME_E_ARG. */
 qme_status qme_set_fold(qme_ctx *ctx, int32_t enable);
 
 /* Tile body of the FP32 products whose second operand is read by rows (all

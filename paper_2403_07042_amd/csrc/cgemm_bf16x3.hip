@@ -74,15 +74,20 @@ __device__ __forceinline__ floatx16 mac3(const bf16x8 *x, const bf16x8 *y, float
 // B 16x32 (lane l: k 8*(l/32)..+7, col l%32), D as for the FP32 32x32 MFMA.
 // PRE: 0 both operands FP32 (split while staged), 1 first operand pre-split
 // (a_split), 2 second operand pre-split (m_split).
-template <bool CONJA, bool CONJB, bool LOWER, int PRE>
+// FOLD: the lower-triangle instantiation may apply the folded decoherence
+// epilogue (CgemmArgs::fold_d), as the FP32 tiles do.
+template <bool CONJA, bool CONJB, bool LOWER, int PRE, bool FOLD = false>
 __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float> p) {
   constexpr int BM = 64;
   constexpr int KT = 32;
   // LDS row (bf16): four 16-byte k-chunks, chunk c of row r at slot c ^ dma_swz(r)
   constexpr int LDK = KT;
   auto slot = [](int row, int c) { return 8 * (c ^ dma_swz(row)); };
-  __shared__ __bf16 sA[6][BM * LDK];
-  __shared__ __bf16 sB[6][BM * LDK];
+  // one block for both operands: after the k loop the folded epilogue stages
+  // its tile there (2 BM (BM + 1) floats and 2 BM doubles, 34 KB of 48 KB)
+  __shared__ __align__(16) __bf16 lds[2][6][BM * LDK];
+  __bf16 (*sA)[BM * LDK] = lds[0];
+  __bf16 (*sB)[BM * LDK] = lds[1];
 
   const int tiles = int(p.ld / BM);
   int bi, bj, kb = 0, ke = int(p.ld / KT);
@@ -205,29 +210,13 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
     if constexpr (CONJA || CONJB) ci[r] -= cin[r];
   }
 
-  if (part) {   // raw accumulator of the chunk, tile-local row-major
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int o = (wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) * BM + wn * 32 + li;
-      part[o] = cr[r];
-      part[BM * BM + o] = ci[r];
-    }
-    return;
-  }
-  const bool has_x = p.beta != 0.0f;
-  const int64_t col = int64_t(bj) * BM + wn * 32 + li;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int64_t row = int64_t(bi) * BM + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-    const int64_t o = row * ld + col;
-    float vr = p.alpha * cr[r], vi = p.alpha * ci[r];
-    if (has_x) {
-      vr += p.beta * p.x_re[o];
-      vi += p.beta * p.x_im[o];
-    }
-    p.c_re[o] = vr;
-    p.c_im[o] = vi;
-  }
+  // raw chunk partials, C = alpha acc + beta X, the FP64 scale or the folded
+  // decoherence step: the FP32 tiles' epilogue (the 32 x 32 bf16 MFMA leaves
+  // its result in the FP32 32 x 32 MFMA's layout)
+  if (FOLD && p.fold_d && !part) __syncthreads();   // every wave is done with the operand LDS
+  const floatx16 acr[1][1] = {{cr}}, aci[1][1] = {{ci}};
+  f32_tile_epilogue<BM, kConjB, FOLD, 1, 32>(p, bi, bj, reinterpret_cast<float *>(&lds[0][0][0]),
+                                             acr, aci, part);
 }
 
 template <typename K>
@@ -248,13 +237,15 @@ static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipSt
 
 hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s) {
   if (a.ld % 64 != 0 || o.b_rows) return hipErrorInvalidValue;
+  // the folded epilogue exists for the step's lower-triangle product only
+  if (a.fold_d && !(o.lower && a.m_split)) return hipErrorInvalidValue;
   if (a.a_split && a.m_split) return hipErrorInvalidValue;
   if (a.a_split || a.m_split) {
     // the two forward products of a step: T = rho + dU rho^H-form (dU
     // pre-split as A) and rho_u = T + T conj(dU) (dU pre-split as M)
     if (o.conj_a || !o.conj_b) return hipErrorInvalidValue;
     if (a.a_split && !o.lower) return launch3(cgemm_bf16x3_kernel<false, true, false, 1>, a, false, s);
-    if (a.m_split && o.lower) return launch3(cgemm_bf16x3_kernel<false, true, true, 2>, a, true, s);
+    if (a.m_split && o.lower) return launch3(cgemm_bf16x3_kernel<false, true, true, 2, true>, a, true, s);
     return hipErrorInvalidValue;
   }
   const int code = (o.conj_a ? 4 : 0) | (o.conj_b ? 2 : 0) | (o.lower ? 1 : 0);

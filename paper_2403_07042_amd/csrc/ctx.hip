@@ -216,11 +216,9 @@ bool uses_small_path(const qme_ctx *c) {
 // onto another (no gather channels: the decoherence step is a factor per
 // element), in FP32 with 64-tiles for the lower product or in FP64.
 bool uses_fold(const qme_ctx *c) {
-  // BF16X3 keeps the separate decoherence pass: its lower product runs two
-  // workgroups per CU, too few to hide the folded epilogue (measured slower)
   if (!c->fold || c->jt.n_gather != 0) return false;
   if (c->precision == QME_FP32) return c->tile2 == 64 || c->tile2 == 32;
-  return c->precision == QME_FP64;
+  return c->precision == QME_FP64 || c->precision == QME_BF16X3;
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -268,9 +266,18 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     o2.lower = true;
     o1.direct = o2.direct = c->direct;
     o1.cus = o2.cus = c->cus;
+    if (c->precision == QME_BF16X3) {
+      // dU pre-split for both products, as in step_once
+      g1.a_split = c->du_split;
+      g2.m_split = c->du_split;
+    }
     auto gemm = [&](const CgemmArgs<T> &g, int tile, const GemmOps &o) {
-      if constexpr (sizeof(T) == 4) return launch_cgemm_f32(g, tile, o, s);
-      else return launch_cgemm_f64(g, tile, o, s);
+      if constexpr (sizeof(T) == 4) {
+        if (c->precision == QME_BF16X3) return launch_cgemm_bf16x3(g, o, s);
+        return launch_cgemm_f32(g, tile, o, s);
+      } else {
+        return launch_cgemm_f64(g, tile, o, s);
+      }
     };
     hipError_t e = mark(c, s, -1);
     if (e == hipSuccess) e = gemm(g1, c->tile1, o1);
