@@ -210,13 +210,39 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
     if constexpr (CONJA || CONJB) ci[r] -= cin[r];
   }
 
-  // raw chunk partials, C = alpha acc + beta X, the FP64 scale or the folded
-  // decoherence step: the FP32 tiles' epilogue (the 32 x 32 bf16 MFMA leaves
-  // its result in the FP32 32 x 32 MFMA's layout)
-  if (FOLD && p.fold_d && !part) __syncthreads();   // every wave is done with the operand LDS
-  const floatx16 acr[1][1] = {{cr}}, aci[1][1] = {{ci}};
-  f32_tile_epilogue<BM, kConjB, FOLD, 1, 32>(p, bi, bj, reinterpret_cast<float *>(&lds[0][0][0]),
-                                             acr, aci, part);
+  if (part) {   // raw accumulator of the chunk, tile-local row-major
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = (wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) * BM + wn * 32 + li;
+      part[o] = cr[r];
+      part[BM * BM + o] = ci[r];
+    }
+    return;
+  }
+  if (p.scale || (FOLD && p.fold_d)) {
+    // the FP64 scale or the folded decoherence step (folded steps): the FP32
+    // tiles' epilogue (the 32 x 32 bf16 MFMA leaves its result in the FP32
+    // 32 x 32 MFMA's layout), once every wave is done with the operand LDS
+    __syncthreads();
+    const floatx16 acr[1][1] = {{cr}}, aci[1][1] = {{ci}};
+    f32_tile_epilogue<BM, kConjB, FOLD, 1, 32>(p, bi, bj, reinterpret_cast<float *>(&lds[0][0][0]),
+                                               acr, aci, nullptr);
+    return;
+  }
+  const bool has_x = p.beta != 0.0f;
+  const int64_t col = int64_t(bj) * BM + wn * 32 + li;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = int64_t(bi) * BM + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+    const int64_t o = row * ld + col;
+    float vr = p.alpha * cr[r], vi = p.alpha * ci[r];
+    if (has_x) {
+      vr += p.beta * p.x_re[o];
+      vi += p.beta * p.x_im[o];
+    }
+    p.c_re[o] = vr;
+    p.c_im[o] = vi;
+  }
 }
 
 template <typename K>
