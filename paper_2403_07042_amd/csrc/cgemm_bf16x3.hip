@@ -222,8 +222,9 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
   if (p.scale || (FOLD && p.fold_d)) {
     // the FP64 scale or the folded decoherence step (folded steps): the FP32
     // tiles' epilogue (the 32 x 32 bf16 MFMA leaves its result in the FP32
-    // 32 x 32 MFMA's layout), once every wave is done with the operand LDS
-    __syncthreads();
+    // 32 x 32 MFMA's layout); the fold stages its tile in the operand LDS
+    // once every wave is done with it
+    if (FOLD && p.fold_d) __syncthreads();
     const floatx16 acr[1][1] = {{cr}}, aci[1][1] = {{ci}};
     f32_tile_epilogue<BM, kConjB, FOLD, 1, 32>(p, bi, bj, reinterpret_cast<float *>(&lds[0][0][0]),
                                                acr, aci, nullptr);
