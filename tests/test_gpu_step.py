@@ -180,6 +180,7 @@ def test_lattice_small_with_sink():
     got = compare(wl, "fp32", [10, 200])
     assert got[200][1] > 1e-3        # population really left through the boundary
     compare(wl, "fp64", [10, 200])
+    compare(wl, "bf16x3", [10, 200])  # folded BF16x3 steps with a real sink
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
