@@ -165,7 +165,7 @@ qme_status qme_state_layout(const qme_ctx *ctx, int64_t *n, int64_t *ld,
 
 /* Device workspace qme_step needs (caller-allocated, 256-byte aligned):
  * four product planes of ld x ld elements, N FP64 values (the diagonal kept
- * by folded steps, qme_set_fold) and, for FP32 and FP64 contexts whose
+ * by folded steps, qme_set_fold) and, for contexts whose
  * products are too small to occupy the device, the partial slots of their
  * k-split (qme_set_split; at most 12 planes, sized for every tile edge
  * qme_set_tiles accepts). */
@@ -395,7 +395,7 @@ qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
  * compute-unit count by a small remainder, the remainder tiles are computed
  * in k-chunks that fill the otherwise idle units, their partials in the
  * output state's planes, which the step overwrites afterwards.  Small-launch
- * split (FP32 and FP64 contexts): a product with at most half as many tiles
+ * split (every precision): a product with at most half as many tiles
  * as compute units has every tile computed in k-chunks of at least two K
  * tiles, their partials in the workspace's slots (qme_workspace_size).  A
  * reduce pass sums each tile's chunks in k order.  Results differ from the

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
   float *part = nullptr;
   {
     int t = blockIdx.x;
-    if (LOWER && p.split > 1 && t >= p.full) {   // k-chunk of a tail tile
+    if (p.split > 1 && t >= p.full) {   // k-chunk of a split tile
       const int q = t - p.full, s = q % p.split, nk = int(p.ld / KT);
       t = p.full + q / p.split;
       kb = s * nk / p.split;
@@ -251,14 +251,14 @@ static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipSt
   const int tiles = int(a.ld / 64);
   int blocks = lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
   if (blocks == 0) return hipSuccess;
-  const bool split = lower && a.split > 1;
+  const bool split = a.split > 1;
   if (split) {
     if (!a.part || a.full < 0 || a.full >= blocks) return hipErrorInvalidValue;
     blocks = a.full + (blocks - a.full) * a.split;
   }
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && split) e = launch_split_reduce(a, 64, true, s);
+  if (e == hipSuccess && split) e = launch_split_reduce(a, 64, lower, s);
   return e;
 }
 

@@ -101,14 +101,12 @@ static int k_tile(const qme_ctx *c, int tile) {
   return c->precision == QME_FP32 && tile == 32 ? 32 : 16;
 }
 
-static bool small_split_applies(const qme_ctx *c) {
-  return c->precision != QME_BF16X3 && c->tail_split;
-}
+static bool small_split_applies(const qme_ctx *c) { return c->tail_split; }
 
 static size_t small_split_elems(const qme_ctx *c) {
-  if (c->precision == QME_BF16X3) return 0;
-  const std::vector<int> edges =
-      c->precision == QME_FP64 ? std::vector<int>{32, 64} : std::vector<int>{32, 64, 128};
+  const std::vector<int> edges = c->precision == QME_FP64   ? std::vector<int>{32, 64}
+                                 : c->precision == QME_FP32 ? std::vector<int>{32, 64, 128}
+                                                            : std::vector<int>{64};
   size_t need = 0;
   for (int bm : edges) {
     if (c->ld % bm != 0) continue;

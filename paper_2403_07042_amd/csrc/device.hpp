@@ -22,7 +22,7 @@ struct GemmOps {
   int direct = 0, cus = 0;
 };
 
-// Split launches (FP32 / FP64; BF16x3: lower-triangle launches only): when
+// Split launches (FP32, FP64 and BF16x3 products): when
 // split > 1, tiles [full, all) are computed in `split` k-chunks each, into
 // partial slots of 2 * tile^2 elements at `part` (re then im, tile-local
 // row-major), and a reduce pass writes C = alpha * (sum of the chunks in

@@ -349,16 +349,20 @@ def test_profile_sampling_stride():
     (W.tch_2x2, "fp64", 1e-12),
     (lambda: W.photon_lattice(16, 16, gamma=0.05), "fp32", 1e-5),   # N = 512, folded steps
     (lambda: W.photon_lattice(16, 16, gamma=0.05), "fp64", 1e-12),
+    (W.tch_2x2, "bf16x3", 1e-5),
+    (lambda: W.photon_lattice(16, 16, gamma=0.05), "bf16x3", 1e-5),
 ])
 def test_small_launch_split(make, precision, tol):
     """Products too small to occupy the device are cut along k: the split
     step against the unsplit one and (N = 144) the oracle, over several
-    qme_step calls, with 64- and 128-tiles (FP32) or 32- and 64-tiles (FP64)."""
+    qme_step calls, with 64- and 128-tiles (FP32), 32- and 64-tiles (FP64) or
+    64-tiles (BF16x3)."""
     wl = dict(make(), init={"kind": "haar", "seed": 11})
     occ = P.basis(wl)
     rho0 = W.initial_rho(wl, occ)
     sol = P.Solver(wl, precision)
-    tiles = [(64, 64), (128, 128), (32, 32)] if precision == "fp32" else [(32, 32), (64, 64)]
+    tiles = {"fp32": [(64, 64), (128, 128), (32, 32)], "fp64": [(32, 32), (64, 64)],
+             "bf16x3": [(64, 64)]}[precision]
     outs = {}
     for t in tiles:
         if sol.ld % t[0]:
