@@ -11,7 +11,7 @@
  *                                 - 1/2 {A_j^dag A_j, rho}).
  *
  * The calls follow the paper's modelling scheme (Sec. II): fix the basis of
- * "matter + field" states (qme_basis), build the Hamiltonian and the
+ * joint atom and photon states (qme_basis), build the Hamiltonian and the
  * decoherence operators (qme_hamiltonian), solve the equation by repeated
  * time steps (qme_step; the "Taylor approximation" stage builds the
  * propagator once, the "unitary evolution" stage applies it, Sec. IV.B,
@@ -147,9 +147,18 @@ qme_status qme_propagator_host(const qme_system *sys, const qme_params *par,
 
 /* ------------------------------------------------------------- with a GPU */
 
-/* Build a context on the current HIP device: basis, Hamiltonian, FP64
+/* Sec. II, first two points of the modelling scheme (the basis of joint
+ * atom and photon states, then the Hamiltonian and the decoherence
+ * operators), with
+ * the Hamiltonian of Sec. IV.A Eq. 8b / Sec. IV.B Eq. 12 and the "Taylor
+ * approximation" stage of Sec. IV.B, Table III (the propagator, built once).
+ * Build a context on the current HIP device: basis, Hamiltonian, FP64
  * propagator (Taylor stage), decoherence tables, and the device copies of
- * the propagator in the arithmetic of `precision`.  Synchronous. */
+ * the propagator in the arithmetic of `precision`.  Synchronous.
+ * Errors: QME_E_ARG (invalid system or parameters, unknown precision),
+ * QME_E_SIZE (basis larger than 2^20 states), QME_E_NUMERIC (propagator not
+ * finite), QME_E_DEVICE (a HIP call failed); *out is NULL on error and owns
+ * nothing.  The context owns its device tables until qme_destroy. */
 qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
                            int32_t precision, void *hip_stream, qme_ctx **out);
 
@@ -183,7 +192,10 @@ qme_status qme_get_state(const qme_ctx *ctx, const void *state_dev,
                          double *rho_re, double *rho_im, double *sink,
                          void *hip_stream);
 
-/* Advance the state by n_steps >= 0 time steps on hip_stream.  The state
+/* Sec. II, third point (solving the master equation of Eqs. 2-3 by
+ * repeated time steps) and the "unitary evolution" stage of Sec. IV.B,
+ * Table III (U rho U^dag applied every step).
+ * Advance the state by n_steps >= 0 time steps on hip_stream.  The state
  * buffer holds rho_{k+n} afterwards (never a pending scale: folded steps
  * apply their last renormalisation before the call's work ends).
  * Asynchronous; the workspace must stay allocated until the stream reaches
@@ -197,12 +209,22 @@ qme_status qme_get_state(const qme_ctx *ctx, const void *state_dev,
 qme_status qme_step(qme_ctx *ctx, void *state_dev, int64_t n_steps,
                     void *workspace_dev, void *hip_stream);
 
-/* Populations p_s = Re rho_ss (FP64, [N] or NULL), trace sum_s p_s and sink
+/* The probabilities of basis states plotted in Figs. 4-8 (Sec. IV) and the
+ * trace that the renormalisation of Sec. III.B keeps at 1 - sink.
+ * Populations p_s = Re rho_ss (FP64, [N] or NULL), trace sum_s p_s and sink
  * (each may be NULL).  Synchronous.  Returns QME_E_NUMERIC when a population
  * is not finite or the trace is not positive (outputs still written). */
 qme_status qme_observe(const qme_ctx *ctx, const void *state_dev,
                        double *populations, double *trace, double *sink,
                        void *hip_stream);
+
+/* The objective of a parameter fit (Sec. II, fourth point): a weighted sum
+ * of final populations, f = sum_s weights[s] Re rho_ss (weights: host [N],
+ * finite, else QME_E_ARG), summed in FP64 in index order on the host from
+ * the device diagonal, exactly as qme_adjoint forms its *value.  *value is
+ * written; QME_E_NUMERIC when it is not finite.  Synchronous. */
+qme_status qme_observe_weighted(const qme_ctx *ctx, const void *state_dev,
+                                const double *weights, double *value, void *hip_stream);
 
 /* Gradients of a final diagonal observable f = sum_s obs[s] Re rho_K[s,s]
  * (rho_K: the state after n_steps steps from state0) with respect to the

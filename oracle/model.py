@@ -2,7 +2,7 @@
 
 Paper passages followed:
 
-* Sec. II, first point: a basis of "matter + field" states and the matrix of
+* Sec. II, first point: a basis of joint atom and photon states and the matrix of
   the Hamiltonian H.
 * Sec. IV.A, Eq. 8b: the resonant Jaynes-Cummings form
   omega (a^dag a + sigma^dag sigma) + g (a sigma^dag + a^dag sigma).

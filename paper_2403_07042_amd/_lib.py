@@ -63,6 +63,8 @@ SIGNATURES = {
     "qme_step": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "qme_observe": (c_int32, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
                               POINTER(c_double), c_void_p]),
+    "qme_observe_weighted": (c_int32, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
+                                       c_void_p]),
     "qme_cgemm": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32, c_int32,
                             c_int32, c_int32, c_int32, c_void_p]),

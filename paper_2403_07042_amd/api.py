@@ -200,6 +200,18 @@ class Solver:
                                      byref(tr), byref(sink), self._sptr()))
         return pops, tr.value, sink.value
 
+    def observe_weighted(self, weights, state=None) -> float:
+        """f = sum_s weights[s] Re rho_ss in FP64 (qme_observe_weighted: the
+        objective qme_adjoint differentiates, summed the same way)."""
+        st = self.state if state is None else state
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        if w.shape != (self.n,):
+            raise ValueError("weights must have one entry per basis state")
+        val = c_double()
+        L.check(self.lib.qme_observe_weighted(self.ctx, c_void_p(st.data_ptr()), _dptr(w),
+                                              byref(val), self._sptr()))
+        return val.value
+
     def adjoint(self, n_steps: int, obs, checkpoint_every: int = 32, state=None):
         """(f, grad) for f = sum_s obs[s] Re rho_K[s,s] after n_steps from the
         given state (default: this solver's state, left unchanged); grad is

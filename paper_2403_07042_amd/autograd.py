@@ -11,7 +11,6 @@ from __future__ import annotations
 
 import copy
 
-import numpy as np
 import torch
 
 from .api import Solver
@@ -46,8 +45,7 @@ class QMEEvolve(torch.autograd.Function):
         sol.set_rho(rho0)
         state0 = sol.state.clone()
         sol.step(n_steps)
-        pops, _, _ = sol.observe()
-        f = float(np.dot(np.asarray(obs, dtype=np.float64), pops))
+        f = sol.observe_weighted(obs)
         ctx.sol = sol
         ctx.state0 = state0
         ctx.n_steps = n_steps

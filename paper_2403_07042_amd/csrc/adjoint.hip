@@ -638,6 +638,17 @@ extern "C" qme_status qme_adjoint(qme_ctx *c, const void *state0, int64_t n_step
     }
     qme_status st = check_device(c);
     if (st != QME_OK) return st;
+    // the recomputed forward steps are not qme_step's kernels: no profiling
+    // records (and no armed launch timer) during the call
+    struct ProfilingOff {
+      qme_ctx *c;
+      bool was;
+      ~ProfilingOff() {
+        c->profiling = was;
+        launch_timer() = nullptr;
+      }
+    } profiling_off{c, c->profiling};
+    c->profiling = false;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     char *w = static_cast<char *>(ws);
     if (c->elem == 8) return adjoint_impl<double>(c, state0, n_steps, checkpoint_every, obs, value, grad, w, s);

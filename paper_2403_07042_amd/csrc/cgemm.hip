@@ -157,9 +157,8 @@ __global__ __launch_bounds__(256) void apply_scale_kernel(T *re, T *im, int64_t 
 template <typename T>
 hipError_t launch_apply_scale(T *re, T *im, int64_t elems, const double *scale, hipStream_t s) {
   if (elems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(apply_scale_kernel<T>, dim3(unsigned((elems + 255) / 256)), dim3(256), 0, s,
-                     re, im, elems, scale);
-  return hipGetLastError();
+  return launch_kernel(apply_scale_kernel<T>, dim3(unsigned((elems + 255) / 256)), dim3(256), 0, s,
+                       re, im, elems, scale);
 }
 template hipError_t launch_apply_scale<float>(float *, float *, int64_t, const double *, hipStream_t);
 template hipError_t launch_apply_scale<double>(double *, double *, int64_t, const double *,
@@ -193,15 +192,10 @@ SplitPlan plan_small_split(int blocks, int bm, int kt, int64_t ld, int cus, size
 template <typename T, bool LOWER>
 static hipError_t split_reduce_tile(const CgemmArgs<T> &a, int tile, dim3 grid, hipStream_t s) {
   const dim3 block(64);
-  if (tile == 128)
-    hipLaunchKernelGGL((split_reduce_kernel<T, 128, LOWER>), grid, block, 0, s, a);
-  else if (tile == 64)
-    hipLaunchKernelGGL((split_reduce_kernel<T, 64, LOWER>), grid, block, 0, s, a);
-  else if (tile == 32)
-    hipLaunchKernelGGL((split_reduce_kernel<T, 32, LOWER>), grid, block, 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (tile == 128) return launch_kernel(split_reduce_kernel<T, 128, LOWER>, grid, block, 0, s, a);
+  if (tile == 64) return launch_kernel(split_reduce_kernel<T, 64, LOWER>, grid, block, 0, s, a);
+  if (tile == 32) return launch_kernel(split_reduce_kernel<T, 32, LOWER>, grid, block, 0, s, a);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -230,8 +224,7 @@ static hipError_t launch(K kernel, const Args &a, int tile, bool lower, hipStrea
     if (!a.part || a.full < 0 || a.full >= blocks) return hipErrorInvalidValue;
     blocks = a.full + (blocks - a.full) * a.split;
   }
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), 0, s, a);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_kernel(kernel, dim3(blocks), dim3(kThreads), 0, s, a);
   if (e == hipSuccess && split) e = launch_split_reduce(a, tile, lower, s);
   return e;
 }

@@ -256,8 +256,7 @@ static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipSt
     if (!a.part || a.full < 0 || a.full >= blocks) return hipErrorInvalidValue;
     blocks = a.full + (blocks - a.full) * a.split;
   }
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_kernel(kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
   if (e == hipSuccess && split) e = launch_split_reduce(a, 64, lower, s);
   return e;
 }

@@ -74,25 +74,40 @@ qme_status check_device(const qme_ctx *c) {
   return QME_OK;
 }
 
-// Records an event on s after a launch of `kind` (-1 marks the start of a
-// step) when profiling is on and the step is one of the sampled ones.
-static hipError_t mark(qme_ctx *c, hipStream_t s, int kind) {
-  if (!c->profiling) return hipSuccess;
-  if (kind < 0) c->profile_this_step = c->profile_step++ % c->profile_every == 0;
-  if (!c->profile_this_step) return hipSuccess;
-  if (c->events_used == c->events.size()) {
-    hipEvent_t e;
-    hipError_t err = hipEventCreate(&e);
-    if (err != hipSuccess) return err;
-    c->events.push_back(e);
-    c->event_kind.push_back(-1);
-  }
-  c->event_kind[c->events_used] = kind;
-  return hipEventRecord(static_cast<hipEvent_t>(c->events[c->events_used++]), s);
+LaunchTimer *&launch_timer() {
+  static thread_local LaunchTimer *armed = nullptr;
+  return armed;
 }
 
+// Profiling marks of the step path: kind < 0 begins a step and arms the
+// context's timer on this thread when the step is one of the sampled ones
+// (every launch then takes an event pair); kind >= 0 ends a kernel kind:
+// the pairs taken since the previous mark become one record of that kind.
+static hipError_t mark(qme_ctx *c, hipStream_t, int kind) {
+  if (!c->profiling) return hipSuccess;
+  if (kind < 0) {
+    const bool sampled = c->profile_step++ % c->profile_every == 0;
+    c->timer.c = c;
+    launch_timer() = sampled ? &c->timer : nullptr;
+    c->pairs_marked = c->pairs_used;
+    return hipSuccess;
+  }
+  if (c->pairs_used > c->pairs_marked)
+    c->records.push_back({kind, c->pairs_marked, c->pairs_used});
+  c->pairs_marked = c->pairs_used;
+  return hipSuccess;
+}
+
+// Disarms the launch timer when a step driver returns.
+struct TimerScope {
+  TimerScope() = default;
+  TimerScope(const TimerScope &) = delete;
+  TimerScope &operator=(const TimerScope &) = delete;
+  ~TimerScope() { launch_timer() = nullptr; }
+};
+
 // Products whose launches cannot occupy the device are split along k (all
-// their tiles, FP32 and FP64 contexts); the partials need their own slots.
+// their tiles, in every precision); the partials need their own slots.
 // Room for the largest plan over the tile edges the context may be set to,
 // at most 12 planes.
 // K tile (elements of k per iteration) of a product tile body
@@ -286,12 +301,14 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     if (e == hipSuccess) e = mark(c, s, 2);
     if (e != hipSuccess) return e;
   }
+  launch_timer() = nullptr;   // the closing pass is no step's kernel
   return n_steps > 0 ? launch_apply_scale<T>(x_re, x_im, int64_t(pe), aux + 4, s) : hipSuccess;
 }
 
 template <typename T>
 static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
                             hipStream_t s) {
+  const TimerScope timer_scope;
   const size_t pe = plane_elems(c);
   if (!uses_small_path(c) && uses_fold(c)) {
     hipError_t e = fold_steps<T>(c, state, n_steps, ws, s);
@@ -806,6 +823,33 @@ extern "C" qme_status qme_observe(const qme_ctx *c, const void *state, double *p
   QME_GUARD_END
 }
 
+extern "C" qme_status qme_observe_weighted(const qme_ctx *c, const void *state,
+                                           const double *weights, double *value,
+                                           void *hip_stream) {
+  QME_GUARD_BEGIN
+  set_error("");
+  if (!c || !state || !weights || !value) { set_error("NULL argument"); return QME_E_ARG; }
+  for (int64_t u = 0; u < c->n; ++u)
+    if (!std::isfinite(weights[u])) { set_error("weights are not finite"); return QME_E_ARG; }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if (c->elem == 8) e = launch_diag<double>(static_cast<const double *>(state), c->ld, c->n, c->diag, s);
+  else e = launch_diag<float>(static_cast<const float *>(state), c->ld, c->n, c->diag, s);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return QME_E_DEVICE; }
+  std::vector<double> pops(c->n);
+  HIP_OK(hipMemcpyAsync(pops.data(), c->diag, sizeof(double) * c->n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  // the same FP64 sum, in index order, as the objective qme_adjoint returns
+  double f = 0.0;
+  for (int64_t u = 0; u < c->n; ++u) f += weights[u] * pops[u];
+  *value = f;
+  if (!std::isfinite(f)) { set_error("the weighted population is not finite"); return QME_E_NUMERIC; }
+  return QME_OK;
+  QME_GUARD_END
+}
+
 extern "C" qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re,
                                 const void *a_im, const void *m_re, const void *m_im,
                                 const void *x_re, const void *x_im, void *c_re, void *c_im,
@@ -925,9 +969,28 @@ extern "C" qme_status qme_profile_enable(qme_ctx *c, int32_t enable) {
   c->profiling = enable != 0;
   c->profile_every = enable > 0 ? enable : 1;
   c->profile_step = 0;
-  c->profile_this_step = true;
-  c->events_used = 0;
+  c->pairs_used = c->pairs_marked = 0;
+  c->records.clear();
   return QME_OK;
+}
+
+hipError_t qme_ctx::Timer::next_pair(hipEvent_t *start, hipEvent_t *stop) {
+  if (c->pairs_used == c->ev_start.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return e;
+    }
+    c->ev_start.push_back(a);
+    c->ev_stop.push_back(b);
+  }
+  *start = static_cast<hipEvent_t>(c->ev_start[c->pairs_used]);
+  *stop = static_cast<hipEvent_t>(c->ev_stop[c->pairs_used]);
+  ++c->pairs_used;
+  return hipSuccess;
 }
 
 extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *launches) {
@@ -936,16 +999,17 @@ extern "C" qme_status qme_profile_read(qme_ctx *c, double *total_ms, int64_t *la
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
   double ms[4] = {0, 0, 0, 0};
   int64_t cnt[4] = {0, 0, 0, 0};
-  if (c->events_used > 0)
-    HIP_OK(hipEventSynchronize(static_cast<hipEvent_t>(c->events[c->events_used - 1])));
-  for (size_t i = 1; i < c->events_used; ++i) {
-    int k = c->event_kind[i];
-    if (k < 0 || k > 3) continue;
-    float t = 0.0f;
-    HIP_OK(hipEventElapsedTime(&t, static_cast<hipEvent_t>(c->events[i - 1]),
-                               static_cast<hipEvent_t>(c->events[i])));
-    ms[k] += t;
-    cnt[k] += 1;
+  if (c->pairs_used > 0)
+    HIP_OK(hipEventSynchronize(static_cast<hipEvent_t>(c->ev_stop[c->pairs_used - 1])));
+  for (const qme_ctx::ProfileRecord &r : c->records) {
+    if (r.kind < 0 || r.kind > 3) continue;
+    for (size_t i = r.first; i < r.last; ++i) {
+      float t = 0.0f;
+      HIP_OK(hipEventElapsedTime(&t, static_cast<hipEvent_t>(c->ev_start[i]),
+                                 static_cast<hipEvent_t>(c->ev_stop[i])));
+      ms[r.kind] += t;
+    }
+    cnt[r.kind] += 1;
   }
   for (int k = 0; k < 4; ++k) {
     if (total_ms) total_ms[k] = ms[k];
@@ -965,9 +1029,11 @@ void qme_ctx::drop_graphs() {
 }
 
 qme_ctx::~qme_ctx() {
+  if (launch_timer() == &timer) launch_timer() = nullptr;
   drop_graphs();
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
-  for (void *e : events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+  for (void *e : ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+  for (void *e : ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)trw, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,
                   (void *)h_ptr, (void *)h_col, (void *)h_val, (void *)t_row, (void *)t_col,

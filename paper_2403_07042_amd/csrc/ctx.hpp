@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include "device.hpp"
 #include "model.hpp"
 #include "qme.h"
 
@@ -71,14 +72,24 @@ struct qme_ctx {
   int64_t parent_n = 0, parent_ld = 0;
   double h_norm1 = 0.0;               // |H|_1
 
-  // per-kernel timing (qme_profile_enable / qme_profile_read)
+  // per-kernel timing (qme_profile_enable / qme_profile_read): on a sampled
+  // step every launch takes a start / stop event pair that its own dispatch
+  // stamps (qme::launch_kernel); each record groups the pairs of one kernel
+  // kind of one step
   bool profiling = false;
   int profile_every = 1;               // record every profile_every-th step
   int64_t profile_step = 0;            // steps begun since enabling
-  bool profile_this_step = true;
-  std::vector<void *> events;          // hipEvent_t pool
-  size_t events_used = 0;
-  std::vector<int> event_kind;         // kind of the launch ending at event i (-1: start)
+  std::vector<void *> ev_start, ev_stop;   // hipEvent_t pools
+  size_t pairs_used = 0, pairs_marked = 0;
+  struct ProfileRecord {
+    int kind;
+    size_t first, last;                // pairs [first, last)
+  };
+  std::vector<ProfileRecord> records;
+  struct Timer final : qme::LaunchTimer {
+    qme_ctx *c = nullptr;
+    hipError_t next_pair(hipEvent_t *start, hipEvent_t *stop) override;
+  } timer;
 
   qme_ctx() = default;
   qme_ctx(const qme_ctx &) = delete;

@@ -1,11 +1,40 @@
 // Device launchers shared by the context code (internal, not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 namespace qme {
+
+// Per-kernel timing of the step path (qme_profile_enable).  While a timer is
+// armed on the calling thread, every kernel enqueued through launch_kernel
+// takes a fresh start / stop event pair from it and is launched with
+// hipExtLaunchKernel, which stamps the two events with that dispatch's own
+// start and end: a duration is the kernel's execution alone, without the
+// gaps between kernels or extra packets on the stream.
+struct LaunchTimer {
+  virtual hipError_t next_pair(hipEvent_t *start, hipEvent_t *stop) = 0;
+
+ protected:
+  ~LaunchTimer() = default;
+};
+LaunchTimer *&launch_timer();   // the calling thread's armed timer (nullptr: none)
+
+template <typename F, typename... Args>
+inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+                                Args... args) {
+  if (LaunchTimer *t = launch_timer()) {
+    hipEvent_t start = nullptr, stop = nullptr;
+    const hipError_t e = t->next_pair(&start, &stop);
+    if (e != hipSuccess) return e;
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, start, stop, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
+  return hipGetLastError();
+}
 
 // Planar complex GEMM  C = alpha * opA(A) * opB(B) + beta * X  on ld x ld
 // row-major matrices (padding rows/columns zero).  The second operand is

@@ -44,16 +44,14 @@ __global__ void diag_kernel(const T *x_re, int64_t ld, int64_t n, double *out) {
 
 template <typename T>
 hipError_t launch_trace(const DissArgs<T> &a, hipStream_t s) {
-  hipLaunchKernelGGL(trace_kernel<T>, dim3(1), dim3(kTraceThreads), 0, s, a);
-  return hipGetLastError();
+  return launch_kernel(trace_kernel<T>, dim3(1), dim3(kTraceThreads), 0, s, a);
 }
 
 template <typename T>
 hipError_t launch_dissipate(const DissArgs<T> &a, hipStream_t s) {
   const int tiles = int((a.n + TD - 1) / TD);
   const int blocks = tiles * (tiles + 1) / 2;
-  hipLaunchKernelGGL(dissipate_kernel<T>, dim3(blocks), dim3(kDissThreads), 0, s, a);
-  return hipGetLastError();
+  return launch_kernel(dissipate_kernel<T>, dim3(blocks), dim3(kDissThreads), 0, s, a);
 }
 
 template <typename T>

@@ -181,8 +181,7 @@ hipError_t launch_small_steps(const SmallArgs<T> &a, hipStream_t s) {
   for (int64_t done = 0; done < a.steps; done += kSmallStepsPerLaunch) {
     SmallArgs<T> b = a;
     b.steps = std::min<int64_t>(kSmallStepsPerLaunch, a.steps - done);
-    hipLaunchKernelGGL(small_steps_kernel<T>, dim3(1), dim3(kSmallThreads), 0, s, b);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_kernel(small_steps_kernel<T>, dim3(1), dim3(kSmallThreads), 0, s, b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

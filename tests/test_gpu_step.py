@@ -244,7 +244,8 @@ def test_tail_split_of_the_lower_product(precision, tol):
 
 
 @pytest.mark.parametrize("precision,tol,tiles", [("fp64", 1e-12, None), ("fp32", 1e-5, None),
-                                                ("fp64", 1e-12, (64, 64))])
+                                                ("fp64", 1e-12, (64, 64)),
+                                                ("bf16x3", 1e-5, None)])
 def test_folded_steps_match_unfolded(precision, tol, tiles):
     """N = 2048 lattice (every decoherence operator leaves the basis, so the
     decoherence step is a factor per element): folded steps (decoherence in
@@ -299,19 +300,60 @@ def _golden(name):
     return json.load(open(path))
 
 
+def _golden_blocks(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+_CHAIN3_LIVE = {}
+
+
+def chain3_live_oracle():
+    """The N = 1728 chain's oracle states after 1 and 10 steps, computed here
+    (a few seconds of host BLAS), whole."""
+    if not _CHAIN3_LIVE:
+        wl = W.tch_chain3()
+        print("oracle: N = 1728 chain, steps 1 and 10", flush=True)
+        _CHAIN3_LIVE.update(oracle_run(wl, [1, 10]))
+    return _CHAIN3_LIVE
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
-def test_tch_chain3_n1728_against_stored_oracle_run(precision):
+def test_tch_chain3_n1728_against_oracle(precision):
     """Full-size TCH chain (3 cavities x 1 atom, cap 5, N = 1728; dephasing and
-    leaks), 2000 steps, against the oracle run stored by
-    tests/golden/make_golden.py: diagonal and a seeded sample of entries at
-    steps 1, 10, 1000 and 2000."""
+    leaks), 2000 steps, against the oracle: the whole state after 1 and 10
+    steps (oracle computed live), whole 64 x 64 blocks of every tile class
+    (diagonal, interior, the k-split tail of a 64-tile lower-triangle product,
+    the far corner, upper-triangle mirrors) after 1000 and 2000 steps, and the
+    diagonal plus a seeded sample of entries at steps 1, 10, 1000 and 2000
+    (the last two stored by tests/golden/make_golden.py)."""
     gold = _golden("tch_chain3")
+    blocks = _golden_blocks("tch_chain3_blocks")
     wl = W.tch_chain3()
-    assert gold["n"] == 1728
+    assert gold["n"] == 1728 and int(blocks["n"]) == 1728
     pairs = np.array(gold["pairs"])
-    tol = {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 1e-4}[precision]
+    tol = TOL[precision]
     ks = sorted(int(k) for k in gold["records"])
     got = gpu_run(wl, precision, ks)
+    live = chain3_live_oracle()
+    for k, (rref, sref) in live.items():
+        rho, sink, trace = got[k]
+        err = np.abs(rho - rref).max()
+        print(f"chain3 {precision} step {k}: whole state max|drho| = {err:.3e}", flush=True)
+        assert err < tol, (k, err)
+        assert abs(sink - sref) < TRACE_TOL[precision]
+        assert np.array_equal(rho, rho.conj().T)
+    bs = int(blocks["block"])
+    for i, k in enumerate(blocks["steps"]):
+        rho, sink, trace = got[int(k)]
+        for b, (r, c) in enumerate(blocks["block_rc"]):
+            sub = rho[r * bs:(r + 1) * bs, c * bs:(c + 1) * bs]
+            err = np.abs(sub - blocks["blocks"][b, i]).max()
+            assert err < tol, (int(k), (int(r), int(c)), err)
+        assert abs(sink - blocks["sink"][i]) < TRACE_TOL[precision]
+        assert abs(trace - blocks["trace"][i]) < TRACE_TOL[precision]
     for k in ks:
         rec = gold["records"][str(k)]
         rho, sink, trace = got[k]
@@ -321,6 +363,51 @@ def test_tch_chain3_n1728_against_stored_oracle_run(precision):
         assert np.abs(sample - ref).max() < tol
         assert abs(sink - rec["sink"]) < TRACE_TOL[precision]
         assert abs(trace - rec["trace"]) < TRACE_TOL[precision]
+
+
+_LATTICE_ORACLE = {}
+
+
+def leaking_lattice(side):
+    """side x side lattice, one atom per site, boundary leak 0.05 (strong
+    enough that the sink is macroscopic), Haar-random start (the state is
+    dense, so every tile of both products and every row / column factor of
+    the folded epilogue carries weight)."""
+    return dict(W.photon_lattice(side, side, gamma=0.05), init={"kind": "haar", "seed": 21})
+
+
+@pytest.mark.parametrize("side,steps", [(16, 50), (32, 5)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
+def test_leaking_lattice_folded_against_oracle(side, steps, precision):
+    """Multi-tile leaking lattices (N = 512 over 50 steps, N = 2048 over 5
+    steps) on the default path, which folds the decoherence step into the
+    lower-triangle product's epilogue (no decoherence pass runs), against the
+    oracle element by element, with the sink."""
+    wl = leaking_lattice(side)
+    key = (side, steps)
+    if key not in _LATTICE_ORACLE:
+        print(f"oracle: {side} x {side} leaking lattice, {steps} steps", flush=True)
+        _LATTICE_ORACLE[key] = oracle_run(wl, [steps])[steps]
+    rref, sref = _LATTICE_ORACLE[key]
+    sol = P.Solver(wl, precision)
+    sol.set_rho(W.initial_rho(wl, P.basis(wl)))
+    sol.profile(True)
+    print(f"lattice {side}x{side} {precision}: {steps} steps", flush=True)
+    sol.step(steps)
+    torch.cuda.synchronize()
+    counts = [c for _, c in sol.profile_read().values()]
+    sol.profile(False)
+    rho, sink = sol.get_rho()
+    _, trace, _ = sol.observe()
+    sol.close()
+    assert counts == [steps, steps, steps, 0]          # folded: no decoherence pass
+    err = np.abs(rho - rref).max()
+    print(f"lattice {side}x{side} {precision}: max|drho| = {err:.3e}, sink {sink:.6e}", flush=True)
+    assert err < TOL[precision]
+    assert sref > 1e-4                                  # a real sink
+    assert abs(sink - sref) < (1e-12 if precision == "fp64" else 1e-6)
+    assert abs(trace - (1.0 - sink)) < TRACE_TOL[precision]
+    assert np.array_equal(rho, rho.conj().T)
 
 
 def test_profile_sampling_stride():
@@ -344,6 +431,19 @@ def test_profile_sampling_stride():
     sol.close()
 
 
+def small_split_expected(ld, tile, precision, cus):
+    """Whether the small-launch split must cut a product of this tiling: at
+    most half as many tiles as compute units, and at least two chunks of two
+    K tiles (K tile: 32 for BF16x3 and FP32 32-tiles, else 16).  Returns
+    (first product split, lower-triangle product split)."""
+    t = ld // tile
+    kt = 32 if precision == "bf16x3" or (precision == "fp32" and tile == 32) else 16
+
+    def applies(blocks):
+        return 2 * blocks <= cus and min(cus // blocks, (ld // kt) // 2) >= 2
+    return applies(t * t), applies(t * (t + 1) // 2)
+
+
 @pytest.mark.parametrize("make,precision,tol", [
     (W.tch_2x2, "fp32", 1e-5),                                   # N = 144: 9 + 6 tiles
     (W.tch_2x2, "fp64", 1e-12),
@@ -356,18 +456,24 @@ def test_small_launch_split(make, precision, tol):
     """Products too small to occupy the device are cut along k: the split
     step against the unsplit one and (N = 144) the oracle, over several
     qme_step calls, with 64- and 128-tiles (FP32), 32- and 64-tiles (FP64) or
-    64-tiles (BF16x3)."""
+    64-tiles (BF16x3).  Where the split rule applies to a tiling, the split
+    result must differ from the unsplit one (the k sums are regrouped), so a
+    split that silently did not run fails."""
     wl = dict(make(), init={"kind": "haar", "seed": 11})
     occ = P.basis(wl)
     rho0 = W.initial_rho(wl, occ)
     sol = P.Solver(wl, precision)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     tiles = {"fp32": [(64, 64), (128, 128), (32, 32)], "fp64": [(32, 32), (64, 64)],
              "bf16x3": [(64, 64)]}[precision]
     outs = {}
+    ran = []
     for t in tiles:
         if sol.ld % t[0]:
             continue
         sol.set_tiles(*t)
+        if any(small_split_expected(sol.ld, t[0], precision, cus)):
+            ran.append(t)
         for split in (True, False):
             print(f"N={sol.n} {precision} tiles={t} split={split}", flush=True)
             sol.set_split(split)
@@ -378,6 +484,9 @@ def test_small_launch_split(make, precision, tol):
             _, trace, _ = sol.observe()
             outs[(t, split)] = (rho, sink, trace)
     sol.close()
+    assert ran                                   # every case has a tiling the split applies to
+    for t in ran:
+        assert not np.array_equal(outs[(t, True)][0], outs[(t, False)][0]), t
     ref_rho = outs[(tiles[0], False)][0]
     scale = np.abs(ref_rho).max()
     for key, (rho, sink, trace) in outs.items():
