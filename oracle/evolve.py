@@ -63,12 +63,22 @@ class System:
 
 class GeneralSystem:
     """A model given directly as matrices (a general-form workload: real
-    symmetric H as COO triplets, decoherence operators as monomial moves
-    A|source> = coef |target>, target -1 for an image outside the basis),
-    optionally restricted to the states `keep` (indices into its basis).
-    Restriction follows the same reading as the window basis: P H P and
-    P A P on the kept states, A^dag A taken before the projection, so moves
-    onto removed states leave through the sink."""
+    symmetric H as COO triplets, each decoherence operator A_j as moves
+    A|source> = sum of coef |target> over its moves, target -1 for a
+    component outside the basis), optionally restricted to the states
+    `keep` (indices into its basis).
+
+    Sec. II, Eq. 3 puts no restriction on the operators A_j: a state may
+    have several images and several preimages (for example collective
+    decay, A = sum of the lowering operators of several atoms).  Readings:
+    moves with the same (source, target) add up (they are the matrix entries
+    of A); every move with target -1 leads to its own state outside the
+    basis, orthogonal to every other state, so it adds coef^2 to the
+    diagonal of A^dag A and nothing else.  Restriction follows the window
+    basis reading: P A P on the kept states and A^dag A formed from the
+    whole operator before the projection, so probability that an operator
+    moves onto removed states -- including the cross terms of two kept
+    states moving onto the same removed state -- leaves through the sink."""
 
     def __init__(self, wl, keep=None):
         import scipy.sparse as sp
@@ -78,24 +88,24 @@ class GeneralSystem:
         h = sp.coo_matrix((np.asarray(vals, float), (np.asarray(rows), np.asarray(cols))),
                           shape=(n, n)).toarray()
         keep = np.arange(n) if keep is None else np.asarray(keep)
-        pos = -np.ones(n, dtype=np.int64)
-        pos[keep] = np.arange(keep.size)
         self.keep = keep
         self.n = keep.size
         self.h = h[np.ix_(keep, keep)]
         self.jumps = []
         for gamma, src, dst, coef in wl["jumps"]:
-            src, dst, coef = np.asarray(src), np.asarray(dst), np.asarray(coef, float)
-            ada_diag = np.zeros(self.n)
-            r, c, v = [], [], []
-            for a, b, x in zip(src, dst, coef):
-                if pos[a] < 0:
-                    continue
-                ada_diag[pos[a]] += x * x
-                if b >= 0 and pos[b] >= 0:
-                    r.append(pos[b]); c.append(pos[a]); v.append(x)
-            a_mat = sp.csr_matrix((v, (r, c)), shape=(self.n, self.n))
-            self.jumps.append((float(gamma), a_mat, sp.diags(ada_diag).tocsr()))
+            src = np.asarray(src, dtype=np.int64)
+            dst = np.asarray(dst, dtype=np.int64)
+            coef = np.asarray(coef, float)
+            # image rows: the n basis states, then one private row per move
+            # whose image leaves the basis
+            image = np.where(dst >= 0, dst, n + np.arange(dst.size))
+            a_full = sp.csr_matrix((coef, (image, src)), shape=(n + dst.size, n))
+            k_full = (a_full.T @ a_full).tocsr()
+            a_p = a_full[keep][:, keep].tocsr()
+            k_p = k_full[keep][:, keep].tocsr()
+            a_p.eliminate_zeros()
+            k_p.eliminate_zeros()
+            self.jumps.append((float(gamma), a_p, k_p))
         self.dt = float(wl["dt"])
         self.u = propagator(self.h, self.dt)
 

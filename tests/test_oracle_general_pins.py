@@ -113,3 +113,139 @@ def test_hb_oracle_invariants():
     assert np.linalg.eigvalsh(rho).min() > -bound
     probs = hb.bond_probabilities(wl, np.real(np.diag(rho)))
     assert abs(probs.sum() - 1.0) < 1e-13 and 0.0 < probs[1] < 1.0
+
+
+# ------------------------------------------------ non-monomial operators
+# Sec. II, Eq. 3 with operators that give a state several images and
+# several preimages: collective decay A = sigma_0 + sigma_1 of two atoms.
+
+from workloads import collective as CO  # noqa: E402
+
+
+def _proj(rho, vec):
+    return float(np.real(vec.conj() @ rho @ vec))
+
+
+def test_collective_decay_superradiant_and_dark_states():
+    """Two atoms with collective decay: the symmetric one-excitation state
+    decays at twice the single-atom rate, P_S(k) = (1 - 2 gamma dt)^k exactly
+    under the discrete map (A|S> = sqrt 2 |gg>, A^dag A |S> = 2 |S>); the
+    antisymmetric state is dark (A|A> = 0) and does not move; from |ee> the
+    populations follow the three-level cascade ee -> S -> gg at rate
+    2 gamma, stepped here as scalars.  Independent decay of the two atoms
+    (two monomial operators) would give rate gamma and a decaying |A>."""
+    gamma, dt, k = 0.05, 0.01, 200
+    s_vec = np.array([0, 1, 1, 0]) / np.sqrt(2.0)
+    a_vec = np.array([0, -1, 1, 0]) / np.sqrt(2.0)
+    gg = np.array([1, 0, 0, 0.0])
+    ee = np.array([0, 0, 0, 1.0])
+    f = 1.0 - 2.0 * gamma * dt
+    wl, rho0 = CO.dicke_pair(gamma=gamma, dt=dt, start="symmetric")
+    rho, sink = ev.evolve(ev.GeneralSystem(wl), rho0, k)
+    assert abs(_proj(rho, s_vec) - f ** k) < 1e-13
+    assert abs(_proj(rho, gg) - (1.0 - f ** k)) < 1e-13 and abs(sink) < 1e-15
+    wl, rho0 = CO.dicke_pair(gamma=gamma, dt=dt, start="antisymmetric")
+    rho, _ = ev.evolve(ev.GeneralSystem(wl), rho0, k)
+    assert np.abs(rho - rho0).max() < 1e-13
+    wl, rho0 = CO.dicke_pair(gamma=gamma, dt=dt, start="excited")
+    rho, _ = ev.evolve(ev.GeneralSystem(wl), rho0, k)
+    p_ee, p_s, p_gg = 1.0, 0.0, 0.0
+    for _ in range(k):
+        p_ee, p_s, p_gg = f * p_ee, f * p_s + 2 * gamma * dt * p_ee, p_gg + 2 * gamma * dt * p_s
+    assert abs(_proj(rho, ee) - p_ee) < 1e-13
+    assert abs(_proj(rho, s_vec) - p_s) < 1e-13
+    assert abs(_proj(rho, gg) - p_gg) < 1e-13
+    assert abs(_proj(rho, a_vec)) < 1e-13
+
+
+def _dense_operator(n, src, dst, coef):
+    """A with one private row per move leaving the basis (as dense)."""
+    n_out = sum(1 for d in dst if d < 0)
+    a = np.zeros((n + n_out, n))
+    o = n
+    for s, d, c in zip(src, dst, coef):
+        if d >= 0:
+            a[d, s] += c
+        else:
+            a[o, s] += c
+            o += 1
+    return a
+
+
+def test_general_operators_match_kronecker_superoperator():
+    """Random real operators with several images and preimages per state
+    (and components leaving the basis) on N = 5 against the step map built
+    here from dense Kronecker products: vec rho_{k+1} = (I + dt L_D)(U kron
+    conj U) vec rho_k with U = expm(-i H dt) (scipy, not the oracle's
+    eigendecomposition) and L_D from the dense operators.  The oracle's
+    renormalisation is the identity in exact arithmetic, so M^k vec rho_0
+    equals its state after k steps and 1 - its trace equals the sink."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng(20240311 + 40)
+    n, dt, steps = 5, 0.05, 40
+    h = rng.standard_normal((n, n))
+    h = h + h.T
+    r, c = np.nonzero(np.ones((n, n)))
+    jumps = []
+    for _ in range(2):
+        m = 9
+        src = list(rng.integers(0, n, m))
+        dst = list(rng.integers(-1, n, m))
+        coef = list(rng.uniform(0.2, 1.0, m))
+        jumps.append((float(rng.uniform(0.1, 0.5)), src, dst, coef))
+    wl = {"general": True, "name": "random_general", "n": n,
+          "h": (r.astype(np.int32), c.astype(np.int32), h[r, c]), "jumps": jumps, "dt": dt}
+    psi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    psi /= np.linalg.norm(psi)
+    rho0 = np.outer(psi, psi.conj())
+    u = sla.expm(-1j * h * dt)
+    eye = np.eye(n)
+    lsup = np.zeros((n * n, n * n), dtype=np.complex128)
+    for gamma, src, dst, coef in jumps:
+        a_full = _dense_operator(n, src, dst, coef)
+        k_mat = a_full.T @ a_full
+        a_in = a_full[:n]
+        lsup += gamma * (np.kron(a_in, a_in) - 0.5 * (np.kron(k_mat, eye) + np.kron(eye, k_mat.T)))
+    step = (np.eye(n * n) + dt * lsup) @ np.kron(u, u.conj())
+    vec = rho0.reshape(-1)
+    for _ in range(steps):
+        vec = step @ vec
+    ref = vec.reshape(n, n)
+    rho, sink = ev.evolve(ev.GeneralSystem(wl), rho0, steps)
+    assert any(len(set(d for s2, d in zip(s, dd) if s2 == x and d >= 0)) > 1
+               for _, s, dd, _ in jumps for x in set(s))          # several images somewhere
+    assert np.abs(rho - ref).max() < 1e-13
+    assert sink > 1e-3 and abs(sink - (1.0 - np.trace(ref).real)) < 1e-13
+
+
+def test_restricted_operator_books_cross_terms_in_the_sink():
+    """Two kept states that decay onto the same removed state: restricting the
+    basis forms A^dag A before the projection, so the sink takes the
+    coherent cross term 2 c1 c2 Re rho_12 as well.  A removed state that H
+    does not couple to the others and that A does not leave is exactly the
+    sink: the full evolution's block on the kept states and its population
+    of the removed state equal the restricted run's state and sink."""
+    rng = np.random.default_rng(20240311 + 41)
+    n, dt, steps = 4, 0.05, 60
+    h = np.zeros((n, n))
+    blk = rng.standard_normal((3, 3))
+    h[:3, :3] = blk + blk.T
+    h[3, 3] = 0.7
+    r, c = np.nonzero(h)
+    jumps = [(0.3, [1, 2, 0], [3, 3, 1], [0.8, 0.6, 0.5])]
+    wl = {"general": True, "name": "shared_removed_target", "n": n,
+          "h": (r.astype(np.int32), c.astype(np.int32), h[r, c]), "jumps": jumps, "dt": dt}
+    psi = np.zeros(n, dtype=np.complex128)
+    psi[:3] = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    psi /= np.linalg.norm(psi)
+    rho0 = np.outer(psi, psi.conj())
+    full, _ = ev.evolve(ev.GeneralSystem(wl), rho0, steps)
+    part = ev.GeneralSystem(wl, keep=np.array([0, 1, 2]))
+    rho, sink = ev.evolve(part, rho0[:3, :3], steps)
+    assert np.abs(rho - full[:3, :3]).max() < 1e-13
+    assert abs(sink - full[3, 3].real) < 1e-13
+    # the cross term matters here: without it the sink would differ
+    k_diag_only = ev.GeneralSystem(wl, keep=np.array([0, 1, 2]))
+    k_diag_only.jumps = [(g, a, sp.diags(k.diagonal()).tocsr()) for g, a, k in k_diag_only.jumps]
+    _, sink_wrong = ev.evolve(k_diag_only, rho0[:3, :3], steps)
+    assert abs(sink_wrong - sink) > 1e-4
