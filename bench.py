@@ -188,7 +188,10 @@ def adjoint_leg(P, W, torch, wl, steps, every):
 
 def batch_leg(P, W, torch, steps):
     """256 TCH instances (64 each of N = 64, 128, 256, 512), FP32, one graph
-    replay of `steps` batched steps (one launch per phase over all instances)."""
+    replay of `steps` batched steps (one launch per phase over all
+    instances), with the tile edges per size, graph replay and instance
+    order picked by the autotuner first."""
+    from paper_2403_07042_amd import autotune as A
     wls = W.batch_sweep(steps=steps)
     sols = []
     for wl in wls:
@@ -196,7 +199,9 @@ def batch_leg(P, W, torch, steps):
         s.set_rho(W.initial_rho(wl, P.basis(wl)))
         sols.append(s)
     b = P.Batch(sols)
-    b.config(use_graph=True, largest_first=True)
+    (use_graph, largest, per_n), tune = A.tune_batch(b, steps=4, trials=3)
+    for wl, s in zip(wls, sols):
+        s.set_rho(W.initial_rho(wl, P.basis(wl)))
     b.step(steps)                    # capture + warm-up run
     torch.cuda.synchronize()
     for wl, s in zip(wls, sols):
@@ -207,11 +212,23 @@ def batch_leg(P, W, torch, steps):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     flops = sum(16.0 * s.n ** 3 for s in sols)
+    # what the matrix cores execute per batched step: both products of every
+    # instance in the 3M form (6 flop per complex multiply-add) over its padded
+    # ld, the lower product over its lower-triangle tiles
+    executed = 0.0
+    for s in sols:
+        t1_, t2_ = s.tiles
+        k = s.ld // t2_
+        executed += MFMA_FLOP_PER_CMAC * (s.ld ** 3 + s.ld * t2_ * t2_ * k * (k + 1) / 2)
     b.close()
     for s in sols:
         s.close()
     rate = steps / (t1 - t0)
     return {"instances": len(wls), "steps": steps, "batched_steps_per_s": rate,
+            "tuned": {"use_graph": use_graph, "largest_first": largest,
+                      "tiles_per_n": {str(n): list(t) for n, t in sorted(per_n.items())}},
+            "executed_tflops": executed * rate / 1e12,
+            "executed_frac_of_fp32_peak": executed * rate / 1e12 / PEAK_FP32_MFMA,
             "instance_steps_per_s": rate * len(wls), "ms_per_batched_step": 1e3 / rate,
             "dense_equivalent_tflops": flops * rate / 1e12,
             "dense_equivalent_frac_of_fp32_peak": flops * rate / 1e12 / PEAK_FP32_MFMA}

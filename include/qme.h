@@ -358,13 +358,18 @@ qme_status qme_pure_step(qme_ctx *ctx, void *state_dev, int32_t n_vec, int64_t n
 
 typedef struct qme_batch qme_batch;
 
-/* Bind `count` FP32 contexts and their device state buffers (one each,
+/* Sec. II, third point (the time steps), for many independent instances at
+ * once (a parameter sweep).
+ * Bind `count` FP32 contexts and their device state buffers (one each,
  * layouts from qme_state_layout, 256-byte aligned) into a batch.  Each step
  * of the batch is one launch per phase (first product, lower-triangle
  * product, trace/sink pass, decoherence pass) covering the tiles of every
  * instance, largest instances first; a run of n steps is captured once into
- * a hipGraph and replayed.  Each instance advances exactly as under qme_step
- * (the same tile arithmetic: bitwise-identical results).  The contexts and
+ * a hipGraph and replayed.  Each instance's two products run in the tile
+ * edges of its context (qme_set_tiles; 32 or 64, else QME_E_UNSUPPORTED),
+ * read when the batch is created or configured.  Each instance advances
+ * exactly as under qme_step with the same tiles, unfolded and unsplit (the
+ * same tile arithmetic: bitwise-identical results).  The contexts and
  * states must outlive the batch. */
 qme_status qme_batch_create(qme_ctx *const *ctxs, void *const *states_dev, int32_t count,
                             qme_batch **out);
@@ -375,7 +380,9 @@ qme_status qme_batch_workspace_size(const qme_batch *batch, size_t *bytes);
 
 /* Whether runs are captured into (and replayed from) a hipGraph per
  * (n_steps, workspace), and whether larger instances come first in each
- * phase launch.  Synchronises the device. */
+ * phase launch.  Rebuilds the batch's tables from the contexts' current
+ * tiles (set them with qme_set_tiles, then call this) and drops earlier
+ * captures.  Synchronises the device. */
 qme_status qme_batch_config(qme_batch *batch, int32_t use_graph, int32_t largest_first);
 
 /* Advance every instance by n_steps on hip_stream (asynchronous). */
@@ -411,6 +418,10 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
  * FP64 32; FP32 32 when the full product in 64-tiles would give fewer than
  * four workgroups per compute unit, else 64; BF16X3 64. */
 qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
+
+/* The tile edges the context's two products use now (defaults or
+ * qme_set_tiles). */
+qme_status qme_get_tiles(const qme_ctx *ctx, int32_t *tile1, int32_t *tile2);
 
 /* Split of the products along k (on by default).  Tail split: when the
  * lower-triangle product's tile count exceeds a multiple of the device's

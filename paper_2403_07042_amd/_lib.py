@@ -78,6 +78,7 @@ SIGNATURES = {
     "qme_batch_step": (c_int32, [c_void_p, c_int64, c_void_p, c_size_t, c_void_p]),
     "qme_batch_destroy": (None, [c_void_p]),
     "qme_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
+    "qme_get_tiles": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "qme_set_split": (c_int32, [c_void_p, c_int32]),
     "qme_set_fused": (c_int32, [c_void_p, c_int32]),
     "qme_set_fold": (c_int32, [c_void_p, c_int32]),

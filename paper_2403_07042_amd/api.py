@@ -287,6 +287,21 @@ class Solver:
     def set_tiles(self, tile1: int, tile2: int):
         L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
 
+    @property
+    def tiles(self):
+        """(tile1, tile2): the tile edges of the two products."""
+        a, b = c_int32(), c_int32()
+        L.check(self.lib.qme_get_tiles(self.ctx, byref(a), byref(b)))
+        return a.value, b.value
+
+    @property
+    def tile1(self):
+        return self.tiles[0]
+
+    @property
+    def tile2(self):
+        return self.tiles[1]
+
     def set_split(self, enable: bool):
         """k-splits of the products on (default) or off: the tail of the
         lower-triangle product, and every tile of a launch too small for the

@@ -3,7 +3,8 @@
 Knobs: the tile edges of the two products of a step (qme_set_tiles) and the
 k-splits of the products (qme_set_split: the tail of the lower-triangle
 product, every tile of a launch too small for the device) for a single
-instance, and graph replay / instance order for a batch.  Every
+instance; for a batch, the tile edges per instance size (32 or 64 for each
+product), graph replay and instance order.  Every
 candidate is timed on the real step (median of several trials of a few steps,
 on a scratch copy of the state so the caller's state does not advance) and
 the fastest is applied.  Results are cached per (GPU architecture,
@@ -115,17 +116,77 @@ def tune_solver(sol, steps: int = 4, trials: int = 3, use_cache: bool = True,
     return best
 
 
-def tune_batch(batch, steps: int = 2, trials: int = 3):
-    """Pick and apply the fastest (use_graph, largest_first) for a batch.
-    Runs advance the batch's states by the steps timed (callers tune before
-    setting their initial states, or re-set them afterwards)."""
+BATCH_TILES = [(32, 32), (32, 64), (64, 32), (64, 64)]
+
+
+def batch_key(arch: str, batch) -> str:
+    sizes = {}
+    for s in batch.solvers:
+        sizes[s.n] = sizes.get(s.n, 0) + 1
+    mix = ",".join(f"{n}x{c}" for n, c in sorted(sizes.items()))
+    return f"{arch}|batch|fp32|{mix}"
+
+
+def tune_batch(batch, steps: int = 2, trials: int = 3, tiles: bool = True,
+               use_cache: bool = False, path: str | None = None):
+    """Pick and apply the fastest batch configuration: the tile edges of the
+    two products per instance size (32 or 64 each; all instances of one N
+    share them), then graph replay on/off and the instance order.  Sizes
+    are tuned one at a time, largest first, each over the four tile pairs
+    with the other sizes held (coordinate descent on the whole batched
+    step).  Runs advance the batch's states by the steps timed (callers tune
+    before setting their initial states, or re-set them afterwards).
+    Returns (best, results): best = (use_graph, largest_first, {N: tiles})."""
     torch = batch.torch
-    options = [(True, True), (True, False), (False, True)]
+    key = batch_key(_arch(torch), batch)
+    if use_cache:
+        entry = load_cache(path).get(key)
+        if entry:
+            per_n = {int(n): tuple(t) for n, t in entry["tiles"].items()}
+            for s in batch.solvers:
+                s.set_tiles(*per_n[s.n])
+            batch.config(use_graph=entry["use_graph"], largest_first=entry["largest_first"])
+            return (entry["use_graph"], entry["largest_first"], per_n), {}
     results = {}
-    for use_graph, largest in options:
+
+    def timed(use_graph, largest):
         batch.config(use_graph=use_graph, largest_first=largest)
         batch.step(steps)                                 # warm-up / capture
-        results[(use_graph, largest)] = _time(torch, lambda: batch.step(steps), trials)
-    best = min(results, key=results.get)
-    batch.config(use_graph=best[0], largest_first=best[1])
+        return _time(torch, lambda: batch.step(steps), trials)
+
+    sizes = sorted({s.n for s in batch.solvers}, reverse=True)
+    per_n = {n: next((s.tile1, s.tile2) for s in batch.solvers if s.n == n) for n in sizes}
+    per_n = {n: (t if t in BATCH_TILES else (64, 64)) for n, t in per_n.items()}
+
+    def apply(assign):
+        for s in batch.solvers:
+            s.set_tiles(*assign[s.n])
+
+    if tiles:
+        for n in sizes:
+            best_t, best_time = None, None
+            for t in BATCH_TILES:
+                trial = dict(per_n)
+                trial[n] = t
+                apply(trial)
+                sec = timed(True, True)
+                results[("tiles", n, t)] = sec
+                if best_time is None or sec < best_time:
+                    best_t, best_time = t, sec
+            per_n[n] = best_t
+    apply(per_n)
+    for use_graph, largest in [(True, True), (True, False), (False, True)]:
+        results[(use_graph, largest)] = timed(use_graph, largest)
+    best_order = min([k for k in results if len(k) == 2], key=results.get)
+    batch.config(use_graph=best_order[0], largest_first=best_order[1])
+    best = (best_order[0], best_order[1], dict(per_n))
+    if use_cache:
+        cache = load_cache(path)
+        cache[key] = {"use_graph": best[0], "largest_first": best[1],
+                      "tiles": {str(n): list(t) for n, t in per_n.items()},
+                      "seconds_per_batched_step": {
+                          (f"{k[1]}:{k[2][0]}x{k[2][1]}" if k[0] == "tiles" else
+                           f"graph={k[0]},largest_first={k[1]}"): v / steps
+                          for k, v in results.items()}}
+        save_cache(cache, path)
     return best, results

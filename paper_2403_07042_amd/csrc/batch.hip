@@ -9,8 +9,10 @@
 // full even when single instances are small.  Phases are ordered by the
 // stream, never by waits between workgroups.  A run of n steps (4 n
 // launches) is captured once into a hipGraph and replayed with one launch.
-// The tile arithmetic is the per-instance kernels' own, so every instance
-// advances bitwise as under qme_step.
+// Each instance's products run in the tile edges of its context (32 or 64,
+// qme_set_tiles; the autotuner picks them per size), and the tile arithmetic
+// is the per-instance kernels' own, so every instance advances bitwise as
+// under qme_step with the same tiles (unfolded, unsplit).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,8 +39,11 @@ struct BatchInstance {
   const int32_t *pi;
   int64_t n, ld;
   double dt;
-  int32_t tiles, n_gather;
-  uint32_t items[4];   // per phase: tiles^2, lower tiles, 1, lower tiles (decoherence)
+  int32_t edge1, edge2;   // tile edges of the two products (32 or 64)
+  int32_t tiles1, tiles2; // ld / edge
+  int32_t n_gather;
+  uint32_t items[4];   // per phase: tiles1^2, lower tiles2, 1, lower tiles (decoherence)
+  DissArgs<float> sparse;   // the sparse-channel fields only (see DissArgs)
 };
 
 struct BatchPhase {
@@ -60,8 +65,11 @@ __device__ __forceinline__ void tri_coords(int t, int &bi, int &bj) {
 
 template <int PHASE>
 __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p) {
+  constexpr int kGemmSmem = cgemm_f32_smem<64, kConjB>() > cgemm_s_smem<float, 32, kConjB>()
+                                ? cgemm_f32_smem<64, kConjB>()
+                                : cgemm_s_smem<float, 32, kConjB>();
   constexpr int kSmemFloats =
-      PHASE <= 1 ? cgemm_f32_smem<64, kConjB>()
+      PHASE <= 1 ? kGemmSmem
       : PHASE == 2 ? 3 * kBatchThreads * 2
                    : 2 * TD * (TD + 1) + int(sizeof(GatherLds) / sizeof(float)) + 2;
   __shared__ float smem[kSmemFloats];
@@ -76,16 +84,34 @@ __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p
   if constexpr (PHASE == 0) {
     const CgemmArgs<float> g{in.u_re, in.u_im, in.x_re, in.x_im, in.x_re, in.x_im,
                              in.y_re, in.y_im, in.ld, 1.0f, 1.0f};
-    cgemm_f32_tile<64, kConjB>(g, tile / in.tiles, tile % in.tiles, smem);
+    if (in.edge1 == 32)
+      cgemm_s_tile<float, 32, kConjB>(g, tile / in.tiles1, tile % in.tiles1, smem);
+    else
+      cgemm_f32_tile<64, kConjB>(g, tile / in.tiles1, tile % in.tiles1, smem);
   } else if constexpr (PHASE == 1) {
     int bi, bj;
     tri_coords(tile, bi, bj);
     const CgemmArgs<float> g{in.y_re, in.y_im, in.u_re, in.u_im, in.y_re, in.y_im,
                              in.z_re, in.z_im, in.ld, 1.0f, 1.0f};
-    cgemm_f32_tile<64, kConjB>(g, bi, bj, smem);
+    if (in.edge2 == 32)
+      cgemm_s_tile<float, 32, kConjB>(g, bi, bj, smem);
+    else
+      cgemm_f32_tile<64, kConjB>(g, bi, bj, smem);
   } else {
-    const DissArgs<float> da{in.z_re, in.z_im, in.x_re, in.x_im, in.ld, in.n, in.dt, in.d,
-                             in.leak, in.pi, in.cg, in.n_gather, in.aux, in.aux, in.trw};
+    DissArgs<float> da{in.z_re, in.z_im, in.x_re, in.x_im, in.ld, in.n, in.dt, in.d,
+                       in.leak, in.pi, in.cg, in.n_gather, in.aux, in.aux, in.trw};
+    da.n_csr = in.sparse.n_csr;
+    da.csr_ptr = in.sparse.csr_ptr;
+    da.csr_col = in.sparse.csr_col;
+    da.csr_val = in.sparse.csr_val;
+    da.csr_gamma = in.sparse.csr_gamma;
+    da.koff_ptr = in.sparse.koff_ptr;
+    da.koff_col = in.sparse.koff_col;
+    da.koff_val = in.sparse.koff_val;
+    da.n_loff = in.sparse.n_loff;
+    da.loff_row = in.sparse.loff_row;
+    da.loff_col = in.sparse.loff_col;
+    da.loff_val = in.sparse.loff_val;
     if constexpr (PHASE == 2) {
       double *sd = reinterpret_cast<double *>(smem);
       trace_body<float, kBatchThreads>(da, sd, sd + kBatchThreads, sd + 2 * kBatchThreads);
@@ -185,11 +211,16 @@ static qme_status build_tables(qme_batch *b) {
     t.n = c->n;
     t.ld = c->ld;
     t.dt = c->model.dt;
-    t.tiles = int32_t(c->ld / 64);
+    t.edge1 = c->tile1;
+    t.edge2 = c->tile2;
+    t.tiles1 = int32_t(c->ld / c->tile1);
+    t.tiles2 = int32_t(c->ld / c->tile2);
     t.n_gather = c->jt.n_gather;
+    t.sparse = DissArgs<float>{};
+    c->sparse_args(t.sparse);
     const int td = int((c->n + TD - 1) / TD);
-    t.items[0] = uint32_t(t.tiles) * uint32_t(t.tiles);
-    t.items[1] = uint32_t(t.tiles) * uint32_t(t.tiles + 1) / 2;
+    t.items[0] = uint32_t(t.tiles1) * uint32_t(t.tiles1);
+    t.items[1] = uint32_t(t.tiles2) * uint32_t(t.tiles2 + 1) / 2;
     t.items[2] = 1;
     t.items[3] = uint32_t(td) * uint32_t(td + 1) / 2;
   }
@@ -265,6 +296,10 @@ extern "C" qme_status qme_batch_create(qme_ctx *const *ctxs, void *const *states
         set_error("batched steps need FP32 contexts (leading dimension a multiple of 64)");
         return QME_E_UNSUPPORTED;
       }
+      if ((c->tile1 != 32 && c->tile1 != 64) || (c->tile2 != 32 && c->tile2 != 64)) {
+        set_error("batched products take 32- or 64-tiles (qme_set_tiles on the context)");
+        return QME_E_UNSUPPORTED;
+      }
       if (reinterpret_cast<uintptr_t>(states[i]) & 255) { set_error("states must be 256-byte aligned"); return QME_E_ARG; }
       if (i > 0 && c->device != ctxs[0]->device) { set_error("contexts on different devices"); return QME_E_ARG; }
       b->ctxs.push_back(c);
@@ -296,14 +331,17 @@ extern "C" qme_status qme_batch_config(qme_batch *b, int32_t use_graph, int32_t 
   qme_status st = check_device(b->ctxs[0]);
   if (st != QME_OK) return st;
   B_OK(hipDeviceSynchronize());   // no launch may still use the old graphs or tables
+  for (qme_ctx *c : b->ctxs)
+    if ((c->tile1 != 32 && c->tile1 != 64) || (c->tile2 != 32 && c->tile2 != 64)) {
+      set_error("batched products take 32- or 64-tiles (qme_set_tiles on the context)");
+      return QME_E_UNSUPPORTED;
+    }
   b->drop_graphs();
   b->use_graph = use_graph != 0;
-  if ((largest_first != 0) != b->lpt) {
-    b->lpt = largest_first != 0;
-    b->drop_tables();
-    return build_tables(b);
-  }
-  return QME_OK;
+  // the tables follow the instance order and each context's current tiles
+  b->lpt = largest_first != 0;
+  b->drop_tables();
+  return build_tables(b);
 }
 
 extern "C" qme_status qme_batch_step(qme_batch *b, int64_t n_steps, void *ws, size_t ws_bytes,

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.hpp"
@@ -176,6 +177,7 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   CgemmArgs<T> g2{y_re, y_im, u_re, u_im, y_re, y_im, z_re, z_im, c->ld, T(1), T(1)};
   DissArgs<T> da{z_re, z_im, o_re, o_im, c->ld, c->n, c->model.dt, c->d, c->leak,
                  c->pi, c->cg, c->jt.n_gather, aux_in, aux_out, c->trw};
+  c->sparse_args(da);
   GemmOps o1, o2;
   o1.conj_b = o2.conj_b = true;
   o2.lower = true;
@@ -220,16 +222,17 @@ template hipError_t step_once<float>(qme_ctx *, const void *, void *, void *, vo
 template hipError_t step_once<double>(qme_ctx *, const void *, void *, void *, void *, hipStream_t,
                                       void *);
 
-// The single-workgroup path applies to FP32 / FP64 contexts with n <= kSmallN.
+// The single-workgroup path applies to FP32 / FP64 contexts with n <= kSmallN
+// whose decoherence operators are all monomial.
 bool uses_small_path(const qme_ctx *c) {
-  return c->fused && c->n <= kSmallN && c->precision != QME_BF16X3;
+  return c->fused && c->n <= kSmallN && c->precision != QME_BF16X3 && c->jt.n_csr == 0;
 }
 
 // The folded step applies when no decoherence operator maps a basis state
 // onto another (no gather channels: the decoherence step is a factor per
 // element), in FP32 with 64-tiles for the lower product or in FP64.
 bool uses_fold(const qme_ctx *c) {
-  if (!c->fold || c->jt.n_gather != 0) return false;
+  if (!c->fold || c->jt.n_gather != 0 || c->jt.n_csr != 0) return false;
   if (c->precision == QME_FP32) return c->tile2 == 64 || c->tile2 == 32;
   return c->precision == QME_FP64 || c->precision == QME_BF16X3;
 }
@@ -409,7 +412,9 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
     // at the state w it reads
     const double dt = c->model.dt;
     std::vector<double> trw(static_cast<size_t>(n), 0.0);
-    for (int64_t w = 0; w < n; ++w) trw[size_t(w)] = 1.0 - dt * c->jt.d[size_t(w)];
+    // (sparse channels: the probability a state sends into the basis)
+    for (int64_t w = 0; w < n; ++w)
+      trw[size_t(w)] = 1.0 - dt * c->jt.d[size_t(w)] + dt * c->jt.arrive[size_t(w)];
     for (int j = 0; j < c->jt.n_gather; ++j)
       for (int64_t u = 0; u < n; ++u) {
         const int32_t w = c->jt.pi[size_t(j) * n + u];
@@ -427,6 +432,37 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
   if (c->jt.n_gather > 0) {
     HIP_OK(hipMemcpy(c->pi, c->jt.pi.data(), sizeof(int32_t) * c->jt.pi.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->cg, c->jt.cg.data(), sizeof(double) * c->jt.cg.size(), hipMemcpyHostToDevice));
+  }
+  // sparse channels (general-form models whose operators are not monomial)
+  {
+    const JumpTables &t = c->jt;
+    auto up = [&](auto **dst, const auto &v) -> qme_status {
+      using E = typename std::decay_t<decltype(v)>::value_type;
+      const size_t cnt = std::max<size_t>(1, v.size());
+      HIP_OK(hipMalloc(reinterpret_cast<void **>(dst), sizeof(E) * cnt));
+      if (!v.empty()) HIP_OK(hipMemcpy(*dst, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice));
+      return QME_OK;
+    };
+    std::vector<double> gam;
+    for (int32_t j : t.csr_channel) gam.push_back(c->model.jumps[size_t(j)].gamma);
+    qme_status st = QME_OK;
+    if (st == QME_OK) st = up(&c->csr_ptr, t.csr_ptr);
+    if (st == QME_OK) st = up(&c->csr_col, t.csr_col);
+    if (st == QME_OK) st = up(&c->csr_val, t.csr_val);
+    if (st == QME_OK) st = up(&c->csrt_ptr, t.csrt_ptr);
+    if (st == QME_OK) st = up(&c->csrt_col, t.csrt_col);
+    if (st == QME_OK) st = up(&c->csrt_val, t.csrt_val);
+    if (st == QME_OK) st = up(&c->kj_ptr, t.kj_ptr);
+    if (st == QME_OK) st = up(&c->kj_col, t.kj_col);
+    if (st == QME_OK) st = up(&c->kj_val, t.kj_val);
+    if (st == QME_OK) st = up(&c->koff_ptr, t.koff_ptr);
+    if (st == QME_OK) st = up(&c->koff_col, t.koff_col);
+    if (st == QME_OK) st = up(&c->koff_val, t.koff_val);
+    if (st == QME_OK) st = up(&c->loff_row, t.loff_row);
+    if (st == QME_OK) st = up(&c->loff_col, t.loff_col);
+    if (st == QME_OK) st = up(&c->loff_val, t.loff_val);
+    if (st == QME_OK) st = up(&c->csr_gamma, gam);
+    if (st != QME_OK) return st;
   }
   // adjoint tables
   const int nj = int(c->model.jumps.size());
@@ -962,6 +998,14 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
   return QME_OK;
 }
 
+extern "C" qme_status qme_get_tiles(const qme_ctx *c, int32_t *tile1, int32_t *tile2) {
+  set_error("");
+  if (!c || !tile1 || !tile2) { set_error("NULL argument"); return QME_E_ARG; }
+  *tile1 = c->tile1;
+  *tile2 = c->tile2;
+  return QME_OK;
+}
+
 extern "C" qme_status qme_profile_enable(qme_ctx *c, int32_t enable) {
   set_error("");
   if (!c) { set_error("ctx is NULL"); return QME_E_ARG; }
@@ -1034,6 +1078,11 @@ qme_ctx::~qme_ctx() {
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   for (void *e : ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *e : ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+  for (void *p : {(void *)csr_ptr, (void *)csrt_ptr, (void *)kj_ptr, (void *)koff_ptr,
+                  (void *)csr_col, (void *)csrt_col, (void *)kj_col, (void *)koff_col,
+                  (void *)csr_val, (void *)csrt_val, (void *)kj_val, (void *)koff_val,
+                  (void *)csr_gamma, (void *)loff_row, (void *)loff_col, (void *)loff_val})
+    if (p) (void)hipFree(p);
   for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)trw, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,
                   (void *)h_ptr, (void *)h_col, (void *)h_val, (void *)t_row, (void *)t_col,

@@ -44,6 +44,29 @@ struct qme_ctx {
   double *trw = nullptr;              // trace weights (DissArgs::trw)
   int32_t *pi = nullptr;
   double *cg = nullptr;
+  // sparse (non-monomial) channels of general-form models (JumpTables)
+  int64_t *csr_ptr = nullptr, *csrt_ptr = nullptr, *kj_ptr = nullptr, *koff_ptr = nullptr;
+  int32_t *csr_col = nullptr, *csrt_col = nullptr, *kj_col = nullptr, *koff_col = nullptr;
+  double *csr_val = nullptr, *csrt_val = nullptr, *kj_val = nullptr, *koff_val = nullptr;
+  double *csr_gamma = nullptr;
+  int32_t *loff_row = nullptr, *loff_col = nullptr;
+  double *loff_val = nullptr;
+  // the decoherence and trace passes' arguments for these tables
+  template <typename T>
+  void sparse_args(qme::DissArgs<T> &a) const {
+    a.n_csr = jt.n_csr;
+    a.csr_ptr = csr_ptr;
+    a.csr_col = csr_col;
+    a.csr_val = csr_val;
+    a.csr_gamma = csr_gamma;
+    a.koff_ptr = jt.koff_col.empty() ? nullptr : koff_ptr;
+    a.koff_col = koff_col;
+    a.koff_val = koff_val;
+    a.n_loff = int64_t(jt.loff_val.size());
+    a.loff_row = loff_row;
+    a.loff_col = loff_col;
+    a.loff_val = loff_val;
+  }
   // adjoint tables (owned)
   int32_t *tau = nullptr;     // [n_gather x n]
   double *ca = nullptr;

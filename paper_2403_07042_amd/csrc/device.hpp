@@ -138,6 +138,27 @@ struct DissArgs {
   const double *trw = nullptr;
   // when set, the diagonal of Z is read from this array (FP64, [n])
   const double *zdiag = nullptr;
+  // decoherence operators that are not monomial (general-form models), in
+  // sparse form: per channel q the rows of A on the basis (csr_ptr
+  // [n_csr][n + 1] into csr_col / csr_val, unit rate) and its rate
+  // csr_gamma[q]; (A Z A^dag)[u,v] = sum over rows u and v of
+  // a_uk a_vl Z[k,l].  koff (CSR over rows, or nullptr): the off-diagonal
+  // part of K = sum gamma A^dag A, whose -1/2 {K, Z} the pass adds (the
+  // diagonal part is in d).  loff: n_loff off-diagonal entries (row, col,
+  // value) of the lost probability's matrix: lost += sum value Re Z[col,row]
+  // (non-zero only on a restricted basis).
+  int n_csr = 0;
+  const int64_t *csr_ptr = nullptr;
+  const int32_t *csr_col = nullptr;
+  const double *csr_val = nullptr;
+  const double *csr_gamma = nullptr;
+  const int64_t *koff_ptr = nullptr;
+  const int32_t *koff_col = nullptr;
+  const double *koff_val = nullptr;
+  int64_t n_loff = 0;
+  const int32_t *loff_row = nullptr;
+  const int32_t *loff_col = nullptr;
+  const double *loff_val = nullptr;
 };
 
 template <typename T>

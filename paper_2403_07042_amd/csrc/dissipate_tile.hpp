@@ -10,6 +10,12 @@
 //   rho_d[u,v] = Z[u,v] (1 - dt (d[u] + d[v]) / 2)
 //              + dt sum_j cg_j[u] cg_j[v] Z[pi_j[u], pi_j[v]]   (cg = sqrt(gamma) c).
 //
+// Decoherence operators that are not monomial (general-form models) enter in
+// sparse form (DissArgs::n_csr, koff): per element the jump term of channel
+// j is gamma_j sum_{k in row u of A_j} sum_{l in row v of A_j} a_uk a_vl
+// Z[k,l], and the off-diagonal part of K = sum gamma A^dag A adds
+// -1/2 (K Z + Z K)[u,v] beside the diagonal factor.
+//
 // trace_kernel (one workgroup) needs only the diagonal of Z: it forms
 // tr rho_d = sum_w trw[w] Z[w,w] (the jump terms regrouped by the diagonal
 // element they read, weights fixed per context) and the probability leaving
@@ -47,6 +53,15 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
   // tr rho_d = sum_u rho_d[u,u] = sum_w trw[w] Z[w,w]: the jump terms
   // c_j[u]^2 Z[pi_j u, pi_j u] regrouped by the state w = pi_j u they read
   double tr = 0.0, lost = 0.0, rot = 0.0;
+  // the lost probability's off-diagonal terms (restricted sparse channels):
+  // lost += value Re Z[col,row], and the trace loses dt times the same
+  for (int64_t e = threadIdx.x; e < p.n_loff; e += NT) {
+    double zr, zi;
+    zlower(p, p.loff_col[e], p.loff_row[e], zr, zi);
+    const double x = p.loff_val[e] * zr;
+    lost += x;
+    tr -= p.dt * x;
+  }
   // u = threadIdx.x + k NT in increasing k; the loads of G values of k are
   // issued together (one batch at N = 2048), the sums keep that order
   constexpr int G = 8;
@@ -195,6 +210,51 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
           xr[q] += w[q] * gr[q];
           xi[q] += w[q] * gi[q];
         }
+      }
+    }
+    if (p.n_csr > 0 || p.koff_ptr) {
+      // sparse channels and K's off-diagonal part
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        if (!ok[q]) continue;
+        const int64_t u = int64_t(bi) * TD + rb + q * kRows;
+        double ar = 0.0, ai = 0.0;
+        for (int ch = 0; ch < p.n_csr; ++ch) {
+          const int64_t *ptr = p.csr_ptr + int64_t(ch) * (p.n + 1);
+          double cr = 0.0, ci = 0.0;
+          for (int64_t x = ptr[u]; x < ptr[u + 1]; ++x) {
+            const int32_t k = p.csr_col[x];
+            const double a = p.csr_val[x];
+            for (int64_t y = ptr[v]; y < ptr[v + 1]; ++y) {
+              double zr, zi;
+              zlower(p, k, p.csr_col[y], zr, zi);
+              const double w = a * p.csr_val[y];
+              cr += w * zr;
+              ci += w * zi;
+            }
+          }
+          ar += p.csr_gamma[ch] * cr;
+          ai += p.csr_gamma[ch] * ci;
+        }
+        if (p.koff_ptr) {
+          double kr = 0.0, ki = 0.0;
+          for (int64_t x = p.koff_ptr[u]; x < p.koff_ptr[u + 1]; ++x) {   // (K Z)[u,v]
+            double zr, zi;
+            zlower(p, p.koff_col[x], v, zr, zi);
+            kr += p.koff_val[x] * zr;
+            ki += p.koff_val[x] * zi;
+          }
+          for (int64_t y = p.koff_ptr[v]; y < p.koff_ptr[v + 1]; ++y) {   // (Z K)[u,v]
+            double zr, zi;
+            zlower(p, u, p.koff_col[y], zr, zi);
+            kr += p.koff_val[y] * zr;
+            ki += p.koff_val[y] * zi;
+          }
+          ar -= 0.5 * kr;
+          ai -= 0.5 * ki;
+        }
+        xr[q] += dt * ar;
+        xi[q] += dt * ai;
       }
     }
 #pragma unroll

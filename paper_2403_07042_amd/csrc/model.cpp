@@ -10,6 +10,7 @@
 #include "model.hpp"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <thread>
 
@@ -192,7 +193,6 @@ bool build_general_model(int64_t n, int64_t h_nnz, const int32_t *h_rows, const 
     }
   }
   m.moves.resize(size_t(n_jumps));
-  std::vector<int32_t> seen_src(size_t(n), -1), seen_dst(size_t(n), -1);
   for (int32_t j = 0; j < n_jumps; ++j) {
     const qme_general_jump &jp = jumps[j];
     if (!(jp.gamma >= 0.0) || !std::isfinite(jp.gamma)) { err = "gamma must be finite and >= 0"; return false; }
@@ -205,16 +205,16 @@ bool build_general_model(int64_t n, int64_t h_nnz, const int32_t *h_rows, const 
       const int32_t a = jp.source[e], b = jp.target[e];
       if (a < 0 || a >= n || b < -1 || b >= n) { err = "jump index out of range"; return false; }
       if (!std::isfinite(jp.coef[e])) { err = "jump coefficient is not finite"; return false; }
-      if (seen_src[size_t(a)] == j || (b >= 0 && seen_dst[size_t(b)] == j)) {
-        err = "decoherence operator is not monomial (a state has two images or two preimages)";
-        unsupported = true;
-        return false;
-      }
-      seen_src[size_t(a)] = j;
-      if (b >= 0) seen_dst[size_t(b)] = j;
-      if (jp.coef[e] != 0.0) m.moves[size_t(j)].push_back({a, b, jp.coef[e]});
+      if (jp.coef[e] != 0.0) m.moves[size_t(j)].push_back({a, int64_t(b), jp.coef[e]});
     }
   }
+  // the gradient parameters: H's symmetric entries (one per pair r <= c of
+  // the merged pattern)
+  for (size_t e = 0; e < m.h_val.size(); ++e)
+    if (m.h_row[e] <= m.h_col[e]) {
+      m.h_in_row.push_back(m.h_row[e]);
+      m.h_in_col.push_back(m.h_col[e]);
+    }
   return true;
 }
 
@@ -239,12 +239,29 @@ bool restrict_basis(Model &m, const int32_t *keep, int64_t n_keep, std::string &
     m.h_row.swap(r);
     m.h_col.swap(c);
     m.h_val.swap(v);
+    // a move onto a removed state keeps that state's identity (an id below
+    // -1, unique over all restrictions of this model), so moves of two kept
+    // states onto it still share it in A^dag A
     for (auto &mv : m.moves) {
       std::vector<Model::Move> kept;
-      for (const Model::Move &x : mv)
-        if (pos[size_t(x.src)] >= 0)
-          kept.push_back({pos[size_t(x.src)], x.dst >= 0 ? pos[size_t(x.dst)] : -1, x.c});
+      for (const Model::Move &x : mv) {
+        if (pos[size_t(x.src)] < 0) continue;
+        int64_t d = x.dst;
+        if (d >= 0) d = pos[size_t(d)] >= 0 ? int64_t(pos[size_t(d)]) : -2 - (m.next_outside + d);
+        kept.push_back({pos[size_t(x.src)], d, x.c});
+      }
       mv.swap(kept);
+    }
+    m.next_outside += m.n;
+    // the parameters keep their identity on the kept states
+    {
+      std::vector<int32_t> r, c;
+      for (size_t e = 0; e < m.h_in_row.size(); ++e) {
+        r.push_back(pos[size_t(m.h_in_row[e])]);
+        c.push_back(pos[size_t(m.h_in_col[e])]);
+      }
+      m.h_in_row.swap(r);
+      m.h_in_col.swap(c);
     }
     m.n = n_keep;
     return true;
@@ -388,7 +405,25 @@ void hamiltonian_coo(const Model &m, std::vector<int32_t> &r,
 }
 
 std::vector<TermCoo> hamiltonian_terms(const Model &m) {
-  if (m.general) return {};
+  if (m.general) {
+    // one parameter per symmetric entry h = H[r][c] = H[c][r] (r <= c) of the
+    // model as given; an entry whose state a restriction removed acts on
+    // nothing (empty term, zero gradient)
+    std::vector<TermCoo> terms(m.h_in_row.size());
+    for (size_t e = 0; e < m.h_in_row.size(); ++e) {
+      const int32_t r = m.h_in_row[e], c = m.h_in_col[e];
+      if (r < 0 || c < 0) continue;
+      terms[e].row.push_back(r);
+      terms[e].col.push_back(c);
+      terms[e].val.push_back(1.0);
+      if (r != c) {
+        terms[e].row.push_back(c);
+        terms[e].col.push_back(r);
+        terms[e].val.push_back(1.0);
+      }
+    }
+    return terms;
+  }
   const int n_atoms = int(m.atom_mode.size());
   std::vector<TermCoo> terms(n_atoms + m.hops.size());
   std::vector<int32_t> buf(m.n_modes);
@@ -434,18 +469,118 @@ JumpTables jump_tables(const Model &m) {
   jt.unit_ada.assign(size_t(nj) * n, 0.0);
   std::vector<int32_t> buf(M);
   std::vector<char> has_arrival(nj, 0);
+  jt.arrive.assign(n, 0.0);
+  jt.koff_ptr.assign(n + 1, 0);
+  std::vector<std::vector<std::pair<int32_t, double>>> koff_rows(m.general ? size_t(n) : 0);
+  std::vector<std::vector<std::pair<int32_t, double>>> loff_rows(m.general ? size_t(n) : 0);
   for (int j = 0; m.general && j < nj; ++j) {
     const double gamma = m.jumps[j].gamma;
-    for (const Model::Move &x : m.moves[j]) {
-      const double a2 = x.c * x.c;
-      jt.unit_ada[size_t(j) * n + x.src] = a2;
-      jt.d[x.src] += gamma * a2;
-      if (x.dst >= 0) {
-        jt.unit_pi[size_t(j) * n + x.dst] = x.src;
-        jt.unit_c[size_t(j) * n + x.dst] = x.c;
-        has_arrival[j] = 1;
-      } else {
-        jt.leak[x.src] += gamma * a2;
+    const std::vector<Model::Move> &mv = m.moves[j];
+    // monomial: every state has at most one move and every target (other
+    // than the private outside one, -1) at most one source
+    bool monomial = true;
+    {
+      std::vector<char> src_seen(size_t(n), 0);
+      std::map<int64_t, int> dst_seen;
+      for (const Model::Move &x : mv) {
+        if (src_seen[size_t(x.src)]++ || (x.dst != -1 && dst_seen[x.dst]++)) {
+          monomial = false;
+          break;
+        }
+      }
+    }
+    if (monomial) {
+      for (const Model::Move &x : mv) {
+        const double a2 = x.c * x.c;
+        jt.unit_ada[size_t(j) * n + x.src] = a2;
+        jt.d[x.src] += gamma * a2;
+        if (x.dst >= 0) {
+          jt.unit_pi[size_t(j) * n + x.dst] = x.src;
+          jt.unit_c[size_t(j) * n + x.dst] = x.c;
+          has_arrival[j] = 1;
+        } else {
+          jt.leak[x.src] += gamma * a2;
+        }
+      }
+      continue;
+    }
+    // sparse channel: A's entries per image key (basis state, removed state
+    // id, or a private outside row per move onto -1), duplicates summed
+    std::map<int64_t, std::map<int32_t, double>> rows;   // key -> (preimage -> coefficient)
+    int64_t private_key = -int64_t(1) << 62;
+    for (const Model::Move &x : mv) {
+      const int64_t key = x.dst == -1 ? private_key++ : x.dst;
+      rows[key][x.src] += x.c;
+    }
+    // K = A^dag A over every row; M = the same over the basis rows only
+    std::map<std::pair<int32_t, int32_t>, double> kmat, mmat;
+    for (const auto &kv : rows)
+      for (const auto &a : kv.second)
+        for (const auto &b : kv.second) {
+          const double prod = a.second * b.second;
+          kmat[{a.first, b.first}] += prod;
+          if (kv.first >= 0) mmat[{a.first, b.first}] += prod;
+        }
+    const int q = jt.n_csr++;
+    jt.csr_channel.push_back(j);
+    jt.csr_sg.push_back(std::sqrt(gamma));
+    // A on the basis, rows = images, and its transpose
+    std::vector<std::vector<std::pair<int32_t, double>>> arow(static_cast<size_t>(n)), atrow(static_cast<size_t>(n));
+    for (const auto &kv : rows) {
+      if (kv.first < 0) continue;
+      for (const auto &a : kv.second) {
+        if (a.second == 0.0) continue;
+        arow[size_t(kv.first)].push_back({a.first, a.second});
+        atrow[size_t(a.first)].push_back({int32_t(kv.first), a.second});
+      }
+    }
+    auto append = [&](std::vector<int64_t> &ptr, std::vector<int32_t> &col, std::vector<double> &val,
+                      const std::vector<std::vector<std::pair<int32_t, double>>> &r) {
+      for (int64_t u = 0; u < n; ++u) {
+        ptr.push_back(int64_t(col.size()));
+        for (const auto &e : r[size_t(u)]) {
+          col.push_back(e.first);
+          val.push_back(e.second);
+        }
+      }
+      ptr.push_back(int64_t(col.size()));
+    };
+    append(jt.csr_ptr, jt.csr_col, jt.csr_val, arow);
+    append(jt.csrt_ptr, jt.csrt_col, jt.csrt_val, atrow);
+    std::vector<std::vector<std::pair<int32_t, double>>> krow(static_cast<size_t>(n));
+    for (const auto &kv : kmat) {
+      const int32_t k = kv.first.first, l = kv.first.second;
+      const double mv_kl = mmat.count(kv.first) ? mmat[kv.first] : 0.0;
+      if (k == l) {
+        jt.unit_ada[size_t(j) * n + k] = kv.second;
+        jt.d[k] += gamma * kv.second;
+        jt.arrive[k] += gamma * mv_kl;
+        jt.leak[k] += gamma * (kv.second - mv_kl);
+      } else if (kv.second != 0.0) {
+        krow[size_t(k)].push_back({l, kv.second});
+        koff_rows[size_t(k)].push_back({l, gamma * kv.second});
+        if (kv.second - mv_kl != 0.0) loff_rows[size_t(k)].push_back({l, gamma * (kv.second - mv_kl)});
+      }
+    }
+    append(jt.kj_ptr, jt.kj_col, jt.kj_val, krow);
+  }
+  if (m.general) {
+    // K's off-diagonal part summed over the sparse channels (entries of one
+    // (k, l) added in channel order), and the lost probability's cross terms
+    for (int64_t k = 0; k < n; ++k) {
+      std::map<int32_t, double> acc;
+      for (const auto &e : koff_rows[size_t(k)]) acc[e.first] += e.second;
+      for (const auto &e : acc) {
+        jt.koff_col.push_back(e.first);
+        jt.koff_val.push_back(e.second);
+      }
+      jt.koff_ptr[size_t(k) + 1] = int64_t(jt.koff_col.size());
+      std::map<int32_t, double> lacc;
+      for (const auto &e : loff_rows[size_t(k)]) lacc[e.first] += e.second;
+      for (const auto &e : lacc) {
+        jt.loff_row.push_back(int32_t(k));
+        jt.loff_col.push_back(e.first);
+        jt.loff_val.push_back(e.second);
       }
     }
   }

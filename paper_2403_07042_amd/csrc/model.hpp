@@ -39,13 +39,19 @@ struct Model {
   // that land in the window; rank() sums it over the levels below a tuple's
   std::vector<uint64_t> cnt;
   // general form (qme_hamiltonian_general): H given as sorted, merged,
-  // symmetric COO and each decoherence operator as monomial moves
-  // (A |src> = c |dst>, dst = -1: out of the basis); jumps[j].gamma holds the
-  // rates.  No occupation table, no parameter terms.
+  // symmetric COO and each decoherence operator as moves (A |src> has the
+  // component c |dst>; moves with one (src, dst) add up); jumps[j].gamma holds
+  // the rates.  dst = -1: a component outside the basis, orthogonal to every
+  // other one; dst <= -2: a state removed by a restriction (qme_subspace),
+  // shared by every move onto it, so A^dag A keeps its cross terms.  No
+  // occupation table; the parameter terms are H's symmetric entries.
   struct Move {
-    int32_t src, dst;
+    int32_t src;
+    int64_t dst;
     double c;
   };
+  int64_t next_outside = 0;               // first unused removed-state id (-2 - id)
+  std::vector<int32_t> h_in_row, h_in_col;   // H's pattern as given (before merging)
   bool general = false;
   std::vector<int32_t> h_row, h_col;
   std::vector<double> h_val;
@@ -96,6 +102,34 @@ struct JumpTables {
   // channels with an arrival inside the basis, whatever their rate
   std::vector<int32_t> arrival_channel;  // original jump index
   std::vector<int32_t> arrival_of;       // per jump: index into arrival_channel or -1
+
+  // General-form channels that are not monomial (a state with several images
+  // or several preimages), in sparse form.  Per such channel j (index q):
+  //   (A Z A^dag)[u,v] = sum_{(k,a) in row u} sum_{(l,b) in row v} a b Z[k,l]
+  // over the rows of A restricted to the basis (row u: the preimages k of
+  // image u with their unit-rate coefficients), csr_ptr[q * (n + 1) + u]
+  // indexing csr_col / csr_val; the transposed rows (row k: images u of
+  // preimage k) in csrt_*; csr_sg[q] = sqrt(gamma_j).  koff: the off-diagonal
+  // part of K = sum over these channels of gamma_j A_j^dag A_j (A^dag A formed
+  // from the whole operator, before any restriction), CSR over rows u; its
+  // diagonal is in d.  kj: the same per channel at unit rate (rate
+  // gradients).  loff: the off-diagonal entries (k, l, value) of
+  // sum_j gamma_j (A_j^dag A_j - A_Pj^T A_Pj), non-zero only where two kept
+  // states move onto one removed state (the lost probability's cross terms;
+  // the diagonal part is in leak).  arrive: sum_j gamma_j (A_Pj^T A_Pj)[w,w],
+  // the probability each state w sends into the basis (trace weights).
+  int n_csr = 0;
+  std::vector<int32_t> csr_channel;      // original jump index
+  std::vector<int64_t> csr_ptr, csrt_ptr, kj_ptr;   // n_csr x (n + 1)
+  std::vector<int32_t> csr_col, csrt_col, kj_col;
+  std::vector<double> csr_val, csrt_val, kj_val;
+  std::vector<double> csr_sg;
+  std::vector<int64_t> koff_ptr;         // n + 1
+  std::vector<int32_t> koff_col;
+  std::vector<double> koff_val;
+  std::vector<int32_t> loff_row, loff_col;
+  std::vector<double> loff_val;
+  std::vector<double> arrive;            // n
 };
 
 bool build_model(const qme_system *sys, const qme_params *par, Model &m,

@@ -45,7 +45,10 @@ def test_tile_choice_is_bitwise_neutral_and_tuner_picks_valid(precision, tmp_pat
     sol.close()
 
 
-def test_batch_tuner():
+def test_batch_tuner(tmp_path):
+    """The batch tuner picks tile edges per instance size (all instances of
+    one N share them), graph replay and order; the choice is cached and
+    re-applied; the tuned batch still equals its solo runs bitwise."""
     wls = W.batch_sweep(per_size=4, sizes=(64, 256))
     sols = []
     for wl in wls:
@@ -53,8 +56,28 @@ def test_batch_tuner():
         s.set_rho(W.initial_rho(wl, P.basis(wl)))
         sols.append(s)
     b = P.Batch(sols)
-    best, results = A.tune_batch(b, steps=2, trials=2)
-    assert best in results and len(results) == 3
+    path = str(tmp_path / "tune.json")
+    best, results = A.tune_batch(b, steps=2, trials=2, use_cache=True, path=path)
+    use_graph, largest, per_n = best
+    assert set(per_n) == {64, 256} and all(t in A.BATCH_TILES for t in per_n.values())
+    for s in sols:
+        assert s.tiles == per_n[s.n]
+    assert len([k for k in results if k[0] == "tiles"]) == 8
+    again, _ = A.tune_batch(b, use_cache=True, path=path)       # from the cache
+    assert again == best
+    for wl, s in zip(wls, sols):
+        s.set_rho(W.initial_rho(wl, P.basis(wl)))
+    b.step(10)
+    torch.cuda.synchronize()
+    for wl, s in zip(wls, sols):
+        solo = P.Solver(wl, "fp32")
+        solo.set_fold(False)
+        solo.set_split(False)
+        solo.set_tiles(*per_n[s.n])
+        solo.set_rho(W.initial_rho(wl, P.basis(wl)))
+        solo.step(10)
+        assert np.array_equal(s.get_rho()[0], solo.get_rho()[0]), wl["name"]
+        solo.close()
     b.close()
     for s in sols:
         s.close()

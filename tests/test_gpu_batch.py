@@ -32,11 +32,15 @@ def make_solvers(wls):
     return sols
 
 
-def solo_rho(wl, steps):
+def solo_rho(wl, steps, tiles=None):
+    """The instance alone under qme_step, as the batch runs it: unfolded,
+    unsplit, with the tiles of its context in the batch (default: the
+    context's default tiles)."""
     s = P.Solver(wl, "fp32")
     s.set_fold(False)            # the batched step does not fold its decoherence pass
     s.set_split(False)           # nor split its products along k
-    s.set_tiles(64, 64)          # and it runs 64-tiles at every size
+    if tiles:
+        s.set_tiles(*tiles)
     s.set_rho(W.initial_rho(wl, P.basis(wl)))
     s.step(steps)
     rho, sink = s.get_rho()
@@ -58,6 +62,50 @@ def test_batch_equals_solo_bitwise(graph, largest):
         ref, ref_sink = solo_rho(wl, 30)
         assert np.array_equal(rho, ref), wl["name"]
         assert sink == ref_sink
+    b.close()
+    for s in sols:
+        s.close()
+
+
+def test_batch_per_instance_tiles_bitwise():
+    """Instances whose contexts take different tile edges (32 or 64 for each
+    product) in one batch: each equals its solo run with the same tiles
+    bitwise; then the tiles of every context change and a reconfigured batch
+    follows them."""
+    wls = mixed_instances()
+    sols = make_solvers(wls)
+    choices = [(32, 32), (64, 64), (32, 64), (64, 32)]
+    assign = [choices[i % 4] for i in range(len(sols))]
+    for s, t in zip(sols, assign):
+        s.set_tiles(*t)
+    b = P.Batch(sols)
+    b.config(use_graph=True, largest_first=True)
+    print(f"batch of {len(wls)} instances, mixed tiles", flush=True)
+    b.step(12)
+    torch.cuda.synchronize()
+    for wl, s, t in zip(wls, sols, assign):
+        rho, sink = s.get_rho()
+        ref, ref_sink = solo_rho(wl, 12, t)
+        assert np.array_equal(rho, ref), (wl["name"], t)
+        assert sink == ref_sink
+    # swap the tiles of every context; the tables follow after config()
+    assign = [choices[(i + 1) % 4] for i in range(len(sols))]
+    for wl, s, t in zip(wls, sols, assign):
+        s.set_tiles(*t)
+        s.set_rho(W.initial_rho(wl, P.basis(wl)))
+    b.config(use_graph=False, largest_first=True)
+    b.step(12)
+    torch.cuda.synchronize()
+    for wl, s, t in zip(wls, sols, assign):
+        rho, _ = s.get_rho()
+        ref, _ = solo_rho(wl, 12, t)
+        assert np.array_equal(rho, ref), (wl["name"], t)
+    s128 = sols[0]
+    s128.set_tiles(*((128, 128) if s128.ld % 128 == 0 else (64, 64)))
+    if s128.tiles == (128, 128):
+        with pytest.raises(L.QmeError) as e:
+            b.config()
+        assert e.value.status == L.QME_E_UNSUPPORTED
     b.close()
     for s in sols:
         s.close()

@@ -145,10 +145,6 @@ def test_general_model_errors():
     with pytest.raises(L.QmeError) as e:
         P.Solver(bad, "fp32")
     assert "QME_E_ARG" in str(e.value)
-    two_images = dict(wl, jumps=[(0.1, [0, 0], [1, 2], [1.0, 1.0])])
-    with pytest.raises(L.QmeError) as e:
-        P.Solver(two_images, "fp32")
-    assert "QME_E_UNSUPPORTED" in str(e.value)
     out_of_range = dict(wl, jumps=[(0.1, [0], [64], [1.0])])
     with pytest.raises(L.QmeError) as e:
         P.Solver(out_of_range, "fp32")
