@@ -16,7 +16,11 @@ independent ways:
 Observable: f = sum_s o_s Re rho_K[s, s] for a diagonal weight vector o.
 
 Parameter order (per term): g per atom (cavity-major), mu per hop (in the
-given order), gamma per jump (in the given order).
+given order), gamma per jump (in the given order).  For a model given as
+matrices (evolve.GeneralSystem) the Hamiltonian parameters are its symmetric
+entries instead: one per pair (r, c), r <= c, of the pattern of the given H
+triplets, in (r, c) order, moving H[r][c] and H[c][r] together; then gamma
+per jump.
 """
 from __future__ import annotations
 
@@ -52,10 +56,31 @@ def frechet_exp_minus_i_h_dt(h, dt, dh):
     return v @ (f * e) @ v.T
 
 
-def parameter_directions(sysm: evolve.System):
-    """Per-term derivative data: a list of ("h", dH) for g and mu terms and
-    ("gamma", j) for jump rates, in the documented parameter order."""
+def general_pattern(wl):
+    """The symmetric entries (r, c), r <= c, of a general-form workload's H
+    pattern, in (r, c) order: its Hamiltonian parameters."""
+    rows, cols, _ = wl["h"]
+    return sorted({(int(r), int(c)) for r, c in zip(rows, cols) if r <= c})
+
+
+def parameter_directions(sysm):
+    """Per-term derivative data: a list of ("h", dH) for g and mu terms (or
+    a general model's symmetric H entries) and ("gamma", j) for jump rates,
+    in the documented parameter order."""
     dirs = []
+    if isinstance(sysm, evolve.GeneralSystem):
+        pos = -np.ones(int(sysm.wl["n"]), dtype=np.int64)
+        pos[sysm.keep] = np.arange(sysm.n)
+        for r, c in general_pattern(sysm.wl):
+            dh = np.zeros((sysm.n, sysm.n))
+            a, b = pos[r], pos[c]
+            if a >= 0 and b >= 0:
+                dh[a, b] = 1.0
+                dh[b, a] = 1.0
+            dirs.append(("h", dh))
+        for j in range(len(sysm.jumps)):
+            dirs.append(("gamma", j))
+        return dirs
     for coef, label, w in sysm.terms:
         if label[0] == "g":
             dirs.append(("h", w.toarray()))
@@ -68,6 +93,8 @@ def parameter_directions(sysm: evolve.System):
 
 
 def n_params(wl):
+    if wl.get("general"):
+        return len(general_pattern(wl)) + len(wl["jumps"])
     return int(sum(wl["atoms"])) + len(wl["hops"]) + len(wl["jumps"])
 
 
@@ -133,6 +160,8 @@ def gradient(sysm: evolve.System, rho0, n_steps, obs):
 
 def perturbed(wl, dtheta, h):
     """Copy of a workload with per-term parameters moved by h * dtheta."""
+    if wl.get("general"):
+        return _perturbed_general(wl, dtheta, h)
     w = copy.deepcopy(wl)
     n_atoms = int(sum(wl["atoms"]))
     n_hops = len(wl["hops"])
@@ -154,11 +183,33 @@ def perturbed(wl, dtheta, h):
     return w
 
 
+def _perturbed_general(wl, dtheta, h):
+    """A general-form workload with its symmetric H entries and rates moved
+    by h * dtheta (entries appended as extra triplets, which add up)."""
+    w = copy.deepcopy(wl)
+    pattern = general_pattern(wl)
+    rows, cols, vals = (list(x) for x in wl["h"])
+    for i, (r, c) in enumerate(pattern):
+        d = dtheta[i]
+        if d == 0.0:
+            continue
+        rows.append(r); cols.append(c); vals.append(h * d)
+        if r != c:
+            rows.append(c); cols.append(r); vals.append(h * d)
+    w["h"] = (np.asarray(rows), np.asarray(cols), np.asarray(vals, float))
+    jumps = [list(x) for x in wl["jumps"]]
+    for j in range(len(jumps)):
+        jumps[j][0] += h * dtheta[len(pattern) + j]
+    w["jumps"] = [tuple(x) for x in jumps]
+    return w
+
+
 def finite_difference(wl, rho0, n_steps, obs, dtheta, h):
     """Central difference (f(theta + h d) - f(theta - h d)) / 2h."""
     vals = []
+    make = evolve.GeneralSystem if wl.get("general") else evolve.System
     for s in (+1.0, -1.0):
-        sysm = evolve.System(perturbed(wl, dtheta, s * h))
+        sysm = make(perturbed(wl, dtheta, s * h))
         rho, _ = evolve.evolve(sysm, rho0, n_steps)
         vals.append(float(np.dot(obs, np.real(np.diag(rho)))))
     return (vals[0] - vals[1]) / (2.0 * h)

@@ -249,3 +249,62 @@ def test_restricted_operator_books_cross_terms_in_the_sink():
     k_diag_only.jumps = [(g, a, sp.diags(k.diagonal()).tocsr()) for g, a, k in k_diag_only.jumps]
     _, sink_wrong = ev.evolve(k_diag_only, rho0[:3, :3], steps)
     assert abs(sink_wrong - sink) > 1e-4
+
+
+# ------------------------------------------------ general-model gradients
+
+from oracle import gradients as GR  # noqa: E402
+
+
+def _collective_general(atoms=(1, 2), cap=1):
+    st, ch = CO.tch_collective(atoms=atoms, cap=cap, g=0.2, mu=0.1, gamma_collective=0.1,
+                               gamma_leak=0.05, dt=0.05)
+    s = ev.System(st)
+    jumps = [(g, *m(s.occ)) for g, m in ch]
+    r, c = np.nonzero(s.h)
+    return st, s, CO.general_workload(st, s.n, (r, c, s.h[r, c]), jumps)
+
+
+def test_general_model_tangent_gradient_matches_finite_differences():
+    """Gradients of a general-form model (parameters: H's symmetric entries,
+    then the rates) with collective decay: the tangent-linear pass against
+    central differences of the whole evolution along random directions."""
+    st, s, wl = _collective_general()
+    g = ev.GeneralSystem(wl)
+    rho0 = W.initial_rho(st, s.occ)
+    obs = np.random.default_rng(20240311 + 42).uniform(0.0, 1.0, g.n)
+    rng = np.random.default_rng(20240311 + 43)
+    for _ in range(2):
+        d = rng.standard_normal(GR.n_params(wl))
+        _, df = GR.tangent(g, rho0, 30, obs, d)
+        fd = GR.finite_difference(wl, rho0, 30, obs, d, 1e-5)
+        assert abs(df - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_general_parameters_chain_to_structured_ones():
+    """A structured model exported to matrices: its g and mu gradients are the
+    general gradient contracted with dH/dg and dH/dmu on the symmetric
+    entries (chain rule), and its rate gradients are equal."""
+    wl = dict(W.tch_2x2(steps=20), jumps=[(W.PHOTON_LEAK, 0, -1, 0.05),
+                                          (W.ATOM_DECAY, 1, 0, 0.03)])
+    wl["g"] = [0.2, 0.15, 0.1, 0.12]
+    s = ev.System(wl)
+    gen = export_general(wl)
+    g = ev.GeneralSystem(gen)
+    rho0 = W.initial_rho(wl, s.occ)
+    obs = np.real(np.diag(rho0)) + 0.5
+    _, grad_s = GR.gradient(s, rho0, 20, obs)
+    pattern = GR.general_pattern(gen)
+    n_h = len(pattern)
+    rng = np.random.default_rng(20240311 + 44)
+    for _ in range(2):
+        d_s = rng.standard_normal(GR.n_params(wl))
+        # the structured direction as a direction in the general parameters
+        dirs = GR.parameter_directions(s)
+        dh = sum(w * item for w, (kind, item) in zip(d_s, dirs) if kind == "h")
+        d_g = np.zeros(GR.n_params(gen))
+        for i, (r, c) in enumerate(pattern):
+            d_g[i] = dh[r, c]
+        d_g[n_h:] = d_s[len(d_s) - len(wl["jumps"]):]
+        _, df_g = GR.tangent(g, rho0, 20, obs, d_g)
+        assert abs(df_g - grad_s @ d_s) < 1e-11 * max(1.0, abs(df_g))
