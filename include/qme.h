@@ -209,6 +209,25 @@ qme_status qme_get_state(const qme_ctx *ctx, const void *state_dev,
 qme_status qme_step(qme_ctx *ctx, void *state_dev, int64_t n_steps,
                     void *workspace_dev, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): qme_step with the step
+ * workspace taken from a fixed device array of QME_NOALLOC_SCRATCH_BYTES
+ * inside the library instead of a caller buffer.  Same kernels and
+ * arithmetic as qme_step with the same knobs: results are bitwise those of
+ * qme_step.  It calls no hipMalloc, hipFree or other allocating routine, and
+ * runs eagerly (no graph replay; no profiling records).  Each device holds
+ * one copy of the array, from library load until the process ends; its
+ * address is looked up at context creation.  Calls on one device share the
+ * array and keep the last call's contents (nothing in it needs to start at
+ * zero), so calls that overlap on one device -- on several streams or
+ * threads, or several contexts -- race; serialise them.
+ * Errors: as qme_step; QME_E_SIZE when the context's workspace
+ * (qme_workspace_size) exceeds QME_NOALLOC_SCRATCH_BYTES (for example FP64
+ * at N = 2048); QME_E_STATE while failure injection is armed.
+ * Asynchronous on hip_stream. */
+#define QME_NOALLOC_SCRATCH_BYTES (80u * 1024u * 1024u)
+qme_status qme_step_noalloc(qme_ctx *ctx, void *state_dev, int64_t n_steps, void *hip_stream);
+
 /* The probabilities of basis states plotted in Figs. 4-8 (Sec. IV) and the
  * trace that the renormalisation of Sec. III.B keeps at 1 - sink.
  * Populations p_s = Re rho_ss (FP64, [N] or NULL), trace sum_s p_s and sink

@@ -61,6 +61,7 @@ SIGNATURES = {
     "qme_get_state": (c_int32, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
                                 POINTER(c_double), c_void_p]),
     "qme_step": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "qme_step_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     "qme_observe": (c_int32, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
                               POINTER(c_double), c_void_p]),
     "qme_observe_weighted": (c_int32, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),

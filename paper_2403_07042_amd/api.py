@@ -192,6 +192,14 @@ class Solver:
         L.check(self.lib.qme_step(self.ctx, c_void_p(st.data_ptr()), int(n_steps),
                                   c_void_p(self.workspace.data_ptr()), self._sptr()))
 
+    def step_noalloc(self, n_steps: int, state=None):
+        """qme_step_noalloc: the same steps with the library's fixed device
+        scratch as the workspace (no allocation; calls on one device must
+        not overlap)."""
+        st = self.state if state is None else state
+        L.check(self.lib.qme_step_noalloc(self.ctx, c_void_p(st.data_ptr()), int(n_steps),
+                                          self._sptr()))
+
     def observe(self, state=None):
         st = self.state if state is None else state
         pops = np.zeros(self.n)

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -39,7 +40,44 @@ using namespace qme;
     }                                                                             \
   } while (0)
 
+// Step workspace of qme_step_noalloc, for callers that cannot allocate
+// device memory: one copy per device, held until the process ends.  Host
+// code never passes `scratch` itself to a kernel or a copy (on the host the
+// name is a stand-in, not a device address): it uses the address
+// hipGetSymbolAddress returned on that device (scratch_address).
+static __device__ __align__(256) unsigned char scratch[QME_NOALLOC_SCRATCH_BYTES];
+
 namespace qme {
+
+// The device address of `scratch` on `device`, looked up once per device
+// with that device current (context creation) and kept.
+static qme_status scratch_address(int device, void **out) {
+  static std::mutex mu;
+  static std::vector<void *> addr;   // per device ordinal; nullptr: not looked up yet
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) {
+    set_error("invalid device");
+    return QME_E_DEVICE;
+  }
+  if (size_t(device) >= addr.size()) addr.resize(size_t(device) + 1, nullptr);
+  if (!addr[size_t(device)]) {
+    int cur = -1;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != device) {
+      set_error("scratch_address: device is not current");
+      return QME_E_DEVICE;
+    }
+    void *p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_error("hipGetSymbolAddress returned no address for the step scratch");
+      return QME_E_DEVICE;
+    }
+    addr[size_t(device)] = p;
+  }
+  *out = addr[size_t(device)];
+  return QME_OK;
+}
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -374,6 +412,10 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
 
   HIP_OK(hipGetDevice(&c->device));
   HIP_OK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  {
+    const qme_status st = scratch_address(c->device, &c->scratch);
+    if (st != QME_OK) return st;
+  }
   pick_tiles(c);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const size_t pe = plane_elems(c);
@@ -812,6 +854,45 @@ extern "C" qme_status qme_step(qme_ctx *c, void *state, int64_t n_steps, void *w
   }
   HIP_OK(hipGraphLaunch(it->second, s));
   return QME_OK;
+  QME_GUARD_END
+}
+
+extern "C" qme_status qme_step_noalloc(qme_ctx *c, void *state, int64_t n_steps,
+                                       void *hip_stream) {
+  QME_GUARD_BEGIN
+  TraceRange range("qme_step_noalloc");
+  set_error("");
+  if (!c || !state) { set_error("NULL argument"); return QME_E_ARG; }
+  if (n_steps < 0) { set_error("n_steps < 0"); return QME_E_ARG; }
+  if (reinterpret_cast<uintptr_t>(state) & 255) {
+    set_error("state must be 256-byte aligned");
+    return QME_E_ARG;
+  }
+  size_t need = 0;
+  qme_status st = qme_workspace_size(c, &need);
+  if (st != QME_OK) return st;
+  if (need > size_t(QME_NOALLOC_SCRATCH_BYTES)) {
+    set_error("qme_step_noalloc: the step workspace of this context (" + std::to_string(need) +
+              " bytes) exceeds the library's fixed scratch of " +
+              std::to_string(size_t(QME_NOALLOC_SCRATCH_BYTES)) + " bytes; use qme_step");
+    return QME_E_SIZE;
+  }
+  st = check_device(c);
+  if (st != QME_OK) return st;
+  if (!c->scratch) { set_error("no scratch address for this context's device"); return QME_E_DEVICE; }
+  if (c->fault_at >= 0 && c->steps_done + n_steps > c->fault_at) {
+    set_error("qme_step_noalloc: failure injection (QME_FAULT_AT_STEP) is served by qme_step");
+    return QME_E_STATE;
+  }
+  // eager launches only (a graph capture or profiling events would allocate)
+  const bool was_profiling = c->profiling;
+  c->profiling = false;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const qme_status r = c->elem == 8 ? step_impl<double>(c, state, n_steps, c->scratch, s)
+                                    : step_impl<float>(c, state, n_steps, c->scratch, s);
+  c->profiling = was_profiling;
+  if (r == QME_OK) c->steps_done += n_steps;
+  return r;
   QME_GUARD_END
 }
 

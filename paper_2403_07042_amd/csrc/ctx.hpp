@@ -37,6 +37,7 @@ struct qme_ctx {
   void drop_graphs();
   int device = 0;
   int cus = 0;                        // compute units of the device
+  void *scratch = nullptr;            // device address of the no-allocation workspace
   // device tables (owned)
   void *du_re = nullptr, *du_im = nullptr;   // dU planes, ld x ld, storage type
   void *du_split = nullptr;                  // BF16X3: dU as six bf16 planes (split once)
