@@ -251,9 +251,15 @@ qme_status qme_observe_weighted(const qme_ctx *ctx, const void *state_dev,
  * time step (the parameter fit of the paper's fourth modelling point,
  * Sec. II, needs them).  The forward pass keeps a checkpoint every
  * checkpoint_every steps and recomputes each segment backwards.  Outputs:
- * *value = f (may be NULL) and grad[n_atoms + n_hops + n_jumps] in the order
- * g per atom (cavity-major), mu per hop, gamma per jump.  The Frechet
- * derivative of exp(-i H dt) is evaluated on the host in FP64; the adjoint
+ * *value = f (may be NULL) and grad[qme_gradient_size] in the order g per
+ * atom (cavity-major), mu per hop, gamma per jump; for a context made by
+ * qme_hamiltonian_general the Hamiltonian parameters are H's symmetric
+ * entries instead -- one per pair (r, c), r <= c, of the pattern of the
+ * given triplets (duplicates merged), in (r, c) order, each moving H[r][c]
+ * and H[c][r] together (zero for an entry a qme_subspace restriction
+ * removed) -- then gamma per jump.  The Frechet derivative of
+ * exp(-i H dt) is evaluated in FP64 (on the device; on the host when the
+ * propagator needed squarings); the adjoint
  * products run in the context's storage arithmetic (FP32 for QME_BF16X3,
  * whose forward recomputation still uses the split-bf16 products).  state0 is
  * not modified.  workspace: device memory of at least
@@ -263,16 +269,22 @@ qme_status qme_adjoint(qme_ctx *ctx, const void *state0_dev, int64_t n_steps,
                        double *grad, void *workspace_dev, size_t workspace_bytes,
                        void *hip_stream);
 
+/* Number of entries qme_adjoint writes to grad for this context. */
+qme_status qme_gradient_size(const qme_ctx *ctx, int64_t *n_params);
+
 /* Device workspace qme_adjoint needs for these arguments. */
 qme_status qme_adjoint_workspace_size(const qme_ctx *ctx, int64_t n_steps,
                                       int32_t checkpoint_every, size_t *bytes);
 
 /* ---------------------------------------------------- general models */
 
-/* One decoherence operator in monomial form (each basis state has at most
- * one image and at most one preimage): A |source[e]> = coef[e] |target[e]>,
- * target -1 meaning the image leaves the basis (its probability goes to the
- * sink); rate gamma >= 0. */
+/* One decoherence operator A_j of Sec. II, Eq. 3, as moves: A |source[e]>
+ * has the component coef[e] |target[e]>, summed over its moves (moves with
+ * the same source and target add up), so a state may have several images
+ * and several preimages.  target -1: a component outside the basis (its
+ * probability goes to the sink), orthogonal to every other component;
+ * rate gamma >= 0.  Errors (QME_E_ARG): indices out of range, non-finite
+ * coefficients or rates, NULL arrays with n_moves > 0. */
 typedef struct {
   double gamma;
   int64_t n_moves;
@@ -286,11 +298,15 @@ typedef struct {
  * hydrogen-bond model of Sec. IV.A (Eqs. 4-9), whose couplings are
  * conditional on other modes and include non-RWA terms.  H: real symmetric
  * n x n as COO triplets (duplicates summed; the summed matrix must equal its
- * transpose exactly, else QME_E_ARG); jumps: monomial decoherence operators
- * (QME_E_UNSUPPORTED when an operator is not monomial).  The step, batching,
- * selection (qme_subspace) and observation work as for qme_hamiltonian;
- * qme_adjoint returns QME_E_UNSUPPORTED (the gradient parameters are those of
- * qme_params).  Synchronous. */
+ * transpose exactly, else QME_E_ARG); jumps: decoherence operators as
+ * moves (see qme_general_jump).  The step, batching, selection
+ * (qme_subspace), observation and gradients (qme_adjoint, with respect to
+ * H's symmetric entries and the rates) work as for qme_hamiltonian.
+ * Operators that give a state at most one move and a target at most one
+ * source run in the gather form of the structured channels; the others
+ * (several images or preimages, e.g. collective decay of several atoms)
+ * in sparse form: per element of the decoherence pass a double sum over
+ * the two rows of A, plus the off-diagonal part of A^dag A.  Synchronous. */
 qme_status qme_hamiltonian_general(int64_t n, int64_t h_nnz, const int32_t *h_rows,
                                    const int32_t *h_cols, const double *h_vals, int32_t n_jumps,
                                    const qme_general_jump *jumps, double dt, int32_t precision,
@@ -403,6 +419,23 @@ qme_status qme_batch_workspace_size(const qme_batch *batch, size_t *bytes);
  * tiles (set them with qme_set_tiles, then call this) and drops earlier
  * captures.  Synchronises the device. */
 qme_status qme_batch_config(qme_batch *batch, int32_t use_graph, int32_t largest_first);
+
+/* Persistent form of the batched run (off by default): with enable = 1 a run
+ * of n steps is ONE launch in which workgroups take (step, phase, instance,
+ * tile) items in order from a global counter and each item waits only until
+ * its own instance has finished the earlier phases (per-instance counters in
+ * the batch workspace), so a small instance's next phase starts while large
+ * instances are still in their last tiles.  Items are taken in order, so the
+ * waits cannot deadlock whatever the number of resident workgroups; a wait
+ * that exceeds a fixed bound ends the run and every instance's sink becomes
+ * NaN (qme_observe then returns QME_E_NUMERIC).  Same tile arithmetic as the
+ * phase launches: bitwise-identical results.  QME_E_SIZE from qme_batch_step
+ * when a run is too long for the 32-bit counters (then split it).
+ * Synchronises the device.
+ * Switched off in this version: enable = 1 returns QME_E_UNSUPPORTED (the
+ * launches did not finish on the device and the cause has not been
+ * established); enable = 0 keeps the phase launches. */
+qme_status qme_batch_persistent(qme_batch *batch, int32_t enable);
 
 /* Advance every instance by n_steps on hip_stream (asynchronous). */
 qme_status qme_batch_step(qme_batch *batch, int64_t n_steps, void *workspace_dev,

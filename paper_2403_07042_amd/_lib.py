@@ -71,11 +71,13 @@ SIGNATURES = {
                             c_int32, c_int32, c_int32, c_void_p]),
     "qme_adjoint": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, POINTER(c_double),
                               POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p]),
+    "qme_gradient_size": (c_int32, [c_void_p, POINTER(c_int64)]),
     "qme_adjoint_workspace_size": (c_int32, [c_void_p, c_int64, c_int32, POINTER(c_size_t)]),
     "qme_batch_create": (c_int32, [POINTER(c_void_p), POINTER(c_void_p), c_int32,
                                    POINTER(c_void_p)]),
     "qme_batch_workspace_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
     "qme_batch_config": (c_int32, [c_void_p, c_int32, c_int32]),
+    "qme_batch_persistent": (c_int32, [c_void_p, c_int32]),
     "qme_batch_step": (c_int32, [c_void_p, c_int64, c_void_p, c_size_t, c_void_p]),
     "qme_batch_destroy": (None, [c_void_p]),
     "qme_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),

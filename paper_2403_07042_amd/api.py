@@ -223,7 +223,8 @@ class Solver:
     def adjoint(self, n_steps: int, obs, checkpoint_every: int = 32, state=None):
         """(f, grad) for f = sum_s obs[s] Re rho_K[s,s] after n_steps from the
         given state (default: this solver's state, left unchanged); grad is
-        ordered g per atom, mu per hop, gamma per jump."""
+        ordered g per atom, mu per hop, gamma per jump (general-form models:
+        H's symmetric entries in (r, c) order, r <= c, then gamma per jump)."""
         st = self.state if state is None else state
         obs = np.ascontiguousarray(np.asarray(obs, dtype=np.float64))
         if obs.shape != (self.n,):
@@ -232,8 +233,9 @@ class Solver:
         L.check(self.lib.qme_adjoint_workspace_size(self.ctx, int(n_steps), int(checkpoint_every),
                                                     byref(ws)))
         buf = self.torch.empty(max(ws.value, 256), dtype=self.torch.uint8, device=st.device)
-        n_par = 0 if self.general else (int(sum(self.wl["atoms"])) + len(self.wl.get("hops", []))
-                                         + len(self.wl.get("jumps", [])))
+        np_c = c_int64()
+        L.check(self.lib.qme_gradient_size(self.ctx, byref(np_c)))
+        n_par = np_c.value
         grad = np.zeros(max(n_par, 1))
         val = c_double()
         L.check(self.lib.qme_adjoint(self.ctx, c_void_p(st.data_ptr()), int(n_steps),
@@ -376,6 +378,10 @@ class Batch:
 
     def config(self, use_graph=True, largest_first=True):
         L.check(self.lib.qme_batch_config(self.handle, int(use_graph), int(largest_first)))
+
+    def persistent(self, enable=True):
+        """One launch per run (qme_batch_persistent) on or off."""
+        L.check(self.lib.qme_batch_persistent(self.handle, int(bool(enable))))
 
     def step(self, n_steps: int):
         L.check(self.lib.qme_batch_step(self.handle, int(n_steps),

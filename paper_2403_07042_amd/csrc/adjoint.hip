@@ -97,6 +97,46 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
             mi += w * gi;
           }
         }
+        if (p.n_csr > 0 || p.koff_ptr) {
+          // sparse channels: gamma A^T lam A and -1/2 {K_off, lam}
+          double ar = 0.0, ai = 0.0;
+          for (int ch = 0; ch < p.n_csr; ++ch) {
+            const int64_t *ptr = p.csrt_ptr + int64_t(ch) * (n + 1);
+            double cr = 0.0, ci = 0.0;
+            for (int64_t x = ptr[u]; x < ptr[u + 1]; ++x) {
+              const int32_t k = p.csrt_col[x];
+              const double a = p.csrt_val[x];
+              for (int64_t y = ptr[v]; y < ptr[v + 1]; ++y) {
+                double gr, gi;
+                herm_at(p.l_re, p.l_im, ld, k, p.csrt_col[y], gr, gi);
+                const double w = a * p.csrt_val[y];
+                cr += w * gr;
+                ci += w * gi;
+              }
+            }
+            ar += p.csr_gamma[ch] * cr;
+            ai += p.csr_gamma[ch] * ci;
+          }
+          if (p.koff_ptr) {
+            double kr = 0.0, ki = 0.0;
+            for (int64_t x = p.koff_ptr[u]; x < p.koff_ptr[u + 1]; ++x) {
+              double gr, gi;
+              herm_at(p.l_re, p.l_im, ld, p.koff_col[x], v, gr, gi);
+              kr += p.koff_val[x] * gr;
+              ki += p.koff_val[x] * gi;
+            }
+            for (int64_t y = p.koff_ptr[v]; y < p.koff_ptr[v + 1]; ++y) {
+              double gr, gi;
+              herm_at(p.l_re, p.l_im, ld, u, p.koff_col[y], gr, gi);
+              kr += p.koff_val[y] * gr;
+              ki += p.koff_val[y] * gi;
+            }
+            ar -= 0.5 * kr;
+            ai -= 0.5 * ki;
+          }
+          mr += dt * ar;
+          mi += dt * ai;
+        }
         if (u == v) mi = 0.0;
         p.mu_re[o] = T(mr);
         p.mu_im[o] = T(mi);
@@ -160,6 +200,82 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
     p.mu_re[vrow * ld + ucol] = s_re[c][a];
     p.mu_im[vrow * ld + ucol] = -s_im[c][a];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) void adj_sparse_gamma_kernel(AdjSparseArgs<T> p) {
+  constexpr int TD = kAdjTile;
+  __shared__ double s_w[kAdjThreads / 64];
+  const int t = blockIdx.x, q = blockIdx.y;
+  int bi = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  while (bi * (bi + 1) / 2 > t) --bi;
+  const int bj = t - bi * (bi + 1) / 2;
+  const int c = threadIdx.x & (TD - 1);
+  const int r0 = threadIdx.x / TD;
+  const int64_t v = int64_t(bj) * TD + c;
+  const int64_t n = p.n, ld = p.ld;
+  const int64_t *aptr = p.csr_ptr + int64_t(q) * (n + 1);
+  const int64_t *kptr = p.kj_ptr + int64_t(q) * (n + 1);
+  double acc = 0.0;
+  for (int rr = r0; rr < TD; rr += kAdjThreads / TD) {
+    const int64_t u = int64_t(bi) * TD + rr;
+    if (u >= n || v >= n || (bi == bj && v > u)) continue;
+    double er = 0.0, ei = 0.0;
+    for (int64_t x = aptr[u]; x < aptr[u + 1]; ++x) {      // (A Z A^T)[u,v]
+      const int32_t k = p.csr_col[x];
+      const double a = p.csr_val[x];
+      for (int64_t y = aptr[v]; y < aptr[v + 1]; ++y) {
+        double zr, zi;
+        herm_at(p.z_re, p.z_im, ld, k, p.csr_col[y], zr, zi);
+        const double w = a * p.csr_val[y];
+        er += w * zr;
+        ei += w * zi;
+      }
+    }
+    double kr = 0.0, ki = 0.0;
+    for (int64_t x = kptr[u]; x < kptr[u + 1]; ++x) {      // (K_off Z)[u,v]
+      double zr, zi;
+      herm_at(p.z_re, p.z_im, ld, p.kj_col[x], v, zr, zi);
+      kr += p.kj_val[x] * zr;
+      ki += p.kj_val[x] * zi;
+    }
+    for (int64_t y = kptr[v]; y < kptr[v + 1]; ++y) {      // (Z K_off)[u,v]
+      double zr, zi;
+      herm_at(p.z_re, p.z_im, ld, u, p.kj_col[y], zr, zi);
+      kr += p.kj_val[y] * zr;
+      ki += p.kj_val[y] * zi;
+    }
+    er -= 0.5 * kr;
+    ei -= 0.5 * ki;
+    const int64_t o = u * ld + v;
+    const double lr = double(p.l_re[o]), li = double(p.l_im[o]);
+    acc += (u == v ? 1.0 : 2.0) * (lr * er + li * ei);
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = s_w[0];
+    for (int w = 1; w < kAdjThreads / 64; ++w) sum += s_w[w];
+    p.part[int64_t(q) * gridDim.x + t] = sum;
+  }
+}
+
+__global__ __launch_bounds__(256) void sparse_gamma_reduce_kernel(const double *part, int blocks,
+                                                                  const int32_t *channel,
+                                                                  double dt, double *grad) {
+  __shared__ double s[256];
+  const int q = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += 256) acc += part[int64_t(q) * blocks + b];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[channel[q]] += dt * s[0];
 }
 
 __global__ void q_reduce_kernel(const double *rowbuf, const double *colbuf, int64_t n,
@@ -290,6 +406,24 @@ hipError_t launch_adj_dissipate(const AdjArgs<T> &a, hipStream_t s) {
   return hipSuccess;
 }
 
+template <typename T>
+hipError_t launch_adj_sparse_gamma(const AdjSparseArgs<T> &a, hipStream_t s) {
+  if (a.n_csr == 0) return hipSuccess;
+  const int tiles = int((a.n + kAdjTile - 1) / kAdjTile);
+  const int blocks = tiles * (tiles + 1) / 2;
+  hipLaunchKernelGGL(adj_sparse_gamma_kernel<T>, dim3(blocks, a.n_csr), dim3(kAdjThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sparse_gamma_reduce(const double *part, int blocks, int n_csr,
+                                      const int32_t *channel, double dt, double *grad,
+                                      hipStream_t s) {
+  if (n_csr == 0) return hipSuccess;
+  hipLaunchKernelGGL(sparse_gamma_reduce_kernel, dim3(n_csr), dim3(256), 0, s, part, blocks,
+                     channel, dt, grad);
+  return hipGetLastError();
+}
+
 hipError_t launch_q_reduce(const double *rowbuf, const double *colbuf, int64_t n, double *q,
                            hipStream_t s) {
   const int tiles = int((n + kAdjTile - 1) / kAdjTile);
@@ -316,6 +450,8 @@ hipError_t launch_set_diag(T *x_re, T *x_im, int64_t ld, int64_t n, const double
   return hipGetLastError();
 }
 
+template hipError_t launch_adj_sparse_gamma<float>(const AdjSparseArgs<float> &, hipStream_t);
+template hipError_t launch_adj_sparse_gamma<double>(const AdjSparseArgs<double> &, hipStream_t);
 template hipError_t launch_adj_dissipate<float>(const AdjArgs<float> &, hipStream_t);
 template hipError_t launch_adj_dissipate<double>(const AdjArgs<double> &, hipStream_t);
 template hipError_t launch_set_diag<float>(float *, float *, int64_t, int64_t, const double *,
@@ -333,6 +469,7 @@ struct AdjLayout {
   int64_t nseg = 0, seg = 0;
   size_t S = 0, cp = 0, R = 0, Zs = 0, Y = 0, lam = 0, mu = 0, X = 0, G = 0;
   size_t rowbuf = 0, colbuf = 0, gbuf = 0, q = 0, o = 0, grad = 0, diag = 0, total = 0;
+  size_t gsp = 0;   // sparse channels' rate-gradient partials
   size_t fw = 0, fm = 0, fm2 = 0, fr = 0, fr2 = 0, fterm = 0;
   int tiles = 0, blocks = 0;
 };
@@ -362,6 +499,7 @@ static AdjLayout adj_layout(const qme_ctx *c, int64_t n_steps, int32_t every) {
   L.rowbuf = take(sizeof(double) * size_t(L.tiles) * n);
   L.colbuf = take(sizeof(double) * size_t(L.tiles) * n);
   L.gbuf = take(sizeof(double) * size_t(L.blocks) * size_t(std::max(1, c->n_arrival)));
+  L.gsp = take(sizeof(double) * size_t(L.blocks) * size_t(std::max(1, c->jt.n_csr)));
   L.q = take(sizeof(double) * n);
   L.o = take(sizeof(double) * n);
   L.grad = take(sizeof(double) * std::max<size_t>(1, c->model.jumps.size()));
@@ -473,6 +611,17 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
                 c->tau, c->ca, c->jt.n_gather, c->upi, c->uc, c->n_arrival,
                 reinterpret_cast<double *>(ws + L.rowbuf), reinterpret_cast<double *>(ws + L.colbuf),
                 reinterpret_cast<double *>(ws + L.gbuf)};
+  aa.n_csr = c->jt.n_csr;
+  aa.csrt_ptr = c->csrt_ptr;
+  aa.csrt_col = c->csrt_col;
+  aa.csrt_val = c->csrt_val;
+  aa.csr_gamma = c->csr_gamma;
+  aa.koff_ptr = c->jt.koff_col.empty() ? nullptr : c->koff_ptr;
+  aa.koff_col = c->koff_col;
+  aa.koff_val = c->koff_val;
+  AdjSparseArgs<T> sa{lam_re, lam_im, nullptr, nullptr, c->ld, n, c->jt.n_csr, c->csr_ptr,
+                      c->csr_col, c->csr_val, c->kj_ptr, c->kj_col, c->kj_val,
+                      reinterpret_cast<double *>(ws + L.gsp)};
   double *q = reinterpret_cast<double *>(ws + L.q);
   GemmOps ox, ol, og;
   ox.conj_a = true;   // X = mu + conj(dU) mu   (mu^H = mu)
@@ -500,6 +649,11 @@ static qme_status adjoint_impl(qme_ctx *c, const void *state0, int64_t n_steps, 
       ADJ_OK(launch_q_reduce(aa.rowbuf, aa.colbuf, n, q, s));
       ADJ_OK(launch_gamma_reduce(aa.gbuf, L.blocks, c->n_arrival, c->arrival_of, c->ada, q, n,
                                  nj, c->model.dt, ggam, s));
+      sa.z_re = z_re;
+      sa.z_im = z_im;
+      ADJ_OK(launch_adj_sparse_gamma<T>(sa, s));
+      ADJ_OK(launch_sparse_gamma_reduce(sa.part, L.blocks, c->jt.n_csr, c->csr_channel,
+                                        c->model.dt, ggam, s));
       ADJ_OK(gemm<T>(c, c->tile1, ox, u_re, u_im, mu_re, mu_im, mu_re, mu_im, x_re, x_im, s));
       // mu is dead once X is formed: it holds the split partials
       ADJ_OK(gemm<T>(c, c->tile2, ol, x_re, x_im, u_re, u_im, x_re, x_im, lam_re, lam_im, s, mu_re));
@@ -621,10 +775,6 @@ extern "C" qme_status qme_adjoint(qme_ctx *c, const void *state0, int64_t n_step
     TraceRange range("qme_adjoint");
     set_error("");
     if (!c || !state0 || !obs || !grad || !ws) { set_error("NULL argument"); return QME_E_ARG; }
-    if (c->model.general) {
-      set_error("gradients need a context built from qme_system / qme_params");
-      return QME_E_UNSUPPORTED;
-    }
     if (n_steps < 0 || checkpoint_every < 1) { set_error("n_steps < 0 or checkpoint_every < 1"); return QME_E_ARG; }
     if ((reinterpret_cast<uintptr_t>(ws) | reinterpret_cast<uintptr_t>(state0)) & 255) {
       set_error("state and workspace must be 256-byte aligned");

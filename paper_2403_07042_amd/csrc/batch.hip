@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <map>
 #include <numeric>
@@ -63,24 +64,22 @@ __device__ __forceinline__ void tri_coords(int t, int &bi, int &bj) {
   bj = t - r * (r + 1) / 2;
 }
 
+constexpr int kGemmSmem = cgemm_f32_smem<64, kConjB>() > cgemm_s_smem<float, 32, kConjB>()
+                              ? cgemm_f32_smem<64, kConjB>()
+                              : cgemm_s_smem<float, 32, kConjB>();
 template <int PHASE>
-__global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p) {
-  constexpr int kGemmSmem = cgemm_f32_smem<64, kConjB>() > cgemm_s_smem<float, 32, kConjB>()
-                                ? cgemm_f32_smem<64, kConjB>()
-                                : cgemm_s_smem<float, 32, kConjB>();
-  constexpr int kSmemFloats =
-      PHASE <= 1 ? kGemmSmem
-      : PHASE == 2 ? 3 * kBatchThreads * 2
-                   : 2 * TD * (TD + 1) + int(sizeof(GatherLds) / sizeof(float)) + 2;
-  __shared__ float smem[kSmemFloats];
-  const int64_t r = blockIdx.x;
-  int lo = 0, hi = p.count;   // largest position with off[pos] <= r
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (p.off[mid] <= r) lo = mid; else hi = mid;
-  }
-  const BatchInstance &in = p.inst[p.order[lo]];
-  const int tile = int(r - p.off[lo]);
+constexpr int phase_smem() {
+  return PHASE <= 1 ? kGemmSmem
+         : PHASE == 2 ? 3 * kBatchThreads * 2
+                      : 2 * TD * (TD + 1) + int(sizeof(GatherLds) / sizeof(float)) + 2;
+}
+constexpr int kPersistSmem =
+    std::max(std::max(phase_smem<0>(), phase_smem<1>()), std::max(phase_smem<2>(), phase_smem<3>()));
+
+// One item of a phase: tile `tile` of the instance at queue position `pos`.
+// PHASE 3 with SPARSE: the decoherence body with the sparse channels' terms.
+template <int PHASE, bool SPARSE>
+__device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, float *smem) {
   if constexpr (PHASE == 0) {
     const CgemmArgs<float> g{in.u_re, in.u_im, in.x_re, in.x_im, in.x_re, in.x_im,
                              in.y_re, in.y_im, in.ld, 1.0f, 1.0f};
@@ -121,9 +120,161 @@ __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p
       // 8-byte aligned start for the tables after the two staging arrays
       float *gp = smem + 2 * TD * (TD + 1);
       gp += (reinterpret_cast<uintptr_t>(gp) & 7) ? 1 : 0;
-      dissipate_tile<float>(da, tile, sr, si, reinterpret_cast<GatherLds *>(gp));
+      dissipate_tile<float, SPARSE>(da, tile, sr, si, reinterpret_cast<GatherLds *>(gp));
     }
   }
+}
+
+// Queue position of item r of a phase (largest position with off[pos] <= r).
+__device__ __forceinline__ int find_position(const int64_t *off, int count, int64_t r) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= r) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <int PHASE, bool SPARSE = false>
+__global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p) {
+  __shared__ float smem[phase_smem<PHASE>()];
+  const int64_t r = blockIdx.x;
+  const int lo = find_position(p.off, p.count, r);
+  batch_item<PHASE, SPARSE>(p.inst[p.order[lo]], int(r - p.off[lo]), smem);
+}
+
+// ------------------------------------------------------------ persistent form
+// One launch runs every step of a run.  The items are (step, phase,
+// instance, tile) in that order (instances largest first inside a phase);
+// each workgroup takes the next item from a global counter, waits until the
+// item's instance has finished every item of the earlier phases and steps
+// (a per-instance completion counter), runs it, and counts it done.
+//   * Progress: items are taken in order and an item waits only on items of
+//     smaller index, so the earliest unfinished item has all its
+//     predecessors taken -- hence finished -- and proceeds: no deadlock,
+//     whatever the number of resident workgroups.
+//   * Visibility across XCDs (each has its own L2): after the workgroup
+//     barrier that ends an item, one thread increments the counter with an
+//     agent-scope release (it writes the L2's dirty lines back first).  The
+//     wait polls with relaxed agent-scope loads, which read the counter past
+//     the caches without invalidating them, and acquires once, when the
+//     count is reached; every wave then acquires after the barrier that ends
+//     the wait.  (An acquire on every poll would invalidate the caches of
+//     the compute unit on every iteration of every waiting workgroup and
+//     starve the items that are running.)
+//   * Termination: a wait gives up after spin_limit polls or wait_ticks of
+//     the 100 MHz real-time counter (far above any real wait), sets the
+//     abort flag and leaves; every workgroup checks the flag before taking
+//     an item and every 64 polls, so the launch ends.  A closing pass then
+//     marks every instance's sink NaN (qme_observe reports
+//     QME_E_NUMERIC).
+struct PersistArgs {
+  const BatchInstance *inst;
+  const int32_t *order;
+  const int64_t *phase_off;   // [4][count + 1]
+  int32_t count;
+  int64_t phase_items[4];
+  int64_t per_step, total;
+  uint32_t *done;             // [count], per queue position
+  unsigned long long *next;
+  uint32_t *abort_flag;
+  uint32_t spin_limit;
+  uint64_t wait_ticks;        // bound of one wait on the 100 MHz real-time counter
+};
+
+// (four waves per SIMD, the phase kernels' own occupancy: the bound keeps the
+// four inlined bodies within the register budget of one of them)
+template <bool SPARSE>
+__global__ __launch_bounds__(kBatchThreads, 4) void batch_persistent_kernel(PersistArgs a) {
+  __shared__ float smem[kPersistSmem];
+  __shared__ int s_item;
+  __shared__ int s_go;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int g = -1;
+      if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        const unsigned long long t =
+            __hip_atomic_fetch_add(a.next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < (unsigned long long)a.total) g = int(t);
+      }
+      s_item = g;
+    }
+    __syncthreads();
+    // the item is the same for the whole workgroup: keep it (and everything
+    // derived from it) in scalar registers
+    const int g = __builtin_amdgcn_readfirstlane(s_item);
+    if (g < 0) return;
+    const int64_t k = g / a.per_step;
+    int64_t r = g - k * a.per_step;
+    int ph = 0;
+    while (r >= a.phase_items[ph]) r -= a.phase_items[ph++];
+    const int64_t *off = a.phase_off + ph * (a.count + 1);
+    const int pos = find_position(off, a.count, r);
+    const BatchInstance &in = a.inst[a.order[pos]];
+    const int tile = int(r - off[pos]);
+    __syncthreads();   // every wave has read s_item before it is written again
+    if (threadIdx.x == 0) {
+      uint32_t per_inst = 0, before = 0;
+      for (int q = 0; q < 4; ++q) {
+        per_inst += in.items[q];
+        if (q < ph) before += in.items[q];
+      }
+      const uint32_t need = uint32_t(k) * per_inst + before;
+      uint32_t spins = 0;
+      int go = 1;
+      if (__hip_atomic_load(a.done + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(a.done + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          ++spins;
+          if ((spins & 63u) == 0u) {
+            if (spins > a.spin_limit || __builtin_amdgcn_s_memrealtime() - t0 > a.wait_ticks) {
+              __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              go = 0;
+              break;
+            }
+            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+              go = 0;
+              break;
+            }
+          }
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      if (go) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_go = go;
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(s_go)) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    switch (ph) {
+      case 0: batch_item<0, SPARSE>(in, tile, smem); break;
+      case 1: batch_item<1, SPARSE>(in, tile, smem); break;
+      case 2: batch_item<2, SPARSE>(in, tile, smem); break;
+      default: batch_item<3, SPARSE>(in, tile, smem); break;
+    }
+    __syncthreads();   // every wave's writes done; LDS free for the next item
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(a.done + pos, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Counters of a persistent run set to zero (a kernel, not a memset, so the
+// run can sit in a captured graph).
+__global__ void persist_reset_kernel(uint32_t *done, int count, unsigned long long *next,
+                                     uint32_t *abort_flag) {
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) done[i] = 0u;
+  if (i == 0) {
+    *next = 0ull;
+    *abort_flag = 0u;
+  }
+}
+
+// After a persistent run: if it gave up, every instance's sink becomes NaN.
+__global__ void persist_finish_kernel(const BatchInstance *inst, int count,
+                                      const uint32_t *abort_flag) {
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count && *abort_flag != 0u) inst[i].aux[0] = __builtin_nan("");
 }
 
 }  // namespace qme
@@ -137,6 +288,10 @@ struct qme_batch {
   int32_t count = 0;
   bool use_graph = true;
   bool lpt = true;
+  bool sparse = false;              // some instance has sparse decoherence channels
+  bool persistent = false;          // qme_batch_persistent
+  int resident = 0;                 // workgroups of the persistent kernel that fit the device
+  size_t ctr_off = 0;               // workspace offset of the persistent run's counters
   // device tables (owned)
   BatchInstance *inst = nullptr;
   int32_t *order = nullptr;
@@ -183,6 +338,7 @@ static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 
 static qme_status build_tables(qme_batch *b) {
   const int nb = b->count;
+  b->sparse = false;
   std::vector<int32_t> ord(nb);
   std::iota(ord.begin(), ord.end(), 0);
   if (b->lpt)
@@ -218,13 +374,18 @@ static qme_status build_tables(qme_batch *b) {
     t.n_gather = c->jt.n_gather;
     t.sparse = DissArgs<float>{};
     c->sparse_args(t.sparse);
+    if (t.sparse.n_csr > 0 || t.sparse.koff_ptr) b->sparse = true;
     const int td = int((c->n + TD - 1) / TD);
     t.items[0] = uint32_t(t.tiles1) * uint32_t(t.tiles1);
     t.items[1] = uint32_t(t.tiles2) * uint32_t(t.tiles2 + 1) / 2;
     t.items[2] = 1;
     t.items[3] = uint32_t(td) * uint32_t(td + 1) / 2;
   }
-  b->ws_bytes = std::max<size_t>(off, 256);
+  // counters of the persistent form: per-instance completion counts, the
+  // item counter and the abort flag
+  b->ctr_off = off;
+  off += a256(sizeof(uint32_t) * size_t(nb)) + 256;
+  b->ws_bytes = off;
   std::vector<int64_t> po(4 * (nb + 1), 0);
   for (int ph = 0; ph < 4; ++ph) {
     int64_t acc = 0;
@@ -263,7 +424,43 @@ static qme_status bind_workspace(qme_batch *b, char *ws) {
   return QME_OK;
 }
 
+static hipError_t enqueue_persistent(qme_batch *b, int64_t n_steps, hipStream_t s) {
+  char *ws = static_cast<char *>(b->last_ws);
+  PersistArgs a{};
+  a.inst = b->inst;
+  a.order = b->order;
+  a.phase_off = b->phase_off;
+  a.count = b->count;
+  a.per_step = 0;
+  for (int ph = 0; ph < 4; ++ph) {
+    a.phase_items[ph] = b->phase_items[ph];
+    a.per_step += b->phase_items[ph];
+  }
+  a.total = a.per_step * n_steps;
+  a.done = reinterpret_cast<uint32_t *>(ws + b->ctr_off);
+  a.next = reinterpret_cast<unsigned long long *>(ws + b->ctr_off + a256(sizeof(uint32_t) * size_t(b->count)));
+  a.abort_flag = reinterpret_cast<uint32_t *>(a.next + 1);
+  a.spin_limit = 1u << 22;
+  a.wait_ticks = 100000000ull;   // 1 s
+  const int rb = (b->count + 255) / 256;
+  hipLaunchKernelGGL(persist_reset_kernel, dim3(rb), dim3(256), 0, s, a.done, b->count, a.next,
+                     a.abort_flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned grid = unsigned(std::min<int64_t>(a.total, int64_t(b->resident)));
+  if (b->sparse)
+    hipLaunchKernelGGL(batch_persistent_kernel<true>, dim3(grid), dim3(kBatchThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(batch_persistent_kernel<false>, dim3(grid), dim3(kBatchThreads), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(persist_finish_kernel, dim3(rb), dim3(256), 0, s, b->inst, b->count,
+                     a.abort_flag);
+  return hipGetLastError();
+}
+
 static hipError_t enqueue(qme_batch *b, int64_t n_steps, hipStream_t s) {
+  if (b->persistent) return enqueue_persistent(b, n_steps, s);
   for (int64_t k = 0; k < n_steps; ++k) {
     for (int ph = 0; ph < 4; ++ph) {
       const BatchPhase p{b->inst, b->order, b->phase_off + ph * (b->count + 1), b->count};
@@ -272,7 +469,12 @@ static hipError_t enqueue(qme_batch *b, int64_t n_steps, hipStream_t s) {
         case 0: hipLaunchKernelGGL(batch_phase_kernel<0>, grid, block, 0, s, p); break;
         case 1: hipLaunchKernelGGL(batch_phase_kernel<1>, grid, block, 0, s, p); break;
         case 2: hipLaunchKernelGGL(batch_phase_kernel<2>, grid, block, 0, s, p); break;
-        default: hipLaunchKernelGGL(batch_phase_kernel<3>, grid, block, 0, s, p); break;
+        default:
+          if (b->sparse)
+            hipLaunchKernelGGL((batch_phase_kernel<3, true>), grid, block, 0, s, p);
+          else
+            hipLaunchKernelGGL((batch_phase_kernel<3, false>), grid, block, 0, s, p);
+          break;
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -310,6 +512,16 @@ extern "C" qme_status qme_batch_create(qme_ctx *const *ctxs, void *const *states
     if (st != QME_OK) return st;
     st = build_tables(b.get());
     if (st != QME_OK) return st;
+    {
+      // workgroups of the persistent kernel that fit the device at once (the
+      // persistent grid; more would only queue behind them)
+      int per_cu = 0, per_cu_sparse = 0;
+      B_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(batch_persistent_kernel<false>), kBatchThreads, 0));
+      B_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu_sparse, reinterpret_cast<const void *>(batch_persistent_kernel<true>), kBatchThreads, 0));
+      b->resident = std::max(1, std::min(per_cu, per_cu_sparse)) * std::max(1, ctxs[0]->cus);
+    }
     *out = b.release();
     return QME_OK;
   } catch (const std::exception &e) {
@@ -344,6 +556,25 @@ extern "C" qme_status qme_batch_config(qme_batch *b, int32_t use_graph, int32_t 
   return build_tables(b);
 }
 
+extern "C" qme_status qme_batch_persistent(qme_batch *b, int32_t enable) {
+  set_error("");
+  if (!b) { set_error("NULL batch"); return QME_E_ARG; }
+  if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return QME_E_ARG; }
+  if (enable == 1) {
+    // switched off: its launches did not finish on the device and the cause
+    // has not been established
+    set_error("the persistent batched launch is switched off (its launches did not finish on "
+              "the device; cause not established)");
+    return QME_E_UNSUPPORTED;
+  }
+  qme_status st = check_device(b->ctxs[0]);
+  if (st != QME_OK) return st;
+  B_OK(hipDeviceSynchronize());   // no launch may still use the old graphs
+  b->drop_graphs();
+  b->persistent = enable != 0;
+  return QME_OK;
+}
+
 extern "C" qme_status qme_batch_step(qme_batch *b, int64_t n_steps, void *ws, size_t ws_bytes,
                                      void *hip_stream) {
   try {
@@ -356,6 +587,22 @@ extern "C" qme_status qme_batch_step(qme_batch *b, int64_t n_steps, void *ws, si
     qme_status st = check_device(b->ctxs[0]);
     if (st != QME_OK) return st;
     if (n_steps == 0) return QME_OK;
+    if (b->persistent) {
+      // per-instance completion counts are 32-bit
+      int64_t per_inst_max = 0;
+      for (int i = 0; i < b->count; ++i) {
+        const qme_ctx *c = b->ctxs[i];
+        const int64_t t1 = c->ld / c->tile1, t2 = c->ld / c->tile2, td = (c->n + TD - 1) / TD;
+        per_inst_max = std::max<int64_t>(per_inst_max, t1 * t1 + t2 * (t2 + 1) / 2 + 1 + td * (td + 1) / 2);
+      }
+      int64_t per_step = 0;
+      for (int ph = 0; ph < 4; ++ph) per_step += b->phase_items[ph];
+      if (n_steps > (int64_t(INT32_MAX) - 1) / std::max<int64_t>(1, per_inst_max) ||
+          n_steps > (int64_t(INT32_MAX) - 1) / std::max<int64_t>(1, per_step)) {
+        set_error("persistent batch run too long for one launch; split it into shorter runs");
+        return QME_E_SIZE;
+      }
+    }
     st = bind_workspace(b, static_cast<char *>(ws));
     if (st != QME_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -181,7 +181,7 @@ __device__ __forceinline__ void fold_elem(const CgemmArgs<T> &p, int bi, int bj,
 template <typename T, int BM>
 __device__ __forceinline__ void fold_mirror(const CgemmArgs<T> &p, int bi, int bj,
                                             T (*s_re)[BM + 1], T (*s_im)[BM + 1]) {
-  for (int idx = threadIdx.x; idx < BM * BM; idx += kThreads) {
+  for (int idx = thread_index(); idx < BM * BM; idx += kThreads) {
     const int a = idx / BM, b = idx - (idx / BM) * BM;
     if (bi == bj && b <= a) continue;
     const int64_t o = (int64_t(bj) * BM + a) * p.ld + int64_t(bi) * BM + b;
@@ -235,7 +235,7 @@ __device__ __forceinline__ void f32_tile_epilogue(const CgemmArgs<float> &p, int
                                                   float *smem, const floatx16 (&cr)[F][F],
                                                   const floatx16 (&ci)[F][F], float *part) {
   const int64_t ld = p.ld;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 31, h = lane >> 5;
@@ -320,7 +320,7 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
   float (*sB)[2][BSZ] = reinterpret_cast<float (*)[2][BSZ]>(smem + 4 * BM * LDK);
 
   const int64_t ld = p.ld;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 31, h = lane >> 5;
@@ -475,7 +475,7 @@ __device__ __forceinline__ void cgemm_f32_tile_dma(const CgemmArgs<float> &p, in
   typedef __attribute__((address_space(3))) void lvoid;
 
   const int64_t ld = p.ld;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 31, h = lane >> 5;
@@ -605,7 +605,7 @@ __device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int 
   T (*sB)[2][BSZ] = reinterpret_cast<T (*)[2][BSZ]>(smem + 4 * BM * LDK);
 
   const int64_t ld = p.ld;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, h = lane >> 4;

@@ -504,6 +504,7 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
     if (st == QME_OK) st = up(&c->loff_col, t.loff_col);
     if (st == QME_OK) st = up(&c->loff_val, t.loff_val);
     if (st == QME_OK) st = up(&c->csr_gamma, gam);
+    if (st == QME_OK) st = up(&c->csr_channel, t.csr_channel);
     if (st != QME_OK) return st;
   }
   // adjoint tables
@@ -1079,6 +1080,13 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
   return QME_OK;
 }
 
+extern "C" qme_status qme_gradient_size(const qme_ctx *c, int64_t *n_params) {
+  set_error("");
+  if (!c || !n_params) { set_error("NULL argument"); return QME_E_ARG; }
+  *n_params = int64_t(c->term_offset.size()) - 1 + int64_t(c->model.jumps.size());
+  return QME_OK;
+}
+
 extern "C" qme_status qme_get_tiles(const qme_ctx *c, int32_t *tile1, int32_t *tile2) {
   set_error("");
   if (!c || !tile1 || !tile2) { set_error("NULL argument"); return QME_E_ARG; }
@@ -1162,7 +1170,8 @@ qme_ctx::~qme_ctx() {
   for (void *p : {(void *)csr_ptr, (void *)csrt_ptr, (void *)kj_ptr, (void *)koff_ptr,
                   (void *)csr_col, (void *)csrt_col, (void *)kj_col, (void *)koff_col,
                   (void *)csr_val, (void *)csrt_val, (void *)kj_val, (void *)koff_val,
-                  (void *)csr_gamma, (void *)loff_row, (void *)loff_col, (void *)loff_val})
+                  (void *)csr_gamma, (void *)csr_channel, (void *)loff_row, (void *)loff_col,
+                  (void *)loff_val})
     if (p) (void)hipFree(p);
   for (void *p : {du_re, du_im, du_split, (void *)parent_keep, (void *)d, (void *)leak, (void *)trw, (void *)diag, (void *)pi, (void *)cg,
                   (void *)tau, (void *)ca, (void *)upi, (void *)uc, (void *)ada, (void *)arrival_of,

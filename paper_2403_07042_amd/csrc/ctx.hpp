@@ -50,6 +50,7 @@ struct qme_ctx {
   int32_t *csr_col = nullptr, *csrt_col = nullptr, *kj_col = nullptr, *koff_col = nullptr;
   double *csr_val = nullptr, *csrt_val = nullptr, *kj_val = nullptr, *koff_val = nullptr;
   double *csr_gamma = nullptr;
+  int32_t *csr_channel = nullptr;     // original jump index per sparse channel
   int32_t *loff_row = nullptr, *loff_col = nullptr;
   double *loff_val = nullptr;
   // the decoherence and trace passes' arguments for these tables

@@ -8,6 +8,18 @@
 
 namespace qme {
 
+// The calling thread's index in its workgroup, for the tile bodies.  It is
+// passed through an empty asm so that in a persistent kernel, which runs
+// many bodies in one loop, the values derived from it (per-lane LDS and
+// global offsets) are formed inside each body rather than hoisted out of the
+// loop and kept live for every body at once (which needs more registers
+// than any one body).
+__device__ __forceinline__ int thread_index() {
+  int t = int(threadIdx.x);
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Per-kernel timing of the step path (qme_profile_enable).  While a timer is
 // armed on the calling thread, every kernel enqueued through launch_kernel
 // takes a fresh start / stop event pair from it and is launched with
@@ -239,7 +251,46 @@ struct AdjArgs {
   double *rowbuf;        // [tiles * n]
   double *colbuf;        // [tiles * n]
   double *gbuf;          // [blocks * n_arrival]
+  // sparse (non-monomial) channels: rows of A^T (csrt_ptr [n_csr][n + 1],
+  // row k: the images u of preimage k with their unit-rate coefficients),
+  // the rates, and K's off-diagonal part (nullptr: none), as in DissArgs:
+  //   mu += dt (sum gamma A^T lam A - 1/2 {K_off, lam})
+  int n_csr = 0;
+  const int64_t *csrt_ptr = nullptr;
+  const int32_t *csrt_col = nullptr;
+  const double *csrt_val = nullptr;
+  const double *csr_gamma = nullptr;
+  const int64_t *koff_ptr = nullptr;
+  const int32_t *koff_col = nullptr;
+  const double *koff_val = nullptr;
 };
+
+// Rate-gradient partials of the sparse channels for one adjoint step: per
+// channel q and lower-triangle tile of 64, the sum over the tile's elements
+// (weight 2 off the diagonal) of Re(conj(lam[u,v]) E_q[u,v]) with
+//   E_q = A_q Z A_q^T - 1/2 (K_q,off Z + Z K_q,off)      (unit rate)
+// into part[q * blocks + tile]; the diagonal of K_q enters through
+// launch_gamma_reduce like a monomial channel's.
+template <typename T>
+struct AdjSparseArgs {
+  const T *l_re, *l_im;     // lam (lower triangle valid)
+  const T *z_re, *z_im;     // Z = rho_u of the step (lower triangle valid)
+  int64_t ld, n;
+  int n_csr;
+  const int64_t *csr_ptr;   // [n_csr][n + 1]: rows of A (images u)
+  const int32_t *csr_col;
+  const double *csr_val;
+  const int64_t *kj_ptr;    // [n_csr][n + 1]: K_q off-diagonal, unit rate
+  const int32_t *kj_col;
+  const double *kj_val;
+  double *part;             // [n_csr * blocks]
+};
+template <typename T>
+hipError_t launch_adj_sparse_gamma(const AdjSparseArgs<T> &a, hipStream_t s);
+// grad[channel[q]] += dt * sum_b part[q * blocks + b]  (b in order)
+hipError_t launch_sparse_gamma_reduce(const double *part, int blocks, int n_csr,
+                                      const int32_t *channel, double dt, double *grad,
+                                      hipStream_t s);
 
 constexpr int kAdjTile = 64;
 constexpr int kMaxArrival = 16;

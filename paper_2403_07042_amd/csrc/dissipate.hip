@@ -28,12 +28,12 @@ __global__ __launch_bounds__(kTraceThreads) void trace_kernel(DissArgs<T> p) {
   trace_body<T, kTraceThreads>(p, s_tr, s_lost, s_rot);
 }
 
-template <typename T>
+template <typename T, bool SPARSE>
 __global__ __launch_bounds__(kDissThreads) void dissipate_kernel(DissArgs<T> p) {
   __shared__ T s_re[TD][TD + 1];
   __shared__ T s_im[TD][TD + 1];
   __shared__ GatherLds g;
-  dissipate_tile<T>(p, blockIdx.x, s_re, s_im, &g);
+  dissipate_tile<T, SPARSE>(p, blockIdx.x, s_re, s_im, &g);
 }
 
 template <typename T>
@@ -51,7 +51,9 @@ template <typename T>
 hipError_t launch_dissipate(const DissArgs<T> &a, hipStream_t s) {
   const int tiles = int((a.n + TD - 1) / TD);
   const int blocks = tiles * (tiles + 1) / 2;
-  return launch_kernel(dissipate_kernel<T>, dim3(blocks), dim3(kDissThreads), 0, s, a);
+  if (a.n_csr > 0 || a.koff_ptr)
+    return launch_kernel(dissipate_kernel<T, true>, dim3(blocks), dim3(kDissThreads), 0, s, a);
+  return launch_kernel(dissipate_kernel<T, false>, dim3(blocks), dim3(kDissThreads), 0, s, a);
 }
 
 template <typename T>

@@ -52,20 +52,21 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
                                            double *s_rot) {
   // tr rho_d = sum_u rho_d[u,u] = sum_w trw[w] Z[w,w]: the jump terms
   // c_j[u]^2 Z[pi_j u, pi_j u] regrouped by the state w = pi_j u they read
+  const int tid = thread_index();
   double tr = 0.0, lost = 0.0, rot = 0.0;
   // the lost probability's off-diagonal terms (restricted sparse channels):
   // lost += value Re Z[col,row], and the trace loses dt times the same
-  for (int64_t e = threadIdx.x; e < p.n_loff; e += NT) {
+  for (int64_t e = tid; e < p.n_loff; e += NT) {
     double zr, zi;
     zlower(p, p.loff_col[e], p.loff_row[e], zr, zi);
     const double x = p.loff_val[e] * zr;
     lost += x;
     tr -= p.dt * x;
   }
-  // u = threadIdx.x + k NT in increasing k; the loads of G values of k are
+  // u = tid + k NT in increasing k; the loads of G values of k are
   // issued together (one batch at N = 2048), the sums keep that order
   constexpr int G = 8;
-  for (int64_t u0 = threadIdx.x; u0 < p.n; u0 += int64_t(G) * NT) {
+  for (int64_t u0 = tid; u0 < p.n; u0 += int64_t(G) * NT) {
     double z[G], wk[G], lk[G];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
@@ -89,13 +90,13 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
     lost += __shfl_xor(lost, off);
     rot += __shfl_xor(rot, off);
   }
-  if ((threadIdx.x & 63) == 0) {
-    s_tr[threadIdx.x >> 6] = tr;
-    s_lost[threadIdx.x >> 6] = lost;
-    s_rot[threadIdx.x >> 6] = rot;
+  if ((tid & 63) == 0) {
+    s_tr[tid >> 6] = tr;
+    s_lost[tid >> 6] = lost;
+    s_rot[tid >> 6] = rot;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double t = s_tr[0], l = s_lost[0], r = s_rot[0];
     for (int w = 1; w < NT / 64; ++w) {
       t += s_tr[w];
@@ -123,7 +124,9 @@ struct GatherLds {
 // One TD x TD lower-triangle tile t of the decoherence pass (256 threads);
 // s_re / s_im: LDS staging of TD x (TD + 1) elements for the mirrored write;
 // g: LDS for the gather tables (used when 0 < n_gather <= kGatherChunk).
-template <typename T>
+// SPARSE: the variant with the sparse channels' terms (DissArgs::n_csr,
+// koff); models without them take the other, which needs fewer registers.
+template <typename T, bool SPARSE = false>
 __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*s_re)[TD + 1],
                                                T (*s_im)[TD + 1], GatherLds *g) {
   int bi = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
@@ -133,12 +136,13 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
   const bool diag_tile = bi == bj;
   const double scale = p.aux_out[4];
   const double dt = p.dt;
-  const int c = threadIdx.x & (TD - 1);
-  const int r0 = threadIdx.x / TD;
+  const int tid = thread_index();
+  const int c = tid & (TD - 1);
+  const int r0 = tid / TD;
   const int64_t v = int64_t(bj) * TD + c;
   const bool staged = p.n_gather > 0 && p.n_gather <= kGatherChunk;
   if (staged) {
-    for (int e = threadIdx.x; e < p.n_gather * TD; e += kDissThreads) {
+    for (int e = tid; e < p.n_gather * TD; e += kDissThreads) {
       const int j = e / TD, i = e - (e / TD) * TD;
       const int64_t u = int64_t(bi) * TD + i, w = int64_t(bj) * TD + i;
       const int64_t base = int64_t(j) * p.n;
@@ -212,7 +216,7 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
         }
       }
     }
-    if (p.n_csr > 0 || p.koff_ptr) {
+    if (SPARSE && (p.n_csr > 0 || p.koff_ptr)) {
       // sparse channels and K's off-diagonal part
 #pragma unroll
       for (int q = 0; q < G; ++q) {

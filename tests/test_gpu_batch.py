@@ -203,3 +203,87 @@ def test_full_sweep_256_instances():
     b.close()
     for s in sols:
         s.close()
+
+
+PERSISTENT_OFF = ("the persistent batched launch is switched off: its launches did not "
+                  "finish on the device (a first run and the run of the fix, which moved the "
+                  "per-poll acquire out of the wait loop), and the cause is not established")
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+@pytest.mark.parametrize("graph", [False, True])
+def test_persistent_batch_equals_phase_launches_bitwise(graph):
+    """qme_batch_persistent: one launch per run (work taken in order from a
+    counter, per-instance waits) equals the phase launches bitwise -- the same
+    tile arithmetic -- over two runs in a row, and each instance its solo run."""
+    wls = mixed_instances()
+    out = {}
+    for persistent in (False, True):
+        sols = make_solvers(wls)
+        b = P.Batch(sols)
+        b.config(use_graph=graph, largest_first=True)
+        b.persistent(persistent)
+        print(f"batch of {len(wls)}, persistent={persistent}, graph={graph}: 7 + 5 steps", flush=True)
+        b.step(7)
+        b.step(5)
+        torch.cuda.synchronize()
+        out[persistent] = [s.get_rho() for s in sols]
+        b.close()
+        for s in sols:
+            s.close()
+    for wl, (ra, sa), (rb, sb) in zip(wls, out[False], out[True]):
+        assert np.isfinite(sb)                        # no wait gave up
+        assert np.array_equal(ra, rb) and sa == sb, wl["name"]
+    ref, ref_sink = solo_rho(wls[0], 12)
+    assert np.array_equal(out[True][0][0], ref)
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_full_sweep():
+    """The 256-instance sweep in one persistent launch of 100 steps: 8
+    instances of every size bitwise against solo runs, one of every size
+    against the oracle."""
+    wls = W.batch_sweep()
+    sols = make_solvers(wls)
+    b = P.Batch(sols)
+    b.config(use_graph=True, largest_first=True)
+    b.persistent(True)
+    print("persistent sweep: 256 instances x 100 steps", flush=True)
+    b.step(100)
+    torch.cuda.synchronize()
+    picks = {}
+    for i, wl in enumerate(wls):
+        picks.setdefault(wl["expected_n"], []).append(i)
+    for n, idx in sorted(picks.items()):
+        for i in idx[:8]:
+            rho, sink = sols[i].get_rho()
+            ref, ref_sink = solo_rho(wls[i], 100)
+            assert np.array_equal(rho, ref), (n, i)
+        i = idx[0]
+        sysm = ev.System(wls[i])
+        ref, ref_sink = ev.evolve(sysm, W.initial_rho(wls[i], sysm.occ), 100)
+        rho, sink = sols[i].get_rho()
+        assert np.abs(rho - ref).max() < 1e-5 and abs(sink - ref_sink) < 1e-6
+    b.close()
+    for s in sols:
+        s.close()
+
+
+def test_persistent_batch_is_switched_off():
+    """Asking for the persistent launch is refused (QME_E_UNSUPPORTED); the
+    phase launches stay in use (no kernel of the persistent form runs)."""
+    wls = mixed_instances()[:2]
+    sols = make_solvers(wls)
+    b = P.Batch(sols)
+    with pytest.raises(L.QmeError) as e:
+        b.persistent(True)
+    assert e.value.status == L.QME_E_UNSUPPORTED
+    b.persistent(False)
+    b.step(3)
+    torch.cuda.synchronize()
+    for wl, s in zip(wls, sols):
+        ref, _ = solo_rho(wl, 3)
+        assert np.array_equal(s.get_rho()[0], ref)
+    b.close()
+    for s in sols:
+        s.close()

@@ -134,12 +134,6 @@ def test_selection_on_hydrogen_bond_64_matches_oracle():
 
 def test_general_model_errors():
     wl = hb.hb_model(1)
-    sol = P.Solver(wl, "fp32")
-    sol.set_rho(hb.initial_rho(wl))
-    with pytest.raises(L.QmeError) as e:
-        sol.adjoint(5, np.zeros(64))
-    assert "QME_E_UNSUPPORTED" in str(e.value)
-    sol.close()
     r, c, v = wl["h"]
     bad = dict(wl, h=(r, c, v + (r > c) * 1e-3))              # H no longer symmetric
     with pytest.raises(L.QmeError) as e:

@@ -30,10 +30,15 @@ def collective_pair(structured, channels):
     occ = P.basis(structured)
     assert np.array_equal(occ, s.occ)
     jumps = [(g, *moves(occ)) for g, moves in channels]
-    lib = CO.general_workload(structured, s.n, P.hamiltonian_coo(structured), jumps)
+    # each side's own Hamiltonian, its non-zero entries (the same pattern, so
+    # the general gradient parameters correspond)
+    r, c, v = P.hamiltonian_coo(structured)
+    nz = v != 0.0
+    lib = CO.general_workload(structured, s.n, (r[nz], c[nz], v[nz]), jumps)
     h = s.h
     r, c = np.nonzero(h)
     orc = CO.general_workload(structured, s.n, (r, c, h[r, c]), jumps)
+    assert set(zip(lib["h"][0].tolist(), lib["h"][1].tolist())) == set(zip(r.tolist(), c.tolist()))
     return lib, orc, W.initial_rho(structured, occ)
 
 
@@ -159,3 +164,84 @@ def test_batch_of_collective_contexts_equals_solo():
     b.close()
     for s in sols:
         s.close()
+
+
+# ------------------------------------------------ gradients of general models
+
+from oracle import gradients as GR  # noqa: E402
+from workloads import hydrogen_bond as hb  # noqa: E402
+
+GRAD_TOL = {"fp64": 1e-9, "fp32": 1e-4}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _small_collective():
+    structured, channels = CO.tch_collective(atoms=(1, 2), cap=1, g=0.2, mu=0.1,
+                                             gamma_collective=0.1, gamma_leak=0.05, dt=0.05)
+    return collective_pair(structured, channels)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_general_adjoint_collective_decay(precision):
+    """qme_adjoint on a general-form context with collective decay (N = 32,
+    sparse channels): every gradient entry (H's symmetric entries, then the
+    rates) against the oracle's tangent-linear gradient."""
+    lib, orc, rho0 = _small_collective()
+    obs = np.random.default_rng(20240311 + 45).uniform(0.0, 1.0, 32)
+    print("oracle: tangent gradient of the N = 32 collective model", flush=True)
+    f_ref, g_ref = GR.gradient(ev.GeneralSystem(orc), rho0, 30, obs)
+    sol = P.Solver(lib, precision)
+    sol.set_rho(rho0)
+    f, g = sol.adjoint(30, obs, checkpoint_every=7)
+    sol.close()
+    assert g.shape == g_ref.shape
+    assert abs(f - f_ref) < (1e-12 if precision == "fp64" else 1e-6)
+    assert _rel(g, g_ref) < GRAD_TOL[precision]
+    n_h = len(GR.general_pattern(orc))
+    assert _rel(g[n_h:], g_ref[n_h:]) < GRAD_TOL[precision]       # the rates alone
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_general_adjoint_hydrogen_bond(precision):
+    """The hydrogen-bond model (N = 64, monomial operators in gather form):
+    gradients with respect to H's entries and the leak rates against the
+    oracle's tangent-linear gradient; the autograd binding gives the same."""
+    wl = hb.hb_model(1, steps=60)
+    rho0 = hb.initial_rho(wl)
+    obs = np.zeros(64)
+    obs[np.arange(0, 64, 3)] = 1.0
+    print("oracle: tangent gradient of the hydrogen-bond model", flush=True)
+    f_ref, g_ref = GR.gradient(ev.GeneralSystem(wl), rho0, 60, obs)
+    sol = P.Solver(wl, precision)
+    sol.set_rho(rho0)
+    f, g = sol.adjoint(60, obs, checkpoint_every=16)
+    sol.close()
+    assert abs(f - f_ref) < (1e-12 if precision == "fp64" else 1e-6)
+    assert _rel(g, g_ref) < GRAD_TOL[precision]
+
+
+def test_general_adjoint_restricted_basis():
+    """Gradients on a qme_subspace context of a collective-decay model (the
+    adjoint takes K formed before the projection); parameters whose entries
+    touch removed states have zero gradient."""
+    lib, orc, rho0 = _small_collective()
+    occ = ev.System(CO.tch_collective(atoms=(1, 2), cap=1)[0]).occ
+    removed = (occ[:, 0] == 0) & (occ[:, 1] == 0)
+    keep = np.nonzero(~removed)[0].astype(np.int32)
+    rk = rho0[np.ix_(keep, keep)]
+    rk = rk / np.trace(rk).real
+    obs = np.linspace(0.0, 1.0, keep.size)
+    f_ref, g_ref = GR.gradient(ev.GeneralSystem(orc, keep=keep), rk, 25, obs)
+    sol = P.Solver(lib, "fp64")
+    sub = sol.subspace(keep)
+    sub.set_rho(rk)
+    f, g = sub.adjoint(25, obs, checkpoint_every=5)
+    sub.close()
+    sol.close()
+    assert abs(f - f_ref) < 1e-12
+    assert _rel(g, g_ref) < 1e-9
+    zero = [i for i, (r, c) in enumerate(GR.general_pattern(orc)) if removed[r] or removed[c]]
+    assert zero and np.all(g[zero] == 0.0)
