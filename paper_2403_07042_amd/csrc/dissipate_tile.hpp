@@ -126,9 +126,18 @@ struct GatherLds {
 // g: LDS for the gather tables (used when 0 < n_gather <= kGatherChunk).
 // SPARSE: the variant with the sparse channels' terms (DissArgs::n_csr,
 // koff); models without them take the other, which needs fewer registers.
+//
+// Each thread owns four consecutive columns of one row of the tile, so the
+// rotated state is read and the new state written with 16-byte accesses;
+// the tile is staged in LDS and its conjugate mirror (and, for a diagonal
+// tile, its strict upper part) written row by row from there.  Gathered
+// elements are loaded for two channels at a time before they are used, and
+// a channel that maps the element onto itself (dephasing) reuses its value.
+// Each element's arithmetic is that of the file comment, in channel order.
 template <typename T, bool SPARSE = false>
 __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*s_re)[TD + 1],
                                                T (*s_im)[TD + 1], GatherLds *g) {
+  typedef T vec4 __attribute__((ext_vector_type(4)));
   int bi = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
   while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
   while (bi * (bi + 1) / 2 > t) --bi;
@@ -137,160 +146,222 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*
   const double scale = p.aux_out[4];
   const double dt = p.dt;
   const int tid = thread_index();
-  const int c = tid & (TD - 1);
-  const int r0 = tid / TD;
-  const int64_t v = int64_t(bj) * TD + c;
+  const int r = tid >> 3;                 // row of the tile
+  const int c0 = (tid & 7) * 4;           // first of the thread's four columns
+  const int64_t ld = p.ld, n = p.n;
+  const int64_t u = int64_t(bi) * TD + r;
+  const int64_t v0 = int64_t(bj) * TD + c0;
   const bool staged = p.n_gather > 0 && p.n_gather <= kGatherChunk;
   if (staged) {
     for (int e = tid; e < p.n_gather * TD; e += kDissThreads) {
       const int j = e / TD, i = e - (e / TD) * TD;
-      const int64_t u = int64_t(bi) * TD + i, w = int64_t(bj) * TD + i;
-      const int64_t base = int64_t(j) * p.n;
-      g->pu[j][i] = u < p.n ? p.pi[base + u] : -1;
-      g->cu[j][i] = u < p.n ? p.cg[base + u] : 0.0;
-      g->pv[j][i] = w < p.n ? p.pi[base + w] : -1;
-      g->cv[j][i] = w < p.n ? p.cg[base + w] : 0.0;
+      const int64_t a = int64_t(bi) * TD + i, b = int64_t(bj) * TD + i;
+      const int64_t base = int64_t(j) * n;
+      g->pu[j][i] = a < n ? p.pi[base + a] : -1;
+      g->cu[j][i] = a < n ? p.cg[base + a] : 0.0;
+      g->pv[j][i] = b < n ? p.pi[base + b] : -1;
+      g->cv[j][i] = b < n ? p.cg[base + b] : 0.0;
     }
     __syncthreads();
   }
 
-  double dv = 0.0;
-  if (v < p.n) dv = p.d[v];
-  // G of this thread's rows at a time (rows r0 + kRows * i): all their loads
-  // (the element, its row's rate, then each channel's gathered elements) are
-  // issued before any of them is used, so a thread keeps G requests in
-  // flight; each element's arithmetic is unchanged.
-  constexpr int kRows = kDissThreads / TD;
-  constexpr int G = 4;
-  for (int rb = r0; rb < TD; rb += kRows * G) {
-    bool ok[G];
-    double xr[G], xi[G];
+  // the four elements, the decay factors
+  const bool row_ok = u < n;
+  bool ok[4];
+  T zr[4], zi[4];
+  double xr[4], xi[4];
+  if (row_ok && v0 + 3 < n) {
+    const vec4 a = *reinterpret_cast<const vec4 *>(p.z_re + u * ld + v0);
+    const vec4 b = *reinterpret_cast<const vec4 *>(p.z_im + u * ld + v0);
 #pragma unroll
-    for (int q = 0; q < G; ++q) {
-      const int rr = rb + q * kRows;
-      const int64_t u = int64_t(bi) * TD + rr;
-      ok[q] = rr < TD && u < p.n && v < p.n && !(diag_tile && v > u);
-      double zr = 0.0, zi = 0.0, du = 0.0;
-      if (ok[q]) {
-        const int64_t o = u * p.ld + v;
-        zr = double(p.z_re[o]);
-        zi = double(p.z_im[o]);
-        du = p.d[u];
-      }
-      const double f = 1.0 - 0.5 * dt * (du + dv);
-      xr[q] = f * zr;
-      xi[q] = f * zi;
+    for (int i = 0; i < 4; ++i) {
+      zr[i] = a[i];
+      zi[i] = b[i];
     }
-    for (int j = 0; j < p.n_gather; ++j) {
-      double gr[G], gi[G], w[G];
-      bool use[G];
+  } else {
 #pragma unroll
-      for (int q = 0; q < G; ++q) {
-        const int rr = rb + q * kRows;
-        const int64_t u = int64_t(bi) * TD + rr;
-        int32_t pu = -1, pv = -1;
-        double cu = 0.0, cv = 0.0;
-        if (ok[q]) {
-          if (staged) {
-            pu = g->pu[j][rr];
-            pv = g->pv[j][c];
-            cu = g->cu[j][rr];
-            cv = g->cv[j][c];
-          } else {
-            pu = p.pi[int64_t(j) * p.n + u];
-            pv = p.pi[int64_t(j) * p.n + v];
-            cu = p.cg[int64_t(j) * p.n + u];
-            cv = p.cg[int64_t(j) * p.n + v];
-          }
-        }
-        use[q] = pu >= 0 && pv >= 0;
-        w[q] = dt * cu * cv;
-        gr[q] = gi[q] = 0.0;
-        if (use[q]) zlower(p, pu, pv, gr[q], gi[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-        if (use[q]) {
-          xr[q] += w[q] * gr[q];
-          xi[q] += w[q] * gi[q];
-        }
-      }
+    for (int i = 0; i < 4; ++i) {
+      const bool in = row_ok && v0 + i < n;
+      zr[i] = in ? p.z_re[u * ld + v0 + i] : T(0);
+      zi[i] = in ? p.z_im[u * ld + v0 + i] : T(0);
     }
-    if (SPARSE && (p.n_csr > 0 || p.koff_ptr)) {
-      // sparse channels and K's off-diagonal part
+  }
+  const double du = row_ok ? p.d[u] : 0.0;
 #pragma unroll
-      for (int q = 0; q < G; ++q) {
-        if (!ok[q]) continue;
-        const int64_t u = int64_t(bi) * TD + rb + q * kRows;
-        double ar = 0.0, ai = 0.0;
-        for (int ch = 0; ch < p.n_csr; ++ch) {
-          const int64_t *ptr = p.csr_ptr + int64_t(ch) * (p.n + 1);
-          double cr = 0.0, ci = 0.0;
-          for (int64_t x = ptr[u]; x < ptr[u + 1]; ++x) {
-            const int32_t k = p.csr_col[x];
-            const double a = p.csr_val[x];
-            for (int64_t y = ptr[v]; y < ptr[v + 1]; ++y) {
-              double zr, zi;
-              zlower(p, k, p.csr_col[y], zr, zi);
-              const double w = a * p.csr_val[y];
-              cr += w * zr;
-              ci += w * zi;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t v = v0 + i;
+    ok[i] = row_ok && v < n && !(diag_tile && v > u);
+    const double dv = v < n ? p.d[v] : 0.0;
+    const double f = 1.0 - 0.5 * dt * ((ok[i] ? du : 0.0) + dv);
+    xr[i] = f * (ok[i] ? double(zr[i]) : 0.0);
+    xi[i] = f * (ok[i] ? double(zi[i]) : 0.0);
+  }
+
+  // monomial channels (gather form)
+  if (staged) {
+    constexpr int B = 2;
+    for (int j0 = 0; j0 < p.n_gather; j0 += B) {
+      T gr[B][4], gi[B][4];
+      bool use[B][4];
+#pragma unroll
+      for (int jb = 0; jb < B; ++jb) {
+        const bool ch = j0 + jb < p.n_gather;
+        const int32_t pu = ch && row_ok ? g->pu[j0 + jb][r] : -1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int32_t pv = ch && ok[i] ? g->pv[j0 + jb][c0 + i] : -1;
+          use[jb][i] = pu >= 0 && pv >= 0;
+          gr[jb][i] = gi[jb][i] = T(0);
+          if (use[jb][i]) {
+            if (pu == u && pv == v0 + i) {        // the element itself
+              gr[jb][i] = zr[i];
+              gi[jb][i] = zi[i];
+            } else {
+              // element (pu, pv) of the Hermitian Z from its lower triangle
+              const bool low = pu >= pv;
+              const int64_t o = low ? int64_t(pu) * ld + pv : int64_t(pv) * ld + pu;
+              gr[jb][i] = p.z_re[o];
+              const T im = p.z_im[o];
+              gi[jb][i] = low ? im : -im;
             }
           }
-          ar += p.csr_gamma[ch] * cr;
-          ai += p.csr_gamma[ch] * ci;
         }
-        if (p.koff_ptr) {
-          double kr = 0.0, ki = 0.0;
-          for (int64_t x = p.koff_ptr[u]; x < p.koff_ptr[u + 1]; ++x) {   // (K Z)[u,v]
-            double zr, zi;
-            zlower(p, p.koff_col[x], v, zr, zi);
-            kr += p.koff_val[x] * zr;
-            ki += p.koff_val[x] * zi;
+      }
+#pragma unroll
+      for (int jb = 0; jb < B; ++jb) {
+        if (j0 + jb >= p.n_gather) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (use[jb][i]) {
+            const double w = dt * g->cu[j0 + jb][r] * g->cv[j0 + jb][c0 + i];
+            xr[i] += w * double(gr[jb][i]);
+            xi[i] += w * double(gi[jb][i]);
           }
-          for (int64_t y = p.koff_ptr[v]; y < p.koff_ptr[v + 1]; ++y) {   // (Z K)[u,v]
-            double zr, zi;
-            zlower(p, u, p.koff_col[y], zr, zi);
-            kr += p.koff_val[y] * zr;
-            ki += p.koff_val[y] * zi;
-          }
-          ar -= 0.5 * kr;
-          ai -= 0.5 * ki;
         }
-        xr[q] += dt * ar;
-        xi[q] += dt * ai;
       }
     }
+  } else {
+    for (int j = 0; j < p.n_gather; ++j) {
+      const int32_t pu = row_ok ? p.pi[int64_t(j) * n + u] : -1;
+      const double cu = row_ok ? p.cg[int64_t(j) * n + u] : 0.0;
 #pragma unroll
-    for (int q = 0; q < G; ++q) {
-      if (!ok[q]) continue;
-      const int rr = rb + q * kRows;
-      const int64_t u = int64_t(bi) * TD + rr;
-      const int64_t o = u * p.ld + v;
-      double yr = xr[q] * scale, yi = xi[q] * scale;
-      if (u == v) yi = 0.0;
-      p.x_re[o] = T(yr);
-      p.x_im[o] = T(yi);
-      if (diag_tile) {
-        if (u != v) {
-          p.x_re[v * p.ld + u] = T(yr);
-          p.x_im[v * p.ld + u] = T(-yi);
-        }
-      } else {
-        s_re[rr][c] = T(yr);
-        s_im[rr][c] = T(yi);
+      for (int i = 0; i < 4; ++i) {
+        if (!ok[i]) continue;
+        const int64_t v = v0 + i;
+        const int32_t pv = p.pi[int64_t(j) * n + v];
+        if (pu < 0 || pv < 0) continue;
+        const double w = dt * cu * p.cg[int64_t(j) * n + v];
+        double gr, gi;
+        zlower(p, pu, pv, gr, gi);
+        xr[i] += w * gr;
+        xi[i] += w * gi;
       }
     }
   }
-  if (diag_tile) return;
+
+  if (SPARSE && (p.n_csr > 0 || p.koff_ptr)) {
+    // sparse channels and K's off-diagonal part
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!ok[i]) continue;
+      const int64_t v = v0 + i;
+      double ar = 0.0, ai = 0.0;
+      for (int ch = 0; ch < p.n_csr; ++ch) {
+        const int64_t *ptr = p.csr_ptr + int64_t(ch) * (n + 1);
+        double cr = 0.0, ci = 0.0;
+        for (int64_t x = ptr[u]; x < ptr[u + 1]; ++x) {
+          const int32_t k = p.csr_col[x];
+          const double a = p.csr_val[x];
+          for (int64_t y = ptr[v]; y < ptr[v + 1]; ++y) {
+            double gr, gi;
+            zlower(p, k, p.csr_col[y], gr, gi);
+            const double w = a * p.csr_val[y];
+            cr += w * gr;
+            ci += w * gi;
+          }
+        }
+        ar += p.csr_gamma[ch] * cr;
+        ai += p.csr_gamma[ch] * ci;
+      }
+      if (p.koff_ptr) {
+        double kr = 0.0, ki = 0.0;
+        for (int64_t x = p.koff_ptr[u]; x < p.koff_ptr[u + 1]; ++x) {   // (K Z)[u,v]
+          double gr, gi;
+          zlower(p, p.koff_col[x], v, gr, gi);
+          kr += p.koff_val[x] * gr;
+          ki += p.koff_val[x] * gi;
+        }
+        for (int64_t y = p.koff_ptr[v]; y < p.koff_ptr[v + 1]; ++y) {   // (Z K)[u,v]
+          double gr, gi;
+          zlower(p, u, p.koff_col[y], gr, gi);
+          kr += p.koff_val[y] * gr;
+          ki += p.koff_val[y] * gi;
+        }
+        ar -= 0.5 * kr;
+        ai -= 0.5 * ki;
+      }
+      xr[i] += dt * ar;
+      xi[i] += dt * ai;
+    }
+  }
+
+  // the scaled lower elements: to the state and to LDS for the mirror
+  T yr[4], yi[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    yr[i] = T(xr[i] * scale);
+    yi[i] = u == v0 + i ? T(0) : T(xi[i] * scale);
+    s_re[r][c0 + i] = yr[i];
+    s_im[r][c0 + i] = yi[i];
+  }
+  if (ok[0] && ok[1] && ok[2] && ok[3]) {
+    vec4 a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = yr[i];
+      b[i] = yi[i];
+    }
+    *reinterpret_cast<vec4 *>(p.x_re + u * ld + v0) = a;
+    *reinterpret_cast<vec4 *>(p.x_im + u * ld + v0) = b;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!ok[i]) continue;
+      p.x_re[u * ld + v0 + i] = yr[i];
+      p.x_im[u * ld + v0 + i] = yi[i];
+    }
+  }
   __syncthreads();
-  // mirror tile (bj, bi): element (a, b) = conj(X[bi*TD + b][bj*TD + a])
-  const int64_t ucol = int64_t(bi) * TD + c;
-  for (int a = r0; a < TD; a += kDissThreads / TD) {
-    const int64_t vrow = int64_t(bj) * TD + a;
-    if (vrow >= p.n || ucol >= p.n) continue;
-    p.x_re[vrow * p.ld + ucol] = s_re[c][a];
-    p.x_im[vrow * p.ld + ucol] = -s_im[c][a];
+  // mirror: element (a, b) of tile (bj, bi) is conj(X[bi*TD + b][bj*TD + a]);
+  // for a diagonal tile only its strict upper part (b > a)
+  const int64_t mrow = int64_t(bj) * TD + r;       // row a = r of the mirror tile
+  const int64_t mcol = int64_t(bi) * TD + c0;      // columns b = c0 .. c0 + 3
+  if (mrow >= n) return;
+  bool mok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) mok[i] = mcol + i < n && (!diag_tile || c0 + i > r);
+  T mr[4], mi[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    mr[i] = s_re[c0 + i][r];
+    mi[i] = -s_im[c0 + i][r];
+  }
+  if (mok[0] && mok[1] && mok[2] && mok[3]) {
+    vec4 a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = mr[i];
+      b[i] = mi[i];
+    }
+    *reinterpret_cast<vec4 *>(p.x_re + mrow * ld + mcol) = a;
+    *reinterpret_cast<vec4 *>(p.x_im + mrow * ld + mcol) = b;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!mok[i]) continue;
+      p.x_re[mrow * ld + mcol + i] = mr[i];
+      p.x_im[mrow * ld + mcol + i] = mi[i];
+    }
   }
 }
 
