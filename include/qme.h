@@ -167,8 +167,10 @@ qme_status qme_hamiltonian(const qme_system *sys, const qme_params *par,
  * elements FP64 for QME_FP64 and FP32 otherwise, followed by 64 bytes of
  * FP64 scalars [sink, trace of the
  * last rotated state, lost-probability rate of the last step, steps taken,
- * last renormalisation factor, 0, 0, 0].  The caller allocates state_bytes
- * of device memory (256-byte aligned) and owns it. */
+ * last renormalisation factor, two library scratch scalars, 0]; the scratch
+ * pair carries the sink and step count between the steps of one call and
+ * holds no meaning afterwards.  The caller allocates state_bytes of device
+ * memory (256-byte aligned) and owns it. */
 qme_status qme_state_layout(const qme_ctx *ctx, int64_t *n, int64_t *ld,
                             int64_t *elem_bytes, size_t *state_bytes);
 

@@ -52,6 +52,9 @@ struct BatchPhase {
   const int32_t *order;        // queue position -> instance
   const int64_t *off;          // [count + 1] item prefix of this phase per queue position
   int32_t count;
+  // phases 2 and 3: scalar slot pairs of the step (DissArgs::slot_in /
+  // slot_out) and, for phase 3, whether each block forms the trace itself
+  int32_t slot_in = 0, slot_out = 0, fuse = 0;
 };
 
 static constexpr int kBatchThreads = 256;
@@ -71,7 +74,8 @@ template <int PHASE>
 constexpr int phase_smem() {
   return PHASE <= 1 ? kGemmSmem
          : PHASE == 2 ? 3 * kBatchThreads * 2
-                      : 2 * TD * (TD + 1) + int(sizeof(GatherLds) / sizeof(float)) + 2;
+                      : 2 * TD * (TD + 1) + int(sizeof(GatherLds) / sizeof(float)) + 2 +
+                            3 * 2 * (kBatchThreads / 64);
 }
 constexpr int kPersistSmem =
     std::max(std::max(phase_smem<0>(), phase_smem<1>()), std::max(phase_smem<2>(), phase_smem<3>()));
@@ -79,7 +83,8 @@ constexpr int kPersistSmem =
 // One item of a phase: tile `tile` of the instance at queue position `pos`.
 // PHASE 3 with SPARSE: the decoherence body with the sparse channels' terms.
 template <int PHASE, bool SPARSE>
-__device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, float *smem) {
+__device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, float *smem,
+                                           int slot_in = 0, int slot_out = 0, bool fuse = false) {
   if constexpr (PHASE == 0) {
     const CgemmArgs<float> g{in.u_re, in.u_im, in.x_re, in.x_im, in.x_re, in.x_im,
                              in.y_re, in.y_im, in.ld, 1.0f, 1.0f};
@@ -111,6 +116,8 @@ __device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, fl
     da.loff_row = in.sparse.loff_row;
     da.loff_col = in.sparse.loff_col;
     da.loff_val = in.sparse.loff_val;
+    da.slot_in = slot_in;
+    da.slot_out = slot_out;
     if constexpr (PHASE == 2) {
       double *sd = reinterpret_cast<double *>(smem);
       trace_body<float, kBatchThreads>(da, sd, sd + kBatchThreads, sd + 2 * kBatchThreads);
@@ -120,7 +127,14 @@ __device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, fl
       // 8-byte aligned start for the tables after the two staging arrays
       float *gp = smem + 2 * TD * (TD + 1);
       gp += (reinterpret_cast<uintptr_t>(gp) & 7) ? 1 : 0;
-      dissipate_tile<float, SPARSE>(da, tile, sr, si, reinterpret_cast<GatherLds *>(gp));
+      double *st = reinterpret_cast<double *>(gp + sizeof(GatherLds) / sizeof(float));
+      // the fused form: this block forms the instance's trace itself (the
+      // first tile's block stores the step's scalars)
+      const double scale = fuse ? trace_body<float, kBatchThreads>(da, st, st + kBatchThreads / 64,
+                                                                   st + 2 * (kBatchThreads / 64),
+                                                                   tile == 0)
+                                : in.aux[4];
+      dissipate_tile<float, SPARSE>(da, tile, scale, sr, si, reinterpret_cast<GatherLds *>(gp));
     }
   }
 }
@@ -140,7 +154,18 @@ __global__ __launch_bounds__(kBatchThreads) void batch_phase_kernel(BatchPhase p
   __shared__ float smem[phase_smem<PHASE>()];
   const int64_t r = blockIdx.x;
   const int lo = find_position(p.off, p.count, r);
-  batch_item<PHASE, SPARSE>(p.inst[p.order[lo]], int(r - p.off[lo]), smem);
+  batch_item<PHASE, SPARSE>(p.inst[p.order[lo]], int(r - p.off[lo]), smem, p.slot_in, p.slot_out,
+                            p.fuse != 0);
+}
+
+// After a run of fused steps that ended in slot pair 1, every instance's
+// sink and step count move back to pair 0.
+__global__ void batch_scalars_home_kernel(const BatchInstance *inst, int count) {
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double *aux = inst[i].aux;
+  aux[sink_slot(0)] = aux[sink_slot(1)];
+  aux[steps_slot(0)] = aux[steps_slot(1)];
 }
 
 // ------------------------------------------------------------ persistent form
@@ -290,6 +315,7 @@ struct qme_batch {
   bool lpt = true;
   bool sparse = false;              // some instance has sparse decoherence channels
   bool persistent = false;          // qme_batch_persistent
+  bool fuse = false;                // every instance small: the trace formed in the decoherence phase
   int resident = 0;                 // workgroups of the persistent kernel that fit the device
   size_t ctr_off = 0;               // workspace offset of the persistent run's counters
   // device tables (owned)
@@ -339,6 +365,8 @@ static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 static qme_status build_tables(qme_batch *b) {
   const int nb = b->count;
   b->sparse = false;
+  b->fuse = true;
+  for (qme_ctx *c : b->ctxs) b->fuse = b->fuse && fuse_trace_applies(c);
   std::vector<int32_t> ord(nb);
   std::iota(ord.begin(), ord.end(), 0);
   if (b->lpt)
@@ -462,8 +490,15 @@ static hipError_t enqueue_persistent(qme_batch *b, int64_t n_steps, hipStream_t 
 static hipError_t enqueue(qme_batch *b, int64_t n_steps, hipStream_t s) {
   if (b->persistent) return enqueue_persistent(b, n_steps, s);
   for (int64_t k = 0; k < n_steps; ++k) {
+    const int parity = b->fuse ? int(k & 1) : 0;
     for (int ph = 0; ph < 4; ++ph) {
-      const BatchPhase p{b->inst, b->order, b->phase_off + ph * (b->count + 1), b->count};
+      if (ph == 2 && b->fuse) continue;   // formed by the decoherence phase's blocks
+      BatchPhase p{b->inst, b->order, b->phase_off + ph * (b->count + 1), b->count};
+      if (b->fuse) {
+        p.slot_in = parity;
+        p.slot_out = 1 - parity;
+        p.fuse = 1;
+      }
       const dim3 grid(unsigned(b->phase_items[ph])), block(kBatchThreads);
       switch (ph) {
         case 0: hipLaunchKernelGGL(batch_phase_kernel<0>, grid, block, 0, s, p); break;
@@ -479,6 +514,11 @@ static hipError_t enqueue(qme_batch *b, int64_t n_steps, hipStream_t s) {
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
+  }
+  if (b->fuse && (n_steps & 1)) {
+    hipLaunchKernelGGL(batch_scalars_home_kernel, dim3((b->count + 255) / 256), dim3(256), 0, s,
+                       b->inst, b->count);
+    return hipGetLastError();
   }
   return hipSuccess;
 }

@@ -201,7 +201,7 @@ static void plan_product(const qme_ctx *c, CgemmArgs<T> &g, int tile, bool lower
 
 template <typename T>
 hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s,
-                     void *split_area) {
+                     void *split_area, int parity) {
   const size_t pe = plane_elems(c);
   const T *x_re = static_cast<const T *>(in), *x_im = x_re + pe;
   const double *aux_in = reinterpret_cast<const double *>(x_im + pe);
@@ -216,6 +216,11 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   DissArgs<T> da{z_re, z_im, o_re, o_im, c->ld, c->n, c->model.dt, c->d, c->leak,
                  c->pi, c->cg, c->jt.n_gather, aux_in, aux_out, c->trw};
   c->sparse_args(da);
+  if (parity >= 0) {
+    da.fuse_trace = 1;
+    da.slot_in = parity;
+    da.slot_out = 1 - parity;
+  }
   GemmOps o1, o2;
   o1.conj_b = o2.conj_b = true;
   o2.lower = true;
@@ -248,7 +253,7 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
     if (e == hipSuccess) e = launch_cgemm_f64(g2, c->tile2, o2, s);
   }
   if (e == hipSuccess) e = mark(c, s, 1);
-  if (e == hipSuccess) e = launch_trace<T>(da, s);
+  if (e == hipSuccess && !da.fuse_trace) e = launch_trace<T>(da, s);
   if (e == hipSuccess) e = mark(c, s, 2);
   if (e == hipSuccess) e = launch_dissipate<T>(da, s);
   if (e == hipSuccess) e = mark(c, s, 3);
@@ -256,9 +261,17 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
 }
 
 template hipError_t step_once<float>(qme_ctx *, const void *, void *, void *, void *, hipStream_t,
-                                     void *);
+                                     void *, int);
 template hipError_t step_once<double>(qme_ctx *, const void *, void *, void *, void *, hipStream_t,
-                                      void *);
+                                      void *, int);
+
+// Systems up to this size form the trace in the decoherence pass (each of
+// its blocks reads the N diagonal values of the rotated state once more).
+static constexpr int64_t kFuseTraceMaxN = 1024;
+
+bool fuse_trace_applies(const qme_ctx *c) {
+  return c->n <= kFuseTraceMaxN && !uses_small_path(c) && !uses_fold(c);
+}
 
 // The single-workgroup path applies to FP32 / FP64 contexts with n <= kSmallN
 // whose decoherence operators are all monomial.
@@ -377,8 +390,21 @@ static qme_status step_impl(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   }
   T *y = static_cast<T *>(ws);
   T *z = y + 2 * pe;
+  // small systems: the trace formed in the decoherence pass, the sink and
+  // step count alternating between two slot pairs (back to pair 0 at the end)
+  const bool fuse = fuse_trace_applies(c);
   for (int64_t k = 0; k < n_steps; ++k) {
-    hipError_t e = step_once<T>(c, state, state, y, z, s, split_area_of<T>(c, ws));
+    hipError_t e = step_once<T>(c, state, state, y, z, s, split_area_of<T>(c, ws),
+                                fuse ? int(k & 1) : -1);
+    if (e != hipSuccess) {
+      set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return QME_E_DEVICE;
+    }
+  }
+  if (fuse && (n_steps & 1)) {
+    launch_timer() = nullptr;   // not a step's kernel
+    const hipError_t e = launch_scalars_home(
+        reinterpret_cast<double *>(static_cast<char *>(state) + 2 * pe * sizeof(T)), s);
     if (e != hipSuccess) {
       set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
       return QME_E_DEVICE;

@@ -139,9 +139,14 @@ qme_status check_device(const qme_ctx *c);
 // workspace plane pairs y (product T) and z (rotated state, lower tiles).
 template <typename T>
 // split_area: the step workspace's partial slots for small-launch splits
-// (nullptr: no such splits, as in the adjoint's recomputation)
+// (nullptr: no such splits, as in the adjoint's recomputation).  parity >= 0:
+// the trace is formed in the decoherence pass (fuse_trace_applies), reading
+// the scalars from slot pair `parity` and writing them to the other one.
 hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hipStream_t s,
-                     void *split_area = nullptr);
+                     void *split_area = nullptr, int parity = -1);
 bool uses_small_path(const qme_ctx *c);
 bool uses_fold(const qme_ctx *c);
+// Whether the unfolded step forms the trace inside the decoherence pass
+// (every block reads the N diagonal values itself: small systems).
+bool fuse_trace_applies(const qme_ctx *c);
 }  // namespace qme

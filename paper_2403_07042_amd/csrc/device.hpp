@@ -171,10 +171,24 @@ struct DissArgs {
   const int32_t *loff_row = nullptr;
   const int32_t *loff_col = nullptr;
   const double *loff_val = nullptr;
+  // Scalar slots of the trace pass.  The sink and the step count are read
+  // from slot pair slot_in and written to slot pair slot_out (pair 0:
+  // scalars 0 and 3, as in qme_state_layout; pair 1: scalars 5 and 6).
+  // When every block of the decoherence pass forms the trace itself (small
+  // systems, launch_dissipate with fuse_trace) the state is updated in place
+  // by many blocks at once, so the two pairs differ and alternate by step.
+  int slot_in = 0, slot_out = 0;
+  int fuse_trace = 0;
 };
+// the scalar indices of the sink and the step count in slot pair `slot`
+__host__ __device__ constexpr int sink_slot(int slot) { return slot ? 5 : 0; }
+__host__ __device__ constexpr int steps_slot(int slot) { return slot ? 6 : 3; }
 
 template <typename T>
 hipError_t launch_trace(const DissArgs<T> &a, hipStream_t s);
+// After a run of fused steps that ended in slot pair 1: the sink and step
+// count moved back to pair 0 (one thread).
+hipError_t launch_scalars_home(double *aux, hipStream_t s);
 template <typename T>
 hipError_t launch_dissipate(const DissArgs<T> &a, hipStream_t s);
 template <typename T>

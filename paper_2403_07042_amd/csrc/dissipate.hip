@@ -28,12 +28,31 @@ __global__ __launch_bounds__(kTraceThreads) void trace_kernel(DissArgs<T> p) {
   trace_body<T, kTraceThreads>(p, s_tr, s_lost, s_rot);
 }
 
-template <typename T, bool SPARSE>
+// FUSE: every block forms the trace sums itself (the same reduction as
+// trace_kernel, so the factor is bitwise the same) and block 0 stores the
+// step's scalars; otherwise the factor comes from the trace pass.
+template <typename T, bool SPARSE, bool FUSE>
 __global__ __launch_bounds__(kDissThreads) void dissipate_kernel(DissArgs<T> p) {
   __shared__ T s_re[TD][TD + 1];
   __shared__ T s_im[TD][TD + 1];
   __shared__ GatherLds g;
-  dissipate_tile<T, SPARSE>(p, blockIdx.x, s_re, s_im, &g);
+  double scale;
+  if constexpr (FUSE) {
+    __shared__ double s_t[3][kDissThreads / 64];
+    scale = trace_body<T, kDissThreads>(p, s_t[0], s_t[1], s_t[2], blockIdx.x == 0);
+  } else {
+    scale = p.aux_out[4];
+  }
+  dissipate_tile<T, SPARSE>(p, blockIdx.x, scale, s_re, s_im, &g);
+}
+
+__global__ void scalars_home_kernel(double *aux) {
+  aux[sink_slot(0)] = aux[sink_slot(1)];
+  aux[steps_slot(0)] = aux[steps_slot(1)];
+}
+
+hipError_t launch_scalars_home(double *aux, hipStream_t s) {
+  return launch_kernel(scalars_home_kernel, dim3(1), dim3(1), 0, s, aux);
 }
 
 template <typename T>
@@ -51,9 +70,12 @@ template <typename T>
 hipError_t launch_dissipate(const DissArgs<T> &a, hipStream_t s) {
   const int tiles = int((a.n + TD - 1) / TD);
   const int blocks = tiles * (tiles + 1) / 2;
-  if (a.n_csr > 0 || a.koff_ptr)
-    return launch_kernel(dissipate_kernel<T, true>, dim3(blocks), dim3(kDissThreads), 0, s, a);
-  return launch_kernel(dissipate_kernel<T, false>, dim3(blocks), dim3(kDissThreads), 0, s, a);
+  const bool sparse = a.n_csr > 0 || a.koff_ptr;
+  if (a.fuse_trace)
+    return sparse ? launch_kernel(dissipate_kernel<T, true, true>, dim3(blocks), dim3(kDissThreads), 0, s, a)
+                  : launch_kernel(dissipate_kernel<T, false, true>, dim3(blocks), dim3(kDissThreads), 0, s, a);
+  return sparse ? launch_kernel(dissipate_kernel<T, true, false>, dim3(blocks), dim3(kDissThreads), 0, s, a)
+                : launch_kernel(dissipate_kernel<T, false, false>, dim3(blocks), dim3(kDissThreads), 0, s, a);
 }
 
 template <typename T>

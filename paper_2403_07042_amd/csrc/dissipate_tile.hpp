@@ -47,9 +47,10 @@ __device__ __forceinline__ void zlower(const DissArgs<T> &p, int64_t a, int64_t 
 
 // One workgroup of NT threads: FP64 trace of rho_d, lost probability,
 // sink and renormalisation factor of one step (see the file comment).
+// Returns the factor to every thread; `write`: store the step's scalars.
 template <typename T, int NT>
-__device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, double *s_lost,
-                                           double *s_rot) {
+__device__ __forceinline__ double trace_body(const DissArgs<T> &p, double *s_tr, double *s_lost,
+                                             double *s_rot, bool write = true) {
   // tr rho_d = sum_u rho_d[u,u] = sum_w trw[w] Z[w,w]: the jump terms
   // c_j[u]^2 Z[pi_j u, pi_j u] regrouped by the state w = pi_j u they read
   const int tid = thread_index();
@@ -103,14 +104,20 @@ __device__ __forceinline__ void trace_body(const DissArgs<T> &p, double *s_tr, d
       l += s_lost[w];
       r += s_rot[w];
     }
-    const double sink = p.aux_in[0] + p.dt * l;
-    const double steps = p.aux_in[3] + 1.0;
-    p.aux_out[0] = sink;
-    p.aux_out[1] = r;
-    p.aux_out[2] = l;
-    p.aux_out[3] = steps;
-    p.aux_out[4] = (1.0 - sink) / t;
+    const double sink = p.aux_in[sink_slot(p.slot_in)] + p.dt * l;
+    const double steps = p.aux_in[steps_slot(p.slot_in)] + 1.0;
+    const double scale = (1.0 - sink) / t;
+    if (write) {
+      p.aux_out[sink_slot(p.slot_out)] = sink;
+      p.aux_out[1] = r;
+      p.aux_out[2] = l;
+      p.aux_out[steps_slot(p.slot_out)] = steps;
+      p.aux_out[4] = scale;
+    }
+    s_tr[0] = scale;
   }
+  __syncthreads();
+  return s_tr[0];
 }
 
 // Gather tables of up to kGatherChunk channels for one tile's rows (u) and
@@ -134,16 +141,17 @@ struct GatherLds {
 // elements are loaded for two channels at a time before they are used, and
 // a channel that maps the element onto itself (dephasing) reuses its value.
 // Each element's arithmetic is that of the file comment, in channel order.
+// scale: the step's renormalisation factor.
 template <typename T, bool SPARSE = false>
-__device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, T (*s_re)[TD + 1],
-                                               T (*s_im)[TD + 1], GatherLds *g) {
+__device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, double scale,
+                                               T (*s_re)[TD + 1], T (*s_im)[TD + 1],
+                                               GatherLds *g) {
   typedef T vec4 __attribute__((ext_vector_type(4)));
   int bi = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
   while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
   while (bi * (bi + 1) / 2 > t) --bi;
   const int bj = t - bi * (bi + 1) / 2;
   const bool diag_tile = bi == bj;
-  const double scale = p.aux_out[4];
   const double dt = p.dt;
   const int tid = thread_index();
   const int r = tid >> 3;                 // row of the tile

@@ -151,7 +151,8 @@ def test_single_workgroup_path_matches_tiled(make, precision, steps, tol):
 def test_single_workgroup_dispatch_rule():
     """N <= 32 in FP32 / FP64 takes the single launch (only index 0 of the
     per-kind launch counts moves); N = 33, BF16X3, and the knob off take the
-    four-launch step."""
+    unfolded step, whose trace a system this small forms inside the
+    decoherence pass (three launches, none of kind 2)."""
     def launches(wl, precision, fused=True):
         sol = P.Solver(wl, precision)
         sol.set_fused(fused)
@@ -164,9 +165,49 @@ def test_single_workgroup_dispatch_rule():
         return counts
     assert launches(n32_system(), "fp64") == [1, 0, 0, 0]
     assert launches(n32_system(), "fp32") == [1, 0, 0, 0]
-    assert launches(n32_system(), "fp32", fused=False) == [3, 3, 3, 3]
-    assert launches(n32_system(), "bf16x3") == [3, 3, 3, 3]
-    assert launches(n33_system(), "fp64") == [3, 3, 3, 3]
+    assert launches(n32_system(), "fp32", fused=False) == [3, 3, 0, 3]
+    assert launches(n32_system(), "bf16x3") == [3, 3, 0, 3]
+    assert launches(n33_system(), "fp64") == [3, 3, 0, 3]
+
+
+def _scalars(sol):
+    """The state's eight FP64 scalars (after the two planes)."""
+    off = 2 * sol.ld * sol.ld * sol.elem
+    return sol.state[off:off + 64].cpu().numpy().view(np.float64).copy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("make", [W.tch_2x2, lambda: W.photon_lattice(12, 12)])
+def test_fused_trace_scalars_across_calls(make, precision, graph):
+    """A small unfolded system forms its trace in the decoherence pass and
+    keeps the sink and step count in two alternating scalar pairs; whatever
+    the split of steps over calls (odd and even counts) the state, the sink
+    and the step count equal those of one call, bit for bit.  The sink
+    starts at 1/8 (the lattice's boundary adds to it)."""
+    wl = make()
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    out = []
+    for split in ([7], [1, 2, 4], [3, 3, 1], [2, 5]):
+        sol = P.Solver(wl, precision)
+        sol.set_fold(False)
+        sol.set_graph(graph)
+        sol.set_rho(rho0, sink=0.125)
+        sol.profile(not graph)          # profiling runs eagerly
+        for k in split:
+            sol.step(k)                 # graph: [3, 3, 1] replays the 3-step capture
+        torch.cuda.synchronize()
+        counts = [c for _, c in sol.profile_read().values()]
+        rho, sink = sol.get_rho()
+        aux = _scalars(sol)
+        sol.close()
+        if not graph:
+            assert counts == [7, 7, 0, 7]
+        assert aux[3] == 7.0 and aux[0] == sink and sink >= 0.125
+        out.append((rho, aux[:5]))
+    for rho, aux in out[1:]:
+        assert np.array_equal(rho, out[0][0])
+        assert np.array_equal(aux, out[0][1])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
