@@ -519,7 +519,7 @@ qme_status qme_set_fold(qme_ctx *ctx, int32_t enable);
  * products of qme_step and the first two of the adjoint step): mode 1 loads
  * the operand tiles from HBM straight into LDS (no register staging), 0
  * stages them through registers, -1 (default) takes the direct body for
- * launches with fewer than four blocks per compute unit, where the few
+ * launches with fewer than two blocks per compute unit, where the few
  * resident workgroups cannot hide the load latency by their number.  The two
  * bodies accumulate every output in the same order: results are bitwise
  * identical.  Other values: QME_E_ARG. */

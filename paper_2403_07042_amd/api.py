@@ -325,7 +325,7 @@ class Solver:
 
     def set_direct_loads(self, mode: int):
         """FP32 product tile body: 1 direct HBM-to-LDS loads, 0 register
-        staging, -1 (default) direct for launches with fewer than four
+        staging, -1 (default) direct for launches with fewer than two
         blocks per compute unit.  Bitwise-neutral."""
         L.check(self.lib.qme_set_direct_loads(self.ctx, int(mode)))
 

@@ -23,7 +23,7 @@
 //   * FP32 has two tile bodies with the same arithmetic: loads staged
 //     through registers into padded LDS rows, or loaded straight into
 //     swizzled LDS rows (global_load_lds); launches with fewer blocks than
-//     four per CU take the second (GemmOps::direct);
+//     two per CU take the second (GemmOps::direct);
 //   * FP64 rows are swizzled, unpadded, and each K tile's fragments are
 //     read in two halves, which fits five waves per SIMD at 32-tiles;
 //   * a complex multiply-add is three real MFMA products (Gauss's 3M form:
@@ -284,7 +284,7 @@ static bool use_direct(const CgemmArgs<float> &a, int tile, const GemmOps &o) {
   const int64_t tiles = a.ld / tile;
   int64_t blocks = o.lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
   if (a.split > 1) blocks = a.full + (blocks - a.full) * a.split;
-  return o.cus > 0 && blocks < 4 * int64_t(o.cus);
+  return o.cus > 0 && blocks < 2 * int64_t(o.cus);
 }
 
 // Whether a tile's LDS holds the folded epilogue's staging (the condition

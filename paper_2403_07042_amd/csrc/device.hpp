@@ -55,7 +55,7 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem,
 // conjugate A / B.  lower: only the tiles on or below the diagonal.
 // direct (FP32 forms with M given by rows only): 1 uses the tile body that
 // loads operands straight into LDS, 0 the register-staged one, -1 picks the
-// direct body when the launch has fewer blocks than 4 per compute unit
+// direct body when the launch has fewer blocks than 2 per compute unit
 // (`cus`), i.e. when resident workgroups cannot hide load latency by their
 // number.  Both bodies give bitwise-identical results.
 struct GemmOps {
