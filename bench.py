@@ -44,8 +44,8 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": 372062.4 * 1024,
-                        "sha256": "817676d308099c533e33faca406d5515efcc8898cf832e1519eed89350b1e901",
+TRAFFIC_FP32_PRODUCT = {"bytes": 377445.8 * 1024,
+                        "sha256": "789e2d7aad7e0a53a8dd96ca8f1400b5d8d9393994ec7e9cc77ac48b413bd191",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
 KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 
@@ -75,6 +75,10 @@ def parse():
                     help="steps of the batched sweep of 256 uneven instances (0: skip)")
     ap.add_argument("--latency", type=int, default=1,
                     help="time the latency-bound N = 8 and N = 144 workloads (0: skip)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="time FP32 / BF16x3 / FP64 on the N = 144 and N = 1728 configurations (0: skip)")
+    ap.add_argument("--config-steps", type=int, default=0,
+                    help="steps per precision there (0: 2000 at N = 144, 200 at N = 1728)")
     ap.add_argument("--selection", type=int, default=1,
                     help="time the state-space selection loop on the N = 2048 lattice (0: skip)")
     ap.add_argument("--plane-steps", type=int, default=100,
@@ -333,14 +337,14 @@ def selection_leg(P, W, torch, steps=1000, eps=1e-20):
             "compact_2048_to_1024_us": us, "compact_gbs": moved / (us * 1e-6) / 1e9}
 
 
-def configs_leg(P, W, torch, warmup=10):
+def configs_leg(P, W, torch, warmup=10, steps_override=0):
     """FP32, split-BF16x3 and plain FP64 steps/s, with the speedups over FP64,
     on the other parity configurations: the 2 x 2 Tavis-Cummings-Hubbard
     model (N = 144, 2000 steps) and the three-cavity chain (N = 1728, 200
-    steps)."""
+    steps); steps_override > 0 runs that many steps on both."""
     out = {}
-    for name, wl, steps in (("tch_2x2_n144", W.tch_2x2(), 2000),
-                            ("tch_chain3_n1728", W.tch_chain3(), 200)):
+    for name, wl, steps in (("tch_2x2_n144", W.tch_2x2(), steps_override or 2000),
+                            ("tch_chain3_n1728", W.tch_chain3(), steps_override or 200)):
         rates = {}
         for prec in ("fp32", "bf16x3", "fp64"):
             leg = timed_leg(P, W, torch, wl, prec, steps, warmup)
@@ -528,7 +532,7 @@ def main():
 
     batch = batch_leg(P, W, torch, args.batch_steps) if args.batch_steps > 0 else None
     latency = latency_leg(P, W, torch) if args.latency else None
-    configs = configs_leg(P, W, torch) if args.latency else None
+    configs = configs_leg(P, W, torch, steps_override=args.config_steps) if args.configs else None
     selection = selection_leg(P, W, torch) if args.selection else None
     plane = plane_leg(P, W, torch, args.plane_steps) if args.plane_steps > 0 else None
     pure = pure_leg(P, W, torch, args.pure_steps) if args.pure_steps > 0 else None
