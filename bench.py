@@ -295,8 +295,10 @@ def selection_leg(P, W, torch, steps=1000, eps=1e-20):
     """State-space selection (Sec. III.B) on the N = 2048 lattice, FP32,
     compared after every step: the first solve (step, populations, selection,
     subset context with its propagator, compaction), then the remaining steps
-    on the selected basis with a comparison after each; plus the compaction
-    kernel alone on a half-size gather of the full state (HIP events)."""
+    on the selected basis with a comparison after each, decided on the host
+    and, again, on the device with the next solve queued ahead; plus the
+    compaction kernel alone on a half-size gather of the full state (HIP
+    events)."""
     wl = W.photon_lattice(steps=steps)
     occ = P.basis(wl)
     rho0 = W.initial_rho(wl, occ)
@@ -311,6 +313,19 @@ def selection_leg(P, W, torch, steps=1000, eps=1e-20):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     final_n = sizes2[-1] if sizes2 else sizes[-1]
+    if out2 is not out:
+        out2.close()
+    if out is not sol:
+        out.close()
+    # the same loop with the decisions on the device, one solve queued ahead
+    sol.set_rho(rho0)
+    out, _, _ = P.evolve_with_selection(sol, 1, eps, 1, device=True)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out2, _, sizes3 = P.evolve_with_selection(out, steps - 1, eps, 1, device=True)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    same = sizes3 == sizes2
     if out2 is not out:
         out2.close()
     if out is not sol:
@@ -334,6 +349,8 @@ def selection_leg(P, W, torch, steps=1000, eps=1e-20):
             "steps": steps, "compare_every": 1, "basis_after_first_solve": sizes[0],
             "final_basis": int(final_n),
             "first_solve_s": t1 - t0, "remaining_steps_per_s": (steps - 1) / (t2 - t1),
+            "remaining_steps_per_s_device_decision": (steps - 1) / (t4 - t3),
+            "device_decision_same_sizes": same,
             "compact_2048_to_1024_us": us, "compact_gbs": moved / (us * 1e-6) / 1e9}
 
 

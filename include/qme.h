@@ -331,6 +331,50 @@ qme_status qme_hamiltonian_general(int64_t n, int64_t h_nnz, const int32_t *h_ro
 qme_status qme_select_states(int64_t n, const double *p_prev, const double *p_now,
                              double interval, double eps, int32_t *keep, int64_t *n_keep);
 
+/* The same keep/delete decision (Sec. III.B, growth speed against epsilon)
+ * taken on the device, so a selection loop need not wait for the host after
+ * every solve.  Reads the populations p_now[s] = Re rho[s][s] of state_dev
+ * (a state of ctx), keeps s when |p_now[s] - p_prev[s]| / interval >= eps
+ * (FP64, the operations of qme_select_states, so both keep the same
+ * states), and writes the kept indices in increasing order to keep_dev and
+ * their count to *n_keep_dev (-1 when a population is not finite; 0 when
+ * every state would be removed).  p_prev_dev, p_now_dev: [n] FP64 device
+ * vectors (p_now_dev may be p_prev_dev: updated in place); keep_dev: [n]
+ * int32 device; n_keep_dev: one int64 on the device.  All caller-owned.
+ * Errors: QME_E_ARG for NULL pointers, interval <= 0, eps < 0 or non-finite
+ * arguments.  Asynchronous on hip_stream. */
+qme_status qme_select_device(const qme_ctx *ctx, const void *state_dev, const double *p_prev_dev,
+                             double *p_now_dev, double interval, double eps, int32_t *keep_dev,
+                             int64_t *n_keep_dev, void *hip_stream);
+
+/* Device area qme_select_run needs (caller-allocated, 256-byte aligned): a
+ * state snapshot, two population vectors, two kept-index vectors and two
+ * counts. */
+qme_status qme_select_workspace_size(const qme_ctx *ctx, size_t *bytes);
+
+/* The selection loop's solves without a host round trip between them
+ * (Sec. III.B, Fig. 2): up to n_solves solves of steps_per_solve steps on
+ * state_dev (workspace_dev as for qme_step), each followed by the decision
+ * of qme_select_device with interval = steps_per_solve * dt.  Solve i + 1 is
+ * queued from a snapshot of solve i's result before the host reads solve
+ * i's count; when that count is below n (states to remove) the queued solve
+ * is dropped and the state restored, so the run stops with the state of the
+ * solve that decided.  fresh = 1 takes the populations the first solve
+ * compares against from state_dev; fresh = 0 takes those the previous run
+ * on this select area left (the populations of its last solve).  On return:
+ * *solves_done = solves whose results stand; *n_keep = n when no decision
+ * removed states, else the deciding solve's count with keep_host[0..n_keep)
+ * ([n] int32 host, caller-owned) its kept states in increasing order.
+ * Returns after the last decision is read (the stream is synchronised when
+ * states are removed).  Errors: QME_E_ARG as for qme_step and for
+ * n_solves < 0, steps_per_solve < 1, eps < 0 or not finite; QME_E_NUMERIC
+ * when a population is not finite, QME_E_STATE when every state would be
+ * removed (both with *solves_done and *n_keep set). */
+qme_status qme_select_run(qme_ctx *ctx, void *state_dev, void *workspace_dev, void *select_ws_dev,
+                          int64_t n_solves, int64_t steps_per_solve, double eps, int32_t fresh,
+                          int64_t *solves_done, int64_t *n_keep, int32_t *keep_host,
+                          void *hip_stream);
+
 /* A context on the subset keep[0..n_keep) of ctx's basis (strictly
  * increasing indices, order kept), with ctx's parameters and precision: the
  * Hamiltonian restricted to the subset (P H P), decoherence operators whose

@@ -92,6 +92,12 @@ SIGNATURES = {
                                           c_int32, c_void_p, POINTER(c_void_p)]),
     "qme_select_states": (c_int32, [c_int64, POINTER(c_double), POINTER(c_double), c_double,
                                     c_double, POINTER(c_int32), POINTER(c_int64)]),
+    "qme_select_device": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                    c_void_p, c_void_p, c_void_p]),
+    "qme_select_workspace_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "qme_select_run": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_double,
+                                 c_int32, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
+                                 c_void_p]),
     "qme_subspace": (c_int32, [c_void_p, POINTER(c_int32), c_int64, c_void_p, POINTER(c_void_p)]),
     "qme_compact_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qme_profile_enable": (c_int32, [c_void_p, c_int32]),

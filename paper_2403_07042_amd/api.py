@@ -294,6 +294,25 @@ class Solver:
         L.check(self.lib.qme_compact_state(self.ctx, c_void_p(st.data_ptr()), sub.ctx,
                                            c_void_p(sub.state.data_ptr()), self._sptr()))
 
+    def select_device(self, p_prev, p_now, interval: float, eps: float, keep, n_keep, state=None):
+        """qme_select_device: the keep/delete decision on the device.  p_prev,
+        p_now: float64 device tensors of at least n entries (may be one
+        tensor); keep: int32 device tensor of at least n entries; n_keep:
+        int64 device tensor (its first entry receives the count, -1 for a
+        non-finite population).  Asynchronous on the solver's stream."""
+        torch = self.torch
+        for t, dt_, size in ((p_prev, torch.float64, self.n), (p_now, torch.float64, self.n),
+                             (keep, torch.int32, self.n), (n_keep, torch.int64, 1)):
+            if (not isinstance(t, torch.Tensor) or t.dtype != dt_ or not t.is_cuda
+                    or not t.is_contiguous() or t.numel() < size):
+                raise ValueError("select_device needs contiguous device tensors of the documented "
+                                 "dtypes and sizes")
+        st = self.state if state is None else state
+        L.check(self.lib.qme_select_device(self.ctx, c_void_p(st.data_ptr()),
+                                           c_void_p(p_prev.data_ptr()), c_void_p(p_now.data_ptr()),
+                                           float(interval), float(eps), c_void_p(keep.data_ptr()),
+                                           c_void_p(n_keep.data_ptr()), self._sptr()))
+
     def set_tiles(self, tile1: int, tile2: int):
         L.check(self.lib.qme_set_tiles(self.ctx, int(tile1), int(tile2)))
 
@@ -415,7 +434,8 @@ def select_states(p_prev, p_now, interval: float, eps: float) -> np.ndarray:
     return keep[:n_keep.value].copy()
 
 
-def evolve_with_selection(sol: Solver, n_steps: int, eps: float, every: int = 1):
+def evolve_with_selection(sol: Solver, n_steps: int, eps: float, every: int = 1,
+                          device: bool = False):
     """The selection loop of Sec. III.B on a solver whose state is set: solve
     `every` steps, compare each state's growth speed over them with eps, move
     the state onto the kept states (renormalised), repeat until n_steps.  The
@@ -423,7 +443,16 @@ def evolve_with_selection(sol: Solver, n_steps: int, eps: float, every: int = 1)
     kept, sizes): the solver on the final basis (the input solver if nothing
     was removed; solvers made on the way are closed except the last, which
     the caller owns), the indices of its states in the input basis, and the
-    basis size after each solve."""
+    basis size after each solve.
+
+    device=True takes each decision on the device (qme_select_device) and
+    runs one solve ahead of it: the next solve is queued from a snapshot of
+    the state before the host reads the decision, and is dropped (the state
+    restored from the snapshot) when the decision removes states.  The same
+    decisions, subsets and states as the host loop, without a host round
+    trip between solves."""
+    if device:
+        return _evolve_with_selection_device(sol, n_steps, eps, every)
     kept = np.arange(sol.n, dtype=np.int64)
     sizes = []
     owned = False
@@ -445,4 +474,47 @@ def evolve_with_selection(sol: Solver, n_steps: int, eps: float, every: int = 1)
             kept = kept[keep]
         p_prev = p_now
         sizes.append(sol.n)
+    return sol, kept, sizes
+
+
+def _evolve_with_selection_device(sol: Solver, n_steps: int, eps: float, every: int):
+    torch = sol.torch
+    kept = np.arange(sol.n, dtype=np.int64)
+    sizes = []
+    owned = False
+    if n_steps <= 0:
+        return sol, kept, sizes
+    lib = sol.lib
+    done_steps = 0
+    fresh = 1
+    area = None
+    while done_steps < n_steps:
+        if area is None:
+            nbytes = c_size_t()
+            L.check(lib.qme_select_workspace_size(sol.ctx, byref(nbytes)))
+            area = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=sol.state.device)
+            keep = np.zeros(sol.n, dtype=np.int32)
+        k = min(every, n_steps - done_steps)
+        solves = (n_steps - done_steps) // k
+        done, n_keep = c_int64(0), c_int64(0)
+        L.check(lib.qme_select_run(sol.ctx, c_void_p(sol.state.data_ptr()),
+                                   c_void_p(sol.workspace.data_ptr()), c_void_p(area.data_ptr()),
+                                   int(solves), int(k), float(eps), int(fresh), byref(done),
+                                   byref(n_keep), keep.ctypes.data_as(POINTER(c_int32)),
+                                   sol._sptr()))
+        done_steps += done.value * k
+        fresh = 0
+        if n_keep.value == sol.n:
+            sizes += [sol.n] * done.value
+            continue
+        sizes += [sol.n] * (done.value - 1)
+        idx = keep[:n_keep.value].copy()
+        sub = sol.subspace(idx)
+        sol.compact_into(sub)
+        if owned:
+            sol.close()
+        sol, owned = sub, True
+        kept = kept[idx]
+        sizes.append(sol.n)
+        fresh, area = 1, None
     return sol, kept, sizes

@@ -678,6 +678,168 @@ extern "C" qme_status qme_select_states(int64_t n, const double *p_prev, const d
   QME_GUARD_END
 }
 
+extern "C" qme_status qme_select_device(const qme_ctx *c, const void *state, const double *p_prev,
+                                        double *p_now, double interval, double eps, int32_t *keep,
+                                        int64_t *n_keep, void *hip_stream) {
+  QME_GUARD_BEGIN
+  TraceRange range("qme_select_device");
+  set_error("");
+  if (!c || !state || !p_prev || !p_now || !keep || !n_keep) {
+    set_error("NULL argument");
+    return QME_E_ARG;
+  }
+  if (!(interval > 0.0) || !std::isfinite(interval)) { set_error("interval must be > 0"); return QME_E_ARG; }
+  if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps must be finite and >= 0"); return QME_E_ARG; }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if (c->elem == 8) {
+    DecideArgs<double> a{static_cast<const double *>(state), c->ld, c->n, p_prev, p_now,
+                         interval, eps, keep, n_keep};
+    e = launch_select_decide<double>(a, s);
+  } else {
+    DecideArgs<float> a{static_cast<const float *>(state), c->ld, c->n, p_prev, p_now,
+                        interval, eps, keep, n_keep};
+    e = launch_select_decide<float>(a, s);
+  }
+  if (e != hipSuccess) { set_error(std::string("kernel launch failed: ") + hipGetErrorString(e)); return QME_E_DEVICE; }
+  return QME_OK;
+  QME_GUARD_END
+}
+
+// The selection run's device area: a snapshot of the state, two population
+// vectors, two kept-index vectors, two counts (slots alternate by solve).
+struct SelectArea {
+  void *snap;
+  double *p[2];
+  int32_t *keep[2];
+  int64_t *count;
+};
+static SelectArea select_area(const qme_ctx *c, void *base) {
+  char *b = static_cast<char *>(base);
+  SelectArea a;
+  a.snap = b;
+  b += align256(state_bytes(c));
+  a.p[0] = reinterpret_cast<double *>(b);
+  a.p[1] = a.p[0] + c->n;
+  b += align256(2 * sizeof(double) * size_t(c->n));
+  a.keep[0] = reinterpret_cast<int32_t *>(b);
+  a.keep[1] = a.keep[0] + c->n;
+  b += align256(2 * sizeof(int32_t) * size_t(c->n));
+  a.count = reinterpret_cast<int64_t *>(b);
+  return a;
+}
+
+extern "C" qme_status qme_select_workspace_size(const qme_ctx *c, size_t *bytes) {
+  set_error("");
+  if (!c || !bytes) { set_error("NULL argument"); return QME_E_ARG; }
+  *bytes = align256(state_bytes(c)) + align256(2 * sizeof(double) * size_t(c->n)) +
+           align256(2 * sizeof(int32_t) * size_t(c->n)) + 2 * sizeof(int64_t);
+  return QME_OK;
+}
+
+template <typename T>
+static hipError_t decide_on(const qme_ctx *c, const void *state, const double *prev, double *now,
+                            double interval, double eps, int32_t *keep, int64_t *count,
+                            hipStream_t s) {
+  DecideArgs<T> a{static_cast<const T *>(state), c->ld, c->n, prev, now, interval, eps, keep, count};
+  return launch_select_decide<T>(a, s);
+}
+
+extern "C" qme_status qme_select_run(qme_ctx *c, void *state, void *ws, void *sel_ws,
+                                     int64_t n_solves, int64_t steps_per_solve, double eps,
+                                     int32_t fresh, int64_t *solves_done, int64_t *n_keep,
+                                     int32_t *keep_host, void *hip_stream) {
+  QME_GUARD_BEGIN
+  TraceRange range("qme_select_run");
+  set_error("");
+  if (!c || !state || !ws || !sel_ws || !solves_done || !n_keep || !keep_host) {
+    set_error("NULL argument");
+    return QME_E_ARG;
+  }
+  if (n_solves < 0 || steps_per_solve < 1) {
+    set_error("n_solves must be >= 0 and steps_per_solve >= 1");
+    return QME_E_ARG;
+  }
+  if (!(eps >= 0.0) || !std::isfinite(eps)) { set_error("eps must be finite and >= 0"); return QME_E_ARG; }
+  if ((reinterpret_cast<uintptr_t>(state) | reinterpret_cast<uintptr_t>(ws) |
+       reinterpret_cast<uintptr_t>(sel_ws)) & 255) {
+    set_error("state and workspaces must be 256-byte aligned");
+    return QME_E_ARG;
+  }
+  qme_status st = check_device(c);
+  if (st != QME_OK) return st;
+  *solves_done = 0;
+  *n_keep = c->n;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (!c->sel_count_host)
+    HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&c->sel_count_host), 2 * sizeof(int64_t)));
+  for (void *&e : c->sel_ev)
+    if (!e) HIP_OK(hipEventCreateWithFlags(reinterpret_cast<hipEvent_t *>(&e), hipEventDisableTiming));
+  const SelectArea a = select_area(c, sel_ws);
+  const bool f64 = c->elem == 8;
+  auto decide = [&](const double *prev, double *now, double interval, double e, int slot) {
+    return f64 ? decide_on<double>(c, state, prev, now, interval, e, a.keep[slot], a.count + slot, s)
+               : decide_on<float>(c, state, prev, now, interval, e, a.keep[slot], a.count + slot, s);
+  };
+  if (fresh) HIP_OK(decide(a.p[0], a.p[0], 1.0, 0.0, 0));   // populations of the entry state
+  if (n_solves == 0) return QME_OK;
+  const double interval = double(steps_per_solve) * c->model.dt;
+  const size_t sbytes = state_bytes(c);
+  auto issue = [&](int slot) -> qme_status {
+    const qme_status r = f64 ? step_impl<double>(c, state, steps_per_solve, ws, s)
+                             : step_impl<float>(c, state, steps_per_solve, ws, s);
+    if (r != QME_OK) return r;
+    HIP_OK(decide(a.p[slot], a.p[1 - slot], interval, eps, slot));
+    HIP_OK(hipMemcpyAsync(c->sel_count_host + slot, a.count + slot, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipEventRecord(static_cast<hipEvent_t>(c->sel_ev[slot]), s));
+    return QME_OK;
+  };
+  // solve i compares p[i % 2] with the populations it writes to p[(i + 1) % 2];
+  // solve i + 1 is queued (from a snapshot of the state) before the host reads
+  // solve i's count
+  int slot = 0;
+  st = issue(slot);
+  if (st != QME_OK) return st;
+  int64_t done = 1;
+  for (;;) {
+    const int cur = slot;
+    const bool ahead = done < n_solves;
+    if (ahead) {
+      HIP_OK(hipMemcpyAsync(a.snap, state, sbytes, hipMemcpyDeviceToDevice, s));
+      slot ^= 1;
+      st = issue(slot);
+      if (st != QME_OK) return st;
+    }
+    HIP_OK(hipEventSynchronize(static_cast<hipEvent_t>(c->sel_ev[cur])));
+    const int64_t cnt = c->sel_count_host[cur];
+    if (cnt != c->n) {
+      // the solve queued ahead is dropped: the state returns to solve `done`'s
+      if (ahead) HIP_OK(hipMemcpyAsync(state, a.snap, sbytes, hipMemcpyDeviceToDevice, s));
+      if (cnt > 0)
+        HIP_OK(hipMemcpyAsync(keep_host, a.keep[cur], sizeof(int32_t) * size_t(cnt),
+                              hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      *solves_done = done;
+      *n_keep = cnt;
+      if (cnt < 0) { set_error("populations are not finite"); return QME_E_NUMERIC; }
+      if (cnt == 0) { set_error("every state would be removed"); return QME_E_STATE; }
+      return QME_OK;
+    }
+    if (!ahead) break;
+    ++done;
+  }
+  // the last solve (slot `slot`) wrote its populations to p[1 - slot]: back
+  // to p[0] for a following run
+  if (slot == 0)
+    HIP_OK(hipMemcpyAsync(a.p[0], a.p[1], sizeof(double) * size_t(c->n), hipMemcpyDeviceToDevice, s));
+  *solves_done = done;
+  return QME_OK;
+  QME_GUARD_END
+}
+
 extern "C" qme_status qme_subspace(const qme_ctx *parent, const int32_t *keep, int64_t n_keep,
                                    void *hip_stream, qme_ctx **out) {
   QME_GUARD_BEGIN
@@ -1191,6 +1353,9 @@ qme_ctx::~qme_ctx() {
   if (launch_timer() == &timer) launch_timer() = nullptr;
   drop_graphs();
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  for (void *e : sel_ev)
+    if (e) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+  if (sel_count_host) (void)hipHostFree(sel_count_host);
   for (void *e : ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *e : ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   for (void *p : {(void *)csr_ptr, (void *)csrt_ptr, (void *)kj_ptr, (void *)koff_ptr,

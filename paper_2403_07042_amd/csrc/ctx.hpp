@@ -105,6 +105,10 @@ struct qme_ctx {
   int profile_every = 1;               // record every profile_every-th step
   int64_t profile_step = 0;            // steps begun since enabling
   std::vector<void *> ev_start, ev_stop;   // hipEvent_t pools
+  // qme_select_run: the decisions' counts in pinned host memory, one event
+  // per slot (made on first use)
+  int64_t *sel_count_host = nullptr;
+  void *sel_ev[2] = {nullptr, nullptr};
   size_t pairs_used = 0, pairs_marked = 0;
   struct ProfileRecord {
     int kind;

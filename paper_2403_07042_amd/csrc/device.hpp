@@ -229,6 +229,23 @@ struct CompactArgs {
 template <typename T>
 hipError_t launch_compact(const CompactArgs<T> &a, hipStream_t s);
 
+// The keep/delete decision of state-space selection on the device: the
+// populations p_now[s] = Re rho[s][s] of a state, the states whose growth
+// speed |p_now - p_prev| / interval is at least eps in increasing order, and
+// their count (-1 when a population is not finite).  p_now may alias p_prev.
+template <typename T>
+struct DecideArgs {
+  const T *re;
+  int64_t ld, n;
+  const double *p_prev;
+  double *p_now;
+  double interval, eps;
+  int32_t *keep;
+  int64_t *n_keep;
+};
+template <typename T>
+hipError_t launch_select_decide(const DecideArgs<T> &a, hipStream_t s);
+
 // One pure-state step of a closed model for nv vectors (planar, [nv][ld]):
 // y_v = (x_v + dU x_v) / |x_v| (see pure.hip).  x and y must not overlap.
 template <typename T>

@@ -7,6 +7,9 @@
 //                        the whole state; writes the new state's scalars
 //   compact_kernel       rho_to[i][j] = scale * rho_from[keep_i][keep_j],
 //                        zero in the padding (rows / columns >= n_to)
+//   select_decide_kernel (one workgroup): the keep/delete decision from two
+//                        population vectors, the kept indices compacted in
+//                        increasing order
 #include "device.hpp"
 
 namespace qme {
@@ -75,5 +78,61 @@ hipError_t launch_compact(const CompactArgs<T> &a, hipStream_t s) {
 
 template hipError_t launch_compact<float>(const CompactArgs<float> &, hipStream_t);
 template hipError_t launch_compact<double>(const CompactArgs<double> &, hipStream_t);
+
+// Growth speed |p_now - p_prev| / interval against eps in FP64, the same
+// operations as the host decision (qme_select_states), so both keep the same
+// states.  The states are taken in chunks of the workgroup's size; a chunk's
+// kept states are numbered by the wave ballots and the waves' counts, after
+// every state of the earlier chunks.
+static constexpr int kDecideThreads = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kDecideThreads) void select_decide_kernel(DecideArgs<T> a) {
+  constexpr int kWaves = kDecideThreads / 64;
+  __shared__ int s_count[kWaves];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  bool bad = false;
+  int64_t base = 0;                       // states kept in earlier chunks
+  for (int64_t s0 = 0; s0 < a.n; s0 += kDecideThreads) {
+    const int64_t s = s0 + tid;
+    bool keep = false;
+    if (s < a.n) {
+      const double pn = double(a.re[s * a.ld + s]);
+      const double pp = a.p_prev[s];
+      bad = bad || !isfinite(pn) || !isfinite(pp);
+      keep = fabs(pn - pp) / a.interval >= a.eps;
+      a.p_now[s] = pn;
+    }
+    const uint64_t m = __ballot(keep);
+    const int below = __popcll(m & ((uint64_t(1) << lane) - 1));
+    if (lane == 0) s_count[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const int c = s_count[w];
+      before += w < wave ? c : 0;
+      total += c;
+    }
+    if (keep) a.keep[base + before + below] = int32_t(s);
+    base += total;
+    __syncthreads();                      // the counts are rewritten by the next chunk
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (tid == 0) *a.n_keep = s_bad ? -1 : base;
+}
+
+template <typename T>
+hipError_t launch_select_decide(const DecideArgs<T> &a, hipStream_t s) {
+  if (a.n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(select_decide_kernel<T>, dim3(1), dim3(kDecideThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_select_decide<float>(const DecideArgs<float> &, hipStream_t);
+template hipError_t launch_select_decide<double>(const DecideArgs<double> &, hipStream_t);
 
 }  // namespace qme

@@ -145,3 +145,157 @@ def test_compact_state_argument_errors():
     assert abs(np.trace(rho).real - 1.0) < 1e-6
     for s in (a, b, sub, sub64):
         s.close()
+
+
+def diagonal_model(n):
+    """A general-form model of n states with a diagonal Hamiltonian and no
+    decoherence: a state's populations are exactly what set_rho put there."""
+    idx = np.arange(n, dtype=np.int32)
+    return {"general": True, "name": f"diag_{n}", "n": n,
+            "h": (idx, idx, np.linspace(0.0, 1.0, n)), "jumps": [], "dt": 0.01, "steps": 1}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [1, 5, 1023, 1024, 1025, 2500])
+def test_device_decision_matches_host_decision(n, precision):
+    """qme_select_device against qme_select_states on the same populations:
+    the same kept indices in the same order and the same count, across the
+    kernel's 1024-state chunks; speeds exactly at eps are kept on both sides;
+    the populations written are the state's diagonal."""
+    rng = np.random.default_rng(100 + n)
+    sol = P.Solver(diagonal_model(n), precision)
+    p_now = rng.random(n) / n
+    p_prev = p_now + rng.choice([0.0, 1e-9, -1e-9, 3e-7], size=n)
+    p_prev[::7] = p_now[::7]                             # zero speed: removed unless eps = 0
+    sol.set_rho(np.diag(p_now).astype(np.complex128))
+    stored = np.real(np.diag(sol.get_rho()[0])).copy()  # the stored (possibly FP32) diagonal
+    interval, eps = 0.5, 2e-9                            # 1e-9 / 0.5 = eps exactly: kept
+    dev = sol.state.device
+    prev = torch.tensor(p_prev, dtype=torch.float64, device=dev)
+    now = torch.zeros(n, dtype=torch.float64, device=dev)
+    keep = torch.full((n,), -7, dtype=torch.int32, device=dev)
+    nk = torch.zeros(1, dtype=torch.int64, device=dev)
+    print(f"device decision n={n} {precision}", flush=True)
+    sol.select_device(prev, now, interval, eps, keep, nk)
+    torch.cuda.synchronize()
+    ref = P.select_states(p_prev, stored, interval, eps) if np.any(
+        np.abs(stored - p_prev) / interval >= eps) else np.zeros(0, np.int32)
+    assert int(nk.item()) == ref.size
+    assert np.array_equal(keep[:ref.size].cpu().numpy(), ref)
+    assert np.array_equal(now.cpu().numpy(), stored)
+    # in place (p_now aliases p_prev), eps = 0 keeps every state
+    sol.select_device(prev, prev, interval, 0.0, keep, nk)
+    torch.cuda.synchronize()
+    assert int(nk.item()) == n and np.array_equal(keep.cpu().numpy(), np.arange(n))
+    assert np.array_equal(prev.cpu().numpy(), stored)
+    # a non-finite population: count -1
+    bad = torch.tensor(p_prev, dtype=torch.float64, device=dev)
+    bad[n // 2] = float("nan")
+    sol.select_device(bad, now, interval, eps, keep, nk)
+    torch.cuda.synchronize()
+    assert int(nk.item()) == -1
+    with pytest.raises(L.QmeError):
+        sol.select_device(prev, now, 0.0, eps, keep, nk)      # interval must be > 0
+    with pytest.raises(ValueError):
+        sol.select_device(prev[: n - 1] if n > 1 else prev.float(), now, interval, eps, keep, nk)
+    sol.close()
+
+
+DEVICE_LOOP_CASES = [("fp64", "damped_jc"), ("fp64", "lattice_9x9"), ("fp64", "tch_2x2_lossy_cut"),
+                     ("fp32", "lattice_9x9"), ("fp32", "damped_jc")]
+
+
+@pytest.mark.parametrize("precision,case", DEVICE_LOOP_CASES)
+def test_device_selection_loop_matches_host_loop(case, precision):
+    """The loop that decides on the device and queues the next solve ahead
+    gives the host loop's sizes, kept states, final state and sink bit for
+    bit, and leaves the input solver's state where the host loop leaves it."""
+    make, steps, eps, every = CASES[case]
+    wl = make()
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    res = {}
+    for device in (False, True):
+        sol = P.Solver(wl, precision)
+        sol.set_rho(rho0)
+        print(f"selection loop {case} {precision} device={device}", flush=True)
+        out, kept, sizes = P.evolve_with_selection(sol, steps, eps, every, device=device)
+        rho, sink = out.get_rho()
+        res[device] = (rho, sink, kept, sizes, sol.get_rho()[0])
+        if out is not sol:
+            out.close()
+        sol.close()
+    (a, sa, ka, za, ia), (b, sb, kb, zb, ib) = res[False], res[True]
+    assert za == zb and np.array_equal(ka, kb)
+    assert np.array_equal(a, b) and sa == sb
+    assert np.array_equal(ia, ib)
+    assert len(za) == -(-steps // every)
+
+
+def test_device_selection_loop_lattice_2048():
+    """N = 2048, FP32, compared after every step: the first solve keeps the
+    18-state ball, then the loop runs on it; device and host loops agree
+    bitwise."""
+    wl = W.photon_lattice(gamma=0.0)
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    res = {}
+    for device in (False, True):
+        sol = P.Solver(wl, "fp32")
+        sol.set_rho(rho0)
+        print(f"selection loop lattice 2048 device={device}", flush=True)
+        out, kept, sizes = P.evolve_with_selection(sol, 40, 1e-20, 1, device=device)
+        res[device] = (out.get_rho(), kept, sizes)
+        if out is not sol:
+            out.close()
+        sol.close()
+    (ra, ka, za), (rb, kb, zb) = res[False], res[True]
+    assert za == zb and za[0] == 18 and np.array_equal(ka, kb)
+    assert np.array_equal(ra[0], rb[0]) and ra[1] == rb[1]
+
+
+def test_device_selection_loop_ragged_runs_and_errors():
+    """A step count that is not a multiple of the solve length (a run of
+    whole solves, then one of the remainder continuing from the populations
+    the first left) agrees with the host loop bitwise; qme_select_run
+    rejects bad arguments."""
+    wl = W.jc_single()
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    res = {}
+    for device in (False, True):
+        sol = P.Solver(wl, "fp64")
+        sol.set_fused(False)                  # the tiled step path as well
+        sol.set_rho(rho0)
+        print(f"selection ragged device={device}", flush=True)
+        out, kept, sizes = P.evolve_with_selection(sol, 2050, 1e-20, 100, device=device)
+        res[device] = (out.get_rho(), kept, sizes)
+        if out is not sol:
+            out.close()
+        sol.close()
+    (ra, ka, za), (rb, kb, zb) = res[False], res[True]
+    assert za == zb and len(za) == 21 and np.array_equal(ka, kb)
+    assert np.array_equal(ra[0], rb[0]) and ra[1] == rb[1]
+    sol = P.Solver(wl, "fp32")
+    sol.set_rho(rho0)
+    lib = L.load()
+    nbytes = L.c_size_t()
+    L.check(lib.qme_select_workspace_size(sol.ctx, L.ctypes.byref(nbytes)))
+    area = torch.empty(nbytes.value, dtype=torch.uint8, device=sol.state.device)
+    keep = np.zeros(sol.n, dtype=np.int32)
+    done, nk = L.c_int64(0), L.c_int64(0)
+    args = lambda solves, k, eps: (sol.ctx, L.c_void_p(sol.state.data_ptr()),  # noqa: E731
+                                   L.c_void_p(sol.workspace.data_ptr()), L.c_void_p(area.data_ptr()),
+                                   solves, k, eps, 1, L.ctypes.byref(done), L.ctypes.byref(nk),
+                                   keep.ctypes.data_as(L.POINTER(L.c_int32)), None)
+    assert lib.qme_select_run(*args(-1, 1, 0.0)) == L.QME_E_ARG
+    assert lib.qme_select_run(*args(1, 0, 0.0)) == L.QME_E_ARG
+    assert lib.qme_select_run(*args(1, 1, -1.0)) == L.QME_E_ARG
+    assert lib.qme_select_run(*args(1, 1, float("nan"))) == L.QME_E_ARG
+    assert lib.qme_select_run(*args(0, 1, 0.0)) == L.QME_OK and done.value == 0
+    # eps = 0 keeps everything: 5 solves, state as 5 plain steps
+    assert lib.qme_select_run(*args(5, 2, 0.0)) == L.QME_OK
+    assert done.value == 5 and nk.value == sol.n
+    ref = P.Solver(wl, "fp32")
+    ref.set_rho(rho0)
+    ref.step(10)
+    assert np.array_equal(sol.get_rho()[0], ref.get_rho()[0])
+    ref.close()
+    sol.close()
