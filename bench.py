@@ -44,8 +44,8 @@ PEAK_HBM = 8000.0           # GB/s
 # WRITE_SIZE counters (scaled by a plain-copy calibration) recorded in
 # profiles/cgemm_f32_lattice_n2048_hbm_counters.md for this source hash of
 # cgemm.hip; reported as null once the kernel source differs.
-TRAFFIC_FP32_PRODUCT = {"bytes": 377445.8 * 1024,
-                        "sha256": "789e2d7aad7e0a53a8dd96ca8f1400b5d8d9393994ec7e9cc77ac48b413bd191",
+TRAFFIC_FP32_PRODUCT = {"bytes": 272463.3 * 1024,
+                        "sha256": "b0a3d943abf0607f0c80a7b66912c88a554c31eaa7f4eace03d313e88c35296f",
                         "source": "profiles/cgemm_f32_lattice_n2048_hbm_counters.md"}
 KERNEL_SOURCES = ("cgemm.hip", "cgemm_tile.hpp")
 

@@ -300,8 +300,17 @@ constexpr bool f64_folds() {
   return 2 * BM * (BM + 1) + 2 * BM <= cgemm_f64_smem<BM, kConjB>();
 }
 
-hipError_t launch_cgemm_f32(const CgemmArgs<float> &a, int tile, const GemmOps &o, hipStream_t s) {
-  if (a.ld % tile != 0) return hipErrorInvalidValue;
+hipError_t launch_cgemm_f32(const CgemmArgs<float> &args, int tile, const GemmOps &o, hipStream_t s) {
+  if (args.ld % tile != 0) return hipErrorInvalidValue;
+  // progress-ranked wave priority for launches resident in one round (four
+  // workgroups per CU at most; larger launches overlap their rounds anyway)
+  CgemmArgs<float> a = args;
+  {
+    const int64_t tiles = a.ld / tile;
+    int64_t blocks = o.lower ? tiles * (tiles + 1) / 2 : tiles * tiles;
+    if (a.split > 1) blocks = a.full + (blocks - a.full) * a.split;
+    a.rank_prio = o.cus > 0 && blocks <= 4 * int64_t(o.cus) ? 1 : 0;
+  }
   if (a.fold_d && (!o.lower || o.b_rows ||
                    !(tile == 32 ? f32_folds<32>() : tile == 64 ? f32_folds<64>() : f32_folds<128>())))
     return hipErrorInvalidValue;

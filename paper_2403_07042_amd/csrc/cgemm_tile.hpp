@@ -385,6 +385,17 @@ __device__ __forceinline__ void cgemm_f32_tile(const CgemmArgs<float> &p, int bi
   __syncthreads();
   for (int kt = kb; kt < nk; ++kt) {
     const int st = (kt - kb) & 1;
+    // wave priority by progress: a workgroup in an earlier quarter of its k
+    // loop issues before one further along (co-resident workgroups would
+    // otherwise finish in dispatch order, the last ones at low occupancy)
+    if (p.rank_prio) {
+      switch (((kt - kb) * 4) / (nk - kb)) {
+        case 0: __builtin_amdgcn_s_setprio(3); break;
+        case 1: __builtin_amdgcn_s_setprio(2); break;
+        case 2: __builtin_amdgcn_s_setprio(1); break;
+        default: __builtin_amdgcn_s_setprio(0); break;
+      }
+    }
     if (kt + 1 < nk) gload((kt + 1) * KT);
     float ar[F][8], ai[F][8], br[F][8], bi_[F][8];
 #pragma unroll

@@ -95,6 +95,10 @@ struct CgemmArgs {
   double fold_dt = 0.0;
   int64_t fold_n = 0;
   double *zdiag = nullptr;
+  // FP32 register-staged tiles: the workgroups that are behind in their k
+  // loop issue first (set by the launcher when the whole launch is resident
+  // at once, so co-resident workgroups finish together)
+  int32_t rank_prio = 0;
 };
 
 // Plan of a tail split for a lower-triangle product of `tiles` tile rows

@@ -507,7 +507,7 @@ JumpTables jump_tables(const Model &m) {
     // sparse channel: A's entries per image key (basis state, removed state
     // id, or a private outside row per move onto -1), duplicates summed
     std::map<int64_t, std::map<int32_t, double>> rows;   // key -> (preimage -> coefficient)
-    int64_t private_key = -int64_t(1) << 62;
+    int64_t private_key = -(int64_t(1) << 62);
     for (const Model::Move &x : mv) {
       const int64_t key = x.dst == -1 ? private_key++ : x.dst;
       rows[key][x.src] += x.c;
