@@ -38,6 +38,7 @@
 //     along k (small-launch split); split tiles are summed in chunk order by
 //     a reduce pass.
 #include "cgemm_tile.hpp"
+#include "dissipate_tile.hpp"   // trace_body: the folded steps' trace in the first product
 
 #include <algorithm>
 
@@ -48,19 +49,42 @@ template <int BM, int OPS, bool LOWER, bool DIRECT = false>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p) {
   // 32-tiles: the 16x16-MFMA body (K tile 32); 64/128: the 32x32 bodies (K tile 16)
   constexpr int kSmem = BM == 32 ? cgemm_s_smem<float, 32, OPS>() : cgemm_f32_smem<BM, OPS>();
-  __shared__ float smem[kSmem];
+  __shared__ __align__(16) float smem[kSmem];
   static_assert(!DIRECT || (!(OPS & kBRow) && BM != 32), "direct loads serve the NT forms");
   // whole tile, or (split launches) one k-chunk of a tile into its partial slot
   const TileWork w = tile_work(blockIdx.x, int(p.ld / (BM == 32 ? 32 : 16)), p.full, p.split);
   int bi, bj;
   tile_coords(w.tile, int(p.ld / BM), LOWER, bi, bj);
   float *part = w.slot < 0 ? nullptr : p.part + size_t(w.slot) * 2 * BM * BM;
-  if constexpr (BM == 32)
+  if constexpr (BM == 32) {
     cgemm_s_tile<float, 32, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
-  else if constexpr (DIRECT)
-    cgemm_f32_tile_dma<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
-  else
-    cgemm_f32_tile<BM, OPS, LOWER>(p, bi, bj, smem, w.kb, w.ke, part);
+  } else {
+    auto run = [&](const CgemmArgs<float> &a) {
+      if constexpr (DIRECT)
+        cgemm_f32_tile_dma<BM, OPS, LOWER>(a, bi, bj, smem, w.kb, w.ke, part);
+      else
+        cgemm_f32_tile<BM, OPS, LOWER>(a, bi, bj, smem, w.kb, w.ke, part);
+    };
+    if (!LOWER && p.tr_aux) {
+      // folded steps: the previous step's factor, summed here by every block
+      // as the trace pass sums it (block 0 stores the scalars), in the
+      // operand LDS before the k loop uses it; the epilogue takes it by value
+      double *st = reinterpret_cast<double *>(smem);
+      DissArgs<float> da{nullptr, nullptr, nullptr, nullptr, p.ld, p.tr_n, p.tr_dt, nullptr,
+                         p.tr_leak, nullptr, nullptr, 0, p.tr_aux, p.tr_aux, p.tr_w, p.tr_zdiag};
+      da.slot_in = p.tr_slot_in;
+      da.slot_out = p.tr_slot_out;
+      const double f = trace_body<float, kThreads>(da, st, st + kThreads / 64,
+                                                   st + 2 * (kThreads / 64), blockIdx.x == 0);
+      __syncthreads();                      // every thread has read it before the LDS is reused
+      CgemmArgs<float> q = p;
+      q.scale_value = f;
+      q.scale_set = 1;
+      run(q);
+    } else {
+      run(p);
+    }
+  }
 }
 
 template <int BM, int OPS, bool LOWER>
@@ -302,6 +326,9 @@ constexpr bool f64_folds() {
 
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &args, int tile, const GemmOps &o, hipStream_t s) {
   if (args.ld % tile != 0) return hipErrorInvalidValue;
+  // the trace inside the product: full 64- / 128-tile launches without a split
+  if (args.tr_aux && (o.lower || tile == 32 || args.split > 1 || args.scale || args.scale_set))
+    return hipErrorInvalidValue;
   // progress-ranked wave priority for launches resident in one round (four
   // workgroups per CU at most; larger launches overlap their rounds anyway)
   CgemmArgs<float> a = args;

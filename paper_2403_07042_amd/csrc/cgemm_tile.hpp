@@ -265,8 +265,8 @@ __device__ __forceinline__ void f32_tile_epilogue(const CgemmArgs<float> &p, int
   float (*f_im)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem + BM * (BM + 1));
   double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
   // the scale read once, before the stores (which could alias it)
-  const bool scaled = p.scale != nullptr;
-  const double sc = scaled ? *p.scale : 1.0;
+  const bool scaled = p.scale != nullptr || p.scale_set;
+  const double sc = p.scale ? *p.scale : p.scale_set ? p.scale_value : 1.0;
   if (fold) {
     if (tid < 2 * BM) {
       const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;

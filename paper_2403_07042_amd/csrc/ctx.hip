@@ -316,9 +316,33 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   T *area = split_area_of<T>(c, ws);
   const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
   const double dt = c->model.dt;
+  // FP32 first products in 64- or 128-tiles without a split form the
+  // previous step's trace themselves (every block sums the stored diagonal,
+  // block 0 stores the scalars), so the trace pass runs once per call, after
+  // the last step; the sink and step count alternate between the scalar
+  // pairs by step parity (as for the unfolded steps)
+  bool fused_tr = false;
+  if constexpr (sizeof(T) == 4) {
+    if (c->precision == QME_FP32 && c->tile1 != 32) {
+      CgemmArgs<T> probe{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
+      plan_product<T>(c, probe, c->tile1, false, area, nullptr, 0);
+      fused_tr = probe.split <= 1;
+    }
+  }
   for (int64_t k = 0; k < n_steps; ++k) {
     CgemmArgs<T> g1{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
-    if (k > 0) g1.scale = aux + 4;
+    if (k > 0 && fused_tr) {
+      g1.tr_zdiag = zdiag;
+      g1.tr_w = c->trw;
+      g1.tr_leak = c->leak;
+      g1.tr_aux = aux;
+      g1.tr_n = c->n;
+      g1.tr_dt = dt;
+      g1.tr_slot_in = int32_t((k - 1) & 1);
+      g1.tr_slot_out = int32_t(k & 1);
+    } else if (k > 0) {
+      g1.scale = aux + 4;
+    }
     CgemmArgs<T> g2{y_re, y_im, u_re, u_im, y_re, y_im, x_re, x_im, c->ld, T(1), T(1)};
     g2.fold_d = c->d;
     g2.fold_dt = dt;
@@ -328,6 +352,10 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     plan_product<T>(c, g2, c->tile2, true, area, z_re, 2 * pe);
     DissArgs<T> da{nullptr, nullptr, x_re, x_im, c->ld, c->n, dt, c->d, c->leak,
                    c->pi, c->cg, 0, aux, aux, c->trw, zdiag};
+    if (fused_tr) {
+      da.slot_in = int(k & 1);
+      da.slot_out = int((k + 1) & 1);
+    }
     GemmOps o1, o2;
     o1.conj_b = o2.conj_b = true;
     o2.lower = true;
@@ -351,11 +379,16 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     if (e == hipSuccess) e = mark(c, s, 0);
     if (e == hipSuccess) e = gemm(g2, c->tile2, o2);
     if (e == hipSuccess) e = mark(c, s, 1);
-    if (e == hipSuccess) e = launch_trace<T>(da, s);
+    // with fused_tr the next step's first product forms this trace
+    if (e == hipSuccess && (!fused_tr || k == n_steps - 1)) e = launch_trace<T>(da, s);
     if (e == hipSuccess) e = mark(c, s, 2);
     if (e != hipSuccess) return e;
   }
-  launch_timer() = nullptr;   // the closing pass is no step's kernel
+  launch_timer() = nullptr;   // the closing passes are no step's kernels
+  if (fused_tr && (n_steps & 1)) {
+    const hipError_t e = launch_scalars_home(aux, s);
+    if (e != hipSuccess) return e;
+  }
   return n_steps > 0 ? launch_apply_scale<T>(x_re, x_im, int64_t(pe), aux + 4, s) : hipSuccess;
 }
 

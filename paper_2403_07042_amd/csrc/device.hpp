@@ -95,6 +95,21 @@ struct CgemmArgs {
   double fold_dt = 0.0;
   int64_t fold_n = 0;
   double *zdiag = nullptr;
+  // FP32 folded steps (64- and 128-tile first products, no split): the
+  // previous step's trace formed by every block of the first product with
+  // the trace pass's arithmetic (DissArgs: the stored diagonal of Z, trace
+  // and leak weights, the state's scalars, the scalar slot pairs read and
+  // written); block 0 stores the step's scalars, and the factor it gives is
+  // the product's alpha = beta (in place of `scale`).
+  const double *tr_zdiag = nullptr, *tr_w = nullptr, *tr_leak = nullptr;
+  double *tr_aux = nullptr;
+  int64_t tr_n = 0;
+  double tr_dt = 0.0;
+  int32_t tr_slot_in = 0, tr_slot_out = 0;
+  // a factor given by value (scale_set): alpha = beta = scale_value in FP64,
+  // as for `scale` (the kernels set it from the trace they form)
+  double scale_value = 0.0;
+  int32_t scale_set = 0;
   // FP32 register-staged tiles: the workgroups that are behind in their k
   // loop issue first (set by the launcher when the whole launch is resident
   // at once, so co-resident workgroups finish together)

@@ -210,6 +210,42 @@ def test_fused_trace_scalars_across_calls(make, precision, graph):
         assert np.array_equal(aux, out[0][1])
 
 
+@pytest.mark.parametrize("tiles", [(64, 64), (128, 64), (32, 64)])
+def test_folded_trace_in_first_product_scalars(tiles):
+    """Folded FP32 steps at N = 2048: with 64- or 128-tile first products
+    every block of the next first product forms the previous step's trace
+    (one trace launch per call, the sink and step count alternating between
+    the scalar pairs); 32-tile first products keep the trace pass.  Over any
+    split of 7 steps into calls the step count is 7, the sink agrees with one
+    call's to rounding and the trace is 1 - sink."""
+    wl = dict(W.photon_lattice(gamma=0.05), init={"kind": "haar", "seed": 11})
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    ref = None
+    for split in ([7], [1, 2, 4], [3, 3, 1], [2, 5], [1, 1, 1, 1, 1, 1, 1]):
+        sol = P.Solver(wl, "fp32")
+        sol.set_tiles(*tiles)
+        sol.set_rho(rho0, sink=0.125)
+        sol.profile(True)
+        print(f"folded trace tiles={tiles} split={split}", flush=True)
+        for k in split:
+            sol.step(k)
+        torch.cuda.synchronize()
+        counts = [c for _, c in sol.profile_read().values()]
+        rho, sink = sol.get_rho()
+        _, trace, _ = sol.observe()
+        aux = _scalars(sol)
+        sol.close()
+        assert counts[0] == 7 and counts[1] == 7 and counts[3] == 0
+        assert counts[2] == (len(split) if tiles[0] != 32 else 7)
+        assert aux[3] == 7.0 and aux[0] == sink and sink > 0.125
+        assert abs(trace - (1.0 - sink)) < 1e-6
+        if ref is None:
+            ref = (rho, sink)
+        else:
+            assert abs(sink - ref[1]) < 1e-9
+            assert np.abs(rho - ref[0]).max() < 1e-6 * np.abs(ref[0]).max()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_tch_n144(precision):
     wl = W.tch_2x2()
@@ -314,9 +350,12 @@ def test_folded_steps_match_unfolded(precision, tol, tiles):
         rho, sink = sol.get_rho()
         pops, trace, _ = sol.observe()
         out[fold] = (rho, sink, trace, counts)
+    # FP32 64-tile first products form the previous step's trace: one trace
+    # launch per qme_step call
+    fused_trace = precision == "fp32" and sol.tile1 != 32
     sol.close()
     (a, sa, ta, ca), (b, sb, tb, cb) = out[True], out[False]
-    assert ca == [24, 24, 24, 0] and cb == [24, 24, 24, 24]
+    assert ca == [24, 24, 3 if fused_trace else 24, 0] and cb == [24, 24, 24, 24]
     assert np.abs(a - b).max() < tol * np.abs(b).max()
     assert abs(sa - sb) < TRACE_TOL[precision] and sa > 1e-6       # real sink
     assert abs(ta - (1.0 - sa)) < TRACE_TOL[precision]
@@ -438,10 +477,14 @@ def test_leaking_lattice_folded_against_oracle(side, steps, precision):
     torch.cuda.synchronize()
     counts = [c for _, c in sol.profile_read().values()]
     sol.profile(False)
+    # FP32 64-tile first products form the previous step's trace themselves:
+    # one trace launch per call
+    fused_trace = precision == "fp32" and sol.tile1 != 32
     rho, sink = sol.get_rho()
     _, trace, _ = sol.observe()
     sol.close()
-    assert counts == [steps, steps, steps, 0]          # folded: no decoherence pass
+    # folded: no decoherence pass
+    assert counts == [steps, steps, 1 if fused_trace else steps, 0]
     err = np.abs(rho - rref).max()
     print(f"lattice {side}x{side} {precision}: max|drho| = {err:.3e}, sink {sink:.6e}", flush=True)
     assert err < TOL[precision]
