@@ -36,6 +36,16 @@ def gpu_run(wl, precision, checkpoints):
     return out
 
 
+def folded_trace_fused(sol, precision):
+    """Whether folded steps form the trace inside the next first product:
+    FP32 64- or 128-tile first products that are not cut along k (a
+    small-launch split applies below two tiles per compute unit)."""
+    if precision != "fp32" or sol.tile1 == 32:
+        return False
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return 2 * (sol.ld // sol.tile1) ** 2 > cus
+
+
 def oracle_run(wl, checkpoints):
     s = ev.System(wl)
     rho, sink = W.initial_rho(wl, s.occ), 0.0
@@ -210,9 +220,10 @@ def test_fused_trace_scalars_across_calls(make, precision, graph):
         assert np.array_equal(aux, out[0][1])
 
 
-@pytest.mark.parametrize("tiles", [(64, 64), (128, 64), (32, 64)])
-def test_folded_trace_in_first_product_scalars(tiles):
-    """Folded FP32 steps at N = 2048: with 64- or 128-tile first products
+@pytest.mark.parametrize("precision,tiles", [("fp32", (64, 64)), ("fp32", (128, 64)),
+                                             ("fp32", (32, 64)), ("bf16x3", (64, 64))])
+def test_folded_trace_in_first_product_scalars(precision, tiles):
+    """Folded steps at N = 2048: with FP32 64- or 128-tile first products
     every block of the next first product forms the previous step's trace
     (one trace launch per call, the sink and step count alternating between
     the scalar pairs); 32-tile first products keep the trace pass.  Over any
@@ -222,11 +233,11 @@ def test_folded_trace_in_first_product_scalars(tiles):
     rho0 = W.initial_rho(wl, P.basis(wl))
     ref = None
     for split in ([7], [1, 2, 4], [3, 3, 1], [2, 5], [1, 1, 1, 1, 1, 1, 1]):
-        sol = P.Solver(wl, "fp32")
+        sol = P.Solver(wl, precision)
         sol.set_tiles(*tiles)
         sol.set_rho(rho0, sink=0.125)
         sol.profile(True)
-        print(f"folded trace tiles={tiles} split={split}", flush=True)
+        print(f"folded trace {precision} tiles={tiles} split={split}", flush=True)
         for k in split:
             sol.step(k)
         torch.cuda.synchronize()
@@ -236,7 +247,7 @@ def test_folded_trace_in_first_product_scalars(tiles):
         aux = _scalars(sol)
         sol.close()
         assert counts[0] == 7 and counts[1] == 7 and counts[3] == 0
-        assert counts[2] == (len(split) if tiles[0] != 32 else 7)
+        assert counts[2] == (len(split) if precision == "fp32" and tiles[0] != 32 else 7)
         assert aux[3] == 7.0 and aux[0] == sink and sink > 0.125
         assert abs(trace - (1.0 - sink)) < 1e-6
         if ref is None:
@@ -352,7 +363,7 @@ def test_folded_steps_match_unfolded(precision, tol, tiles):
         out[fold] = (rho, sink, trace, counts)
     # FP32 64-tile first products form the previous step's trace: one trace
     # launch per qme_step call
-    fused_trace = precision == "fp32" and sol.tile1 != 32
+    fused_trace = folded_trace_fused(sol, precision)
     sol.close()
     (a, sa, ta, ca), (b, sb, tb, cb) = out[True], out[False]
     assert ca == [24, 24, 3 if fused_trace else 24, 0] and cb == [24, 24, 24, 24]
@@ -479,7 +490,7 @@ def test_leaking_lattice_folded_against_oracle(side, steps, precision):
     sol.profile(False)
     # FP32 64-tile first products form the previous step's trace themselves:
     # one trace launch per call
-    fused_trace = precision == "fp32" and sol.tile1 != 32
+    fused_trace = folded_trace_fused(sol, precision)
     rho, sink = sol.get_rho()
     _, trace, _ = sol.observe()
     sol.close()
