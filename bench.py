@@ -100,16 +100,21 @@ def parse():
 PROFILE_EVERY = 8
 
 
-def timed_leg(P, W, torch, wl, precision, steps, warmup, tiles=""):
+def timed_leg(P, W, torch, wl, precision, steps, warmup, tiles="", tune=False):
     """steps/s of `steps` time steps with no profiling (the throughput), then
     the same steps again from the same state with per-kernel events on every
-    PROFILE_EVERY-th step (the kernel durations)."""
+    PROFILE_EVERY-th step (the kernel durations).  tune: tile pair and split
+    picked first by the autotuner (timed on a scratch state, no cache)."""
     occ = P.basis(wl)
     rho0 = W.initial_rho(wl, occ)
     sol = P.Solver(wl, precision)
     if tiles:
         sol.set_tiles(*[int(x) for x in tiles.split(",")])
     sol.set_rho(rho0)
+    tuned = None
+    if tune:
+        from paper_2403_07042_amd import autotune as A
+        tuned = A.tune_solver(sol, steps=8, trials=3, use_cache=False)
     sol.step(warmup)
     torch.cuda.synchronize()
     sol.set_rho(rho0)
@@ -141,9 +146,10 @@ def timed_leg(P, W, torch, wl, precision, steps, warmup, tiles=""):
         "kernels_us": kern,
         "kernels_us_sum": sum(kern.values()),
         "profiled_ms_per_step": 1e3 * (p1 - p0) / steps,
-        "tiles": tiles or "default",
-        "tile1": int(tiles.split(",")[0]) if tiles else (32 if precision == "fp64" else 64),
-        "tile2": int(tiles.split(",")[1]) if tiles else (32 if precision == "fp64" else 64),
+        "tiles": tiles or ("autotuned" if tune else "default"),
+        "tile1": sol.tile1,
+        "tile2": sol.tile2,
+        "tuned_split": None if tuned is None else bool(tuned[2]),
         "pops": pops, "trace": trace, "sink": sink, "n": sol.n, "ld": sol.ld,
     }
     sol.close()
@@ -361,15 +367,17 @@ def configs_leg(P, W, torch, warmup=10, steps_override=0):
     """FP32, split-BF16x3 and plain FP64 steps/s, with the speedups over FP64,
     on the other parity configurations: the 2 x 2 Tavis-Cummings-Hubbard
     model (N = 144, 2000 steps) and the three-cavity chain (N = 1728, 200
-    steps); steps_override > 0 runs that many steps on both."""
+    steps), each context's tile pair and split picked by the autotuner;
+    steps_override > 0 runs that many steps on both."""
     out = {}
     for name, wl, steps in (("tch_2x2_n144", W.tch_2x2(), steps_override or 2000),
                             ("tch_chain3_n1728", W.tch_chain3(), steps_override or 200)):
-        rates = {}
+        rates, picked = {}, {}
         for prec in ("fp32", "bf16x3", "fp64"):
-            leg = timed_leg(P, W, torch, wl, prec, steps, warmup)
+            leg = timed_leg(P, W, torch, wl, prec, steps, warmup, tune=True)
             rates[prec] = leg["steps_per_s"]
-        out[name] = {"steps": steps, "steps_per_s": rates,
+            picked[prec] = {"tiles": [leg["tile1"], leg["tile2"]], "split": leg["tuned_split"]}
+        out[name] = {"steps": steps, "steps_per_s": rates, "autotuned": picked,
                      "fp32_speedup_over_fp64": rates["fp32"] / rates["fp64"],
                      "bf16x3_speedup_over_fp64": rates["bf16x3"] / rates["fp64"]}
     return out

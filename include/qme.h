@@ -511,10 +511,14 @@ qme_status qme_cgemm(int32_t precision, int64_t ld, const void *a_re_dev,
 
 /* Tile edge of the two products of each step (the autotuner's knob):
  * tile1 for T = rho + dU rho, tile2 for the lower-triangle product.
- * FP32 tiles: 128, 64 or 32; FP64 tiles: 64 or 32; BF16X3: 64.  Each must divide the
+ * FP32 tiles: 128, 64 or 32; FP64 tiles: 64 or 32; BF16X3: tile2 64, tile1
+ * 64 or 128 (128: the first product on 128 x 64 tiles, bitwise-identical
+ * results; a split first product still takes 64-tiles).  Each must divide the
  * state's leading dimension ld (qme_state_layout), else QME_E_ARG.  Defaults:
  * FP64 32; FP32 32 when the full product in 64-tiles would give fewer than
- * four workgroups per compute unit, else 64; BF16X3 64. */
+ * four workgroups per compute unit, else 64; BF16X3 64, with tile1 128 when
+ * ld is a multiple of 128 and the 128 x 64 tiles number at least twice the
+ * compute units. */
 qme_status qme_set_tiles(qme_ctx *ctx, int32_t tile1, int32_t tile2);
 
 /* The tile edges the context's two products use now (defaults or

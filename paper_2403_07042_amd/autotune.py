@@ -30,7 +30,7 @@ CACHE_ENV = "QME_TUNE_CACHE"
 TILES = {
     "fp32": [(32, 32), (32, 64), (64, 32), (64, 64), (64, 128), (128, 64), (128, 128)],
     "fp64": [(32, 32), (32, 64), (64, 32), (64, 64)],
-    "bf16x3": [(64, 64)],
+    "bf16x3": [(64, 64), (128, 64)],
 }
 
 

@@ -246,6 +246,163 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
   }
 }
 
+// Full-grid tile order of the wide first product (tr x tc tiles, block t
+// dispatched to XCD t % 8): with tr % 4 == 0 and tc % 2 == 0 each XCD takes a
+// (tr / 4) x (tc / 2) sub-grid walked column by column in groups of at most
+// eight tile rows, so its workgroups share row and column panels in its L2;
+// otherwise column-major groups of four tile rows.
+__device__ __forceinline__ void wide_coords(int t, int tr, int tc, int &bi, int &bj) {
+  if ((tr & 3) == 0 && (tc & 1) == 0) {
+    const int x = t & 7, l = t >> 3;
+    const int R = tr >> 2, C = tc >> 1;
+    const int G = R < 8 ? R : 8;
+    const int g = l / (G * C), in = l - g * (G * C);
+    const int rows = min(G, R - g * G);
+    bi = (x >> 1) * R + g * G + in % rows;
+    bj = (x & 1) * C + in / rows;
+    return;
+  }
+  const int gsz = 4 * tc, g = t / gsz, first = 4 * g;
+  const int rows = min(4, tr - first), in = t - g * gsz;
+  bi = first + in % rows;
+  bj = in / rows;
+}
+
+// The first product of a time step, T = rho + dU rho in the NT form with M
+// conjugated (dU pre-split as A), on 128 x 64 output tiles: 4 waves (2 x 2),
+// each a 64 x 32 block of two 32 x 32 MFMA blocks that share the fragments
+// of M, so a 16-k step reads 18 fragments from LDS for 48 MFMAs (the 64 x 64
+// tile: 12 for 24).  LDS holds the six pre-split planes of 128 A rows and
+// the six planes of 64 M rows split while staged (72 KB: two workgroups per
+// CU, so a grid of twice the compute units runs in one round).  Per element
+// the k order, the six products and the three accumulators are those of
+// cgemm_bf16x3_kernel, and the epilogue is the FP32 tiles', so the two give
+// bitwise-identical results.
+__global__ __launch_bounds__(kThreads3, 2) void cgemm_bf16x3_wide_kernel(CgemmArgs<float> p) {
+  constexpr int BA = 128, BB = 64, KT = 32, LDK = KT;
+  auto slot = [](int row, int c) { return 8 * (c ^ dma_swz(row)); };
+  __shared__ __align__(16) __bf16 sA[6][BA * LDK];
+  __shared__ __align__(16) __bf16 sB[6][BB * LDK];
+
+  const int64_t ld = p.ld;
+  int bi, bj;
+  wide_coords(blockIdx.x, int(ld / BA), int(ld / BB), bi, bj);
+  const int nk = int(ld / KT);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 31, h = lane >> 5;
+
+  // A: 128 rows x 4 chunks of 8 bf16 per plane, two chunks per thread and
+  // plane (rows pr and pr + 64); M: 64 rows x 32 k per FP32 plane, two
+  // float4 per thread and plane (rows lr and lr + 32)
+  const int pr = tid >> 2, pk = (tid & 3) * 8;
+  const __bf16 *psrc = static_cast<const __bf16 *>(p.a_split) + (int64_t(bi) * BA + pr) * ld + pk;
+  const int64_t pstride = ld * ld;
+  const int lr = tid >> 3, lk = (tid & 7) * 4;
+  const float *msrc[2] = {p.m_re + (int64_t(bj) * BB + lr) * ld + lk,
+                          p.m_im + (int64_t(bj) * BB + lr) * ld + lk};
+  bf16x8 preg[6][2];
+  floatx4 reg[2][2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int pl = 0; pl < 6; ++pl)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        preg[pl][q] = *reinterpret_cast<const bf16x8 *>(psrc + pl * pstride + int64_t(q) * 64 * ld + k0);
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        reg[o][q] = *reinterpret_cast<const floatx4 *>(msrc[o] + int64_t(q) * 32 * ld + k0);
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int pl = 0; pl < 6; ++pl)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int row = pr + 64 * q;
+        *reinterpret_cast<bf16x8 *>(&sA[pl][row * LDK + slot(row, pk >> 3)]) = preg[pl][q];
+      }
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      __bf16 *base = &sB[o * 3][0];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        uint32_t vh[2], vm[2], vl[2];
+        split3_pair(reg[o][q][0], reg[o][q][1], vh[0], vm[0], vl[0]);
+        split3_pair(reg[o][q][2], reg[o][q][3], vh[1], vm[1], vl[1]);
+        const int row = q * 32 + lr;
+        const int off = row * LDK + slot(row, lk >> 3) + (lk & 7);
+        *reinterpret_cast<uint2 *>(base + 0 * BB * LDK + off) = make_uint2(vh[0], vh[1]);
+        *reinterpret_cast<uint2 *>(base + 1 * BB * LDK + off) = make_uint2(vm[0], vm[1]);
+        *reinterpret_cast<uint2 *>(base + 2 * BB * LDK + off) = make_uint2(vl[0], vl[1]);
+      }
+    }
+  };
+
+  // (A + i Ai)(Br - i Bi): Cr += Ar Br + Ai Bi, Ci += Ai Br - Ar Bi, the
+  // negative products in cin (subtracted once after the k loop)
+  floatx16 cr[2], ci[2], cin[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { cr[b][r] = 0.0f; ci[b][r] = 0.0f; cin[b][r] = 0.0f; }
+
+  gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();             // previous tile's fragments consumed
+    lstore();
+    __syncthreads();
+    if (kt + 1 < nk) gload((kt + 1) * KT);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 br[3], bim[3];
+      const int rb_ = wn * 32 + li;
+      const int ob = rb_ * LDK + slot(rb_, 2 * s + h);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        br[t] = *reinterpret_cast<const bf16x8 *>(&sB[t][ob]);
+        bim[t] = *reinterpret_cast<const bf16x8 *>(&sB[3 + t][ob]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bf16x8 ar[3], ai[3];
+        const int ra_ = wm * 64 + b * 32 + li;
+        const int oa = ra_ * LDK + slot(ra_, 2 * s + h);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          ar[t] = *reinterpret_cast<const bf16x8 *>(&sA[t][oa]);
+          ai[t] = *reinterpret_cast<const bf16x8 *>(&sA[3 + t][oa]);
+        }
+        cr[b] = mac3(ar, br, cr[b]);
+        ci[b] = mac3(ai, br, ci[b]);
+        cr[b] = mac3(ai, bim, cr[b]);
+        cin[b] = mac3(ar, bim, cin[b]);
+        // one block's A fragments live at a time
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+
+  const bool has_x = p.beta != 0.0f;
+  const bool scaled = p.scale != nullptr;
+  const double sc = p.scale ? *p.scale : 1.0;
+  const int64_t col = int64_t(bj) * BB + wn * 32 + li;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = int64_t(bi) * BA + wm * 64 + b * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      const int64_t o = row * ld + col;
+      float vr, vi;
+      epi_value(p, has_x, scaled, sc, o, cr[b][r], ci[b][r] - cin[b][r], vr, vi);
+      p.c_re[o] = vr;
+      p.c_im[o] = vi;
+    }
+  }
+}
+
 template <typename K>
 static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipStream_t s) {
   const int tiles = int(a.ld / 64);
@@ -263,6 +420,15 @@ static hipError_t launch3(K kernel, const CgemmArgs<float> &a, bool lower, hipSt
 
 hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipStream_t s) {
   if (a.ld % 64 != 0 || o.b_rows) return hipErrorInvalidValue;
+  if (o.wide) {
+    // 128 x 64 tiles: the step's first product only, unsplit, unfolded
+    if (a.ld % 128 != 0 || !a.a_split || o.lower || o.conj_a || !o.conj_b || a.split > 1 ||
+        a.fold_d || a.tr_aux || a.scale_set)
+      return hipErrorInvalidValue;
+    const int blocks = int((a.ld / 128) * (a.ld / 64));
+    if (blocks == 0) return hipSuccess;
+    return launch_kernel(cgemm_bf16x3_wide_kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
+  }
   // the folded epilogue exists for the step's lower-triangle product only
   if (a.fold_d && !(o.lower && a.m_split)) return hipErrorInvalidValue;
   if (a.a_split && a.m_split) return hipErrorInvalidValue;

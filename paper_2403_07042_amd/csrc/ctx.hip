@@ -100,6 +100,13 @@ void pick_tiles(qme_ctx *c) {
     c->tile1 = c->tile2 = 64;
   }
   c->ld = round_up(c->n, c->precision == QME_FP64 ? std::max(c->tile1, c->tile2) : 64);
+  // BF16x3: the first product on 128 x 64 tiles (two workgroups per CU) when
+  // they fill at least one round of the device: at N = 2048, 512 such tiles
+  // in one round took 243 us against 281 us for the 64-tiles' 1024 in a round
+  // of three per CU and a second one
+  if (c->precision == QME_BF16X3 && c->ld % 128 == 0 &&
+      2 * (c->ld / 128) * (c->ld / 128) >= 2 * int64_t(c->cus))
+    c->tile1 = 128;
 }
 
 size_t plane_elems(const qme_ctx *c) { return size_t(c->ld) * size_t(c->ld); }
@@ -156,6 +163,15 @@ static int k_tile(const qme_ctx *c, int tile) {
 }
 
 static bool small_split_applies(const qme_ctx *c) { return c->tail_split; }
+
+// BF16x3 contexts with tile1 = 128 run the step's first product on 128 x 64
+// tiles (launch_cgemm_bf16x3, GemmOps::wide) unless its launch is split; the
+// split plan is that of the 64-tiles, which the split launch then takes.
+static int plan_tile1(const qme_ctx *c) { return c->precision == QME_BF16X3 ? 64 : c->tile1; }
+template <typename T>
+static bool wide_first(const qme_ctx *c, const CgemmArgs<T> &g1) {
+  return c->precision == QME_BF16X3 && c->tile1 == 128 && g1.split <= 1;
+}
 
 static size_t small_split_elems(const qme_ctx *c) {
   const std::vector<int> edges = c->precision == QME_FP64   ? std::vector<int>{32, 64}
@@ -230,8 +246,9 @@ hipError_t step_once(qme_ctx *c, const void *in, void *out, void *y, void *z, hi
   // caller has them); the lower product's tail into the output planes, dead
   // until the decoherence pass
   T *area = static_cast<T *>(split_area);
-  plan_product<T>(c, g1, c->tile1, false, area, nullptr, 0);
+  plan_product<T>(c, g1, plan_tile1(c), false, area, nullptr, 0);
   plan_product<T>(c, g2, c->tile2, true, area, o_re, 2 * pe);
+  o1.wide = wide_first(c, g1);
   hipError_t e = mark(c, s, -1);
   if constexpr (sizeof(T) == 4) {
     if (c->precision == QME_BF16X3) {
@@ -348,7 +365,7 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
     g2.fold_dt = dt;
     g2.fold_n = c->n;
     g2.zdiag = zdiag;
-    plan_product<T>(c, g1, c->tile1, false, area, nullptr, 0);
+    plan_product<T>(c, g1, plan_tile1(c), false, area, nullptr, 0);
     plan_product<T>(c, g2, c->tile2, true, area, z_re, 2 * pe);
     DissArgs<T> da{nullptr, nullptr, x_re, x_im, c->ld, c->n, dt, c->d, c->leak,
                    c->pi, c->cg, 0, aux, aux, c->trw, zdiag};
@@ -365,6 +382,7 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
       // dU pre-split for both products, as in step_once
       g1.a_split = c->du_split;
       g2.m_split = c->du_split;
+      o1.wide = wide_first(c, g1);
     }
     auto gemm = [&](const CgemmArgs<T> &g, int tile, const GemmOps &o) {
       if constexpr (sizeof(T) == 4) {
@@ -1291,7 +1309,9 @@ extern "C" qme_status qme_set_tiles(qme_ctx *c, int32_t tile1, int32_t tile2) {
                                             : t == 64;
     return valid && c->ld % t == 0;
   };
-  if (!ok(tile1) || !ok(tile2)) {
+  // BF16x3: the first product also on 128 x 64 tiles
+  const bool wide = c->precision == QME_BF16X3 && tile1 == 128 && c->ld % 128 == 0 && tile2 == 64;
+  if (!(ok(tile1) || wide) || !ok(tile2)) {
     set_error("tile not supported for this precision or does not divide ld");
     return QME_E_ARG;
   }

@@ -61,6 +61,8 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem,
 struct GemmOps {
   bool conj_a = false, conj_b = false, b_rows = false, lower = false;
   int direct = 0, cus = 0;
+  // BF16x3 first product of a step on 128 x 64 tiles (launch_cgemm_bf16x3)
+  bool wide = false;
 };
 
 // Split launches (FP32, FP64 and BF16x3 products): when

@@ -10,7 +10,8 @@ def test_candidates_respect_ld_and_precision():
                                           (128, 64), (128, 128)]
     assert A.candidates("fp32", 1728) == [(32, 32), (32, 64), (64, 32), (64, 64)]
     assert A.candidates("fp64", 96) == [(32, 32)]
-    assert A.candidates("bf16x3", 2048) == [(64, 64)]
+    assert A.candidates("bf16x3", 2048) == [(64, 64), (128, 64)]
+    assert A.candidates("bf16x3", 1728) == [(64, 64)]
 
 
 def test_cache_round_trip(tmp_path):

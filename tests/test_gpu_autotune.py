@@ -13,7 +13,7 @@ P = pytest.importorskip("paper_2403_07042_amd")
 from paper_2403_07042_amd import autotune as A  # noqa: E402
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "bf16x3"])
 def test_tile_choice_is_bitwise_neutral_and_tuner_picks_valid(precision, tmp_path):
     wl = W.photon_lattice(16, 16)          # N = 512
     occ = P.basis(wl)
@@ -22,7 +22,8 @@ def test_tile_choice_is_bitwise_neutral_and_tuner_picks_valid(precision, tmp_pat
     sol.set_fold(False)          # folding depends on the lower tile; compare tiles alone
     sol.set_split(False)         # so do the k-splits of small launches
     outs = []
-    # one matrix-core shape: FP32 64/128-tiles (32x32 MFMA), FP64 32/64 (16x16)
+    # one matrix-core shape: FP32 64/128-tiles (32x32 MFMA), FP64 32/64
+    # (16x16), BF16x3 64 x 64 and 128 x 64 first-product tiles
     same_shape = [t for t in A.candidates(precision, sol.ld)
                   if precision != "fp32" or 32 not in t]
     for tiles in same_shape:

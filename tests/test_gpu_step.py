@@ -221,7 +221,8 @@ def test_fused_trace_scalars_across_calls(make, precision, graph):
 
 
 @pytest.mark.parametrize("precision,tiles", [("fp32", (64, 64)), ("fp32", (128, 64)),
-                                             ("fp32", (32, 64)), ("bf16x3", (64, 64))])
+                                             ("fp32", (32, 64)), ("bf16x3", (64, 64)),
+                                             ("bf16x3", (128, 64))])
 def test_folded_trace_in_first_product_scalars(precision, tiles):
     """Folded steps at N = 2048: with FP32 64- or 128-tile first products
     every block of the next first product forms the previous step's trace
@@ -255,6 +256,43 @@ def test_folded_trace_in_first_product_scalars(precision, tiles):
         else:
             assert abs(sink - ref[1]) < 1e-9
             assert np.abs(rho - ref[0]).max() < 1e-6 * np.abs(ref[0]).max()
+
+
+@pytest.mark.parametrize("make", [lambda: W.photon_lattice(32, 16, gamma=0.05),
+                                  lambda: W.photon_lattice(gamma=0.05)])
+@pytest.mark.parametrize("fold", [True, False])
+def test_bf16x3_wide_first_product_bitwise(make, fold):
+    """BF16x3 first products on 128 x 64 tiles (tile1 = 128) against the
+    64 x 64 tiles: the same k order, products and epilogue per element, so
+    the states and scalars after 3 + 4 steps are bitwise identical, folded
+    (the renormalisation scale in the first product) and unfolded, at
+    N = 1024 and N = 2048 (leaking lattices, Haar start, sink 0.125).  The
+    default takes 128 x 64 tiles where there are at least twice as many of
+    them as compute units (N = 2048 on 256 compute units)."""
+    wl = dict(make(), init={"kind": "haar", "seed": 5})
+    rho0 = W.initial_rho(wl, P.basis(wl))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for tiles in ((64, 64), (128, 64)):
+        sol = P.Solver(wl, "bf16x3")
+        if tiles == (64, 64):
+            wide = sol.ld % 128 == 0 and 2 * (sol.ld // 128) ** 2 >= 2 * cus
+            assert sol.tiles == ((128, 64) if wide else (64, 64))
+        sol.set_tiles(*tiles)
+        sol.set_fold(fold)
+        sol.set_rho(rho0, sink=0.125)
+        print(f"bf16x3 wide N={sol.n} tiles={tiles} fold={fold}", flush=True)
+        sol.step(3)
+        sol.step(4)
+        torch.cuda.synchronize()
+        rho, sink = sol.get_rho()
+        out[tiles] = (rho, sink, _scalars(sol))
+        sol.close()
+    a, b = out[(64, 64)], out[(128, 64)]
+    assert np.array_equal(a[0], b[0])
+    assert a[1] == b[1]
+    assert np.array_equal(a[2], b[2])
+    assert a[1] > 0.125 and np.array_equal(a[0], a[0].conj().T)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
@@ -531,6 +569,8 @@ def small_split_expected(ld, tile, precision, cus):
     most half as many tiles as compute units, and at least two chunks of two
     K tiles (K tile: 32 for BF16x3 and FP32 32-tiles, else 16).  Returns
     (first product split, lower-triangle product split)."""
+    if precision == "bf16x3":
+        tile = 64                    # a split BF16x3 product runs on 64-tiles
     t = ld // tile
     kt = 32 if precision == "bf16x3" or (precision == "fp32" and tile == 32) else 16
 
@@ -551,7 +591,8 @@ def test_small_launch_split(make, precision, tol):
     """Products too small to occupy the device are cut along k: the split
     step against the unsplit one and (N = 144) the oracle, over several
     qme_step calls, with 64- and 128-tiles (FP32), 32- and 64-tiles (FP64) or
-    64-tiles (BF16x3).  Where the split rule applies to a tiling, the split
+    64-tiles and a 128 x 64 first product (BF16x3, whose split launch takes
+    the 64-tiles).  Where the split rule applies to a tiling, the split
     result must differ from the unsplit one (the k sums are regrouped), so a
     split that silently did not run fails."""
     wl = dict(make(), init={"kind": "haar", "seed": 11})
@@ -560,7 +601,7 @@ def test_small_launch_split(make, precision, tol):
     sol = P.Solver(wl, precision)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     tiles = {"fp32": [(64, 64), (128, 128), (32, 32)], "fp64": [(32, 32), (64, 64)],
-             "bf16x3": [(64, 64)]}[precision]
+             "bf16x3": [(64, 64), (128, 64)]}[precision]
     outs = {}
     ran = []
     for t in tiles:
