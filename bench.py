@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QME steps/sec at N=2048 (FP32 MFMA vs FP64) + adjoint grad time/step"
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6       # TFLOP/s, MI355X dense FP64 matrix
+PEAK_BF16_MFMA = 2500.0     # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0           # GB/s
 
 # HBM bytes per launch of the first FP32 product, from the FETCH_SIZE /
@@ -662,8 +663,12 @@ def main():
                           "steps": args.bf16x3_steps, "kernels_us": b["kernels_us"],
                           "dense_equivalent_frac_of_fp32_peak":
                               flops_step * b["steps_per_s"] / 1e12 / PEAK_FP32_MFMA,
+                          "tiles": [b["tile1"], b["tile2"]],
                           "bf16_mfma_tflops_first_product":
-                              6 * flops_product / (b["kernels_us"]["product_full"] * 1e-6) / 1e12}
+                              6 * flops_product / (b["kernels_us"]["product_full"] * 1e-6) / 1e12,
+                          "first_product_frac_of_bf16_peak":
+                              6 * flops_product / (b["kernels_us"]["product_full"] * 1e-6) / 1e12
+                              / PEAK_BF16_MFMA}
     if "fp64" in res:
         f = res["fp64"]
         line["fp64"] = {"steps_per_s": f["steps_per_s"], "ms_per_step": f["ms_per_step"],
