@@ -136,10 +136,13 @@ __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
   const bool has_x = p.beta != T(0);
   const bool scaled = p.scale != nullptr;
   const double sc = scaled ? *p.scale : 1.0;
+  T xr[V], xi[V];   // X loaded before any store (see epi_load_x)
+#pragma unroll
+  for (int v = 0; v < V; ++v) epi_load_x(p, has_x, o + v, xr[v], xi[v]);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     T vr, vi;
-    epi_value(p, has_x, scaled, sc, o + v, sr[v], si[v], vr, vi);
+    epi_combine(p, has_x, scaled, sc, sr[v], si[v], xr[v], xi[v], vr, vi);
     if (!p.fold_d) {
       p.c_re[o + v] = vr;
       p.c_im[o + v] = vi;

@@ -232,14 +232,20 @@ __global__ __launch_bounds__(kThreads3) void cgemm_bf16x3_kernel(CgemmArgs<float
   }
   const bool has_x = p.beta != 0.0f;
   const int64_t col = int64_t(bj) * BM + wn * 32 + li;
+  float xr[16], xi[16];   // X loaded before any store (see epi_load_x)
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = int64_t(bi) * BM + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+    epi_load_x(p, has_x, row * ld + col, xr[r], xi[r]);
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int64_t row = int64_t(bi) * BM + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
     const int64_t o = row * ld + col;
     float vr = p.alpha * cr[r], vi = p.alpha * ci[r];
     if (has_x) {
-      vr += p.beta * p.x_re[o];
-      vi += p.beta * p.x_im[o];
+      vr += p.beta * xr[r];
+      vi += p.beta * xi[r];
     }
     p.c_re[o] = vr;
     p.c_im[o] = vi;
@@ -389,6 +395,14 @@ __global__ __launch_bounds__(kThreads3, 2) void cgemm_bf16x3_wide_kernel(CgemmAr
   const bool scaled = p.scale != nullptr;
   const double sc = p.scale ? *p.scale : 1.0;
   const int64_t col = int64_t(bj) * BB + wn * 32 + li;
+  float xr[2][16], xi[2][16];   // X loaded before any store (see epi_load_x)
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = int64_t(bi) * BA + wm * 64 + b * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      epi_load_x(p, has_x, row * ld + col, xr[b][r], xi[b][r]);
+    }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
 #pragma unroll
@@ -396,7 +410,7 @@ __global__ __launch_bounds__(kThreads3, 2) void cgemm_bf16x3_wide_kernel(CgemmAr
       const int64_t row = int64_t(bi) * BA + wm * 64 + b * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
       const int64_t o = row * ld + col;
       float vr, vi;
-      epi_value(p, has_x, scaled, sc, o, cr[b][r], ci[b][r] - cin[b][r], vr, vi);
+      epi_combine(p, has_x, scaled, sc, cr[b][r], ci[b][r] - cin[b][r], xr[b][r], xi[b][r], vr, vi);
       p.c_re[o] = vr;
       p.c_im[o] = vi;
     }

@@ -130,6 +130,39 @@ __device__ __forceinline__ S opsum_b(S r, S i) { return (OPS & kConjB) ? r - i :
 
 // Value of one output element: alpha acc + beta X, or with a device scale
 // s (the previous step's renormalisation) s acc + s X formed in FP64.
+// The epilogues load a block's X elements before they store any of its
+// results: C may alias X as far as the compiler knows, so a load placed
+// after a store waits for it, and one load per element would cost one
+// memory round trip per element.
+template <typename T>
+__device__ __forceinline__ void epi_load_x(const CgemmArgs<T> &p, bool has_x, int64_t o, T &xr,
+                                           T &xi) {
+  xr = has_x ? p.x_re[o] : T(0);
+  xi = has_x ? p.x_im[o] : T(0);
+}
+
+// epi_value with the X element already loaded (the same arithmetic)
+template <typename T>
+__device__ __forceinline__ void epi_combine(const CgemmArgs<T> &p, bool has_x, bool scaled, double s,
+                                            T ar, T ai, T x_r, T x_i, T &vr, T &vi) {
+  if (scaled) {
+    double xr = s * double(ar), xi = s * double(ai);
+    if (has_x) {
+      xr += s * double(x_r);
+      xi += s * double(x_i);
+    }
+    vr = T(xr);
+    vi = T(xi);
+  } else {
+    vr = p.alpha * ar;
+    vi = p.alpha * ai;
+    if (has_x) {
+      vr += p.beta * x_r;
+      vi += p.beta * x_i;
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void epi_value(const CgemmArgs<T> &p, bool has_x, bool scaled, double s,
                                           int64_t o, T ar, T ai, T &vr, T &vi) {
@@ -230,7 +263,7 @@ constexpr int cgemm_f64_smem() { return cgemm_s_smem<double, BM, OPS>(); }
 // Writes a finished FP32 tile: the raw accumulator into a split partial, or
 // C = alpha * acc + beta * X, or the folded decoherence step (the operand LDS
 // is free after the k loop's last barrier).
-template <int BM, int OPS, bool FOLD, int F, int WM>
+template <int BM, int OPS, bool FOLD, int F, int WM, int XG = 8>
 __device__ __forceinline__ void f32_tile_epilogue(const CgemmArgs<float> &p, int bi, int bj,
                                                   float *smem, const floatx16 (&cr)[F][F],
                                                   const floatx16 (&ci)[F][F], float *part) {
@@ -280,19 +313,32 @@ __device__ __forceinline__ void f32_tile_epilogue(const CgemmArgs<float> &p, int
     for (int b = 0; b < F; ++b) {
       const int cl = wn * WM + b * 32 + li;
       const int64_t col = int64_t(bj) * BM + cl;
+      // X in groups of XG elements (XG registers a plane: the whole block's
+      // would cost the four-waves-per-SIMD occupancy)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int g = 0; g < 16; g += XG) {
+      float xr[XG], xi[XG];
+#pragma unroll
+      for (int e = 0; e < XG; ++e) {
+        const int r = g + e;
+        const int64_t row = int64_t(bi) * BM + wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        epi_load_x(p, has_x, row * ld + col, xr[e], xi[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < XG; ++e) {
+        const int r = g + e;
         const int rl = wm * WM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         const int64_t row = int64_t(bi) * BM + rl;
         const int64_t o = row * ld + col;
         float vr, vi;
-        epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
+        epi_combine(p, has_x, scaled, sc, cr[a][b][r], ci[a][b][r], xr[e], xi[e], vr, vi);
         if (fold) {
           fold_elem<float, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
         } else {
           p.c_re[o] = vr;
           p.c_im[o] = vi;
         }
+      }
       }
     }
   }
@@ -774,6 +820,17 @@ __device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int 
     }
     __syncthreads();
   }
+  T xr[F][F][4], xi[F][F][4];
+#pragma unroll
+  for (int a = 0; a < F; ++a)
+#pragma unroll
+    for (int b = 0; b < F; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = int64_t(bi) * BM + wm * WM + a * 16 + s_row<T>(h, r);
+        const int64_t col = int64_t(bj) * BM + wn * WM + b * 16 + li;
+        epi_load_x(p, has_x, row * ld + col, xr[a][b][r], xi[a][b][r]);
+      }
 #pragma unroll
   for (int a = 0; a < F; ++a) {
 #pragma unroll
@@ -786,7 +843,7 @@ __device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int 
         const int64_t row = int64_t(bi) * BM + rl;
         const int64_t o = row * ld + col;
         T vr, vi;
-        epi_value(p, has_x, scaled, sc, o, cr[a][b][r], ci[a][b][r], vr, vi);
+        epi_combine(p, has_x, scaled, sc, cr[a][b][r], ci[a][b][r], xr[a][b][r], xi[a][b][r], vr, vi);
         if (fold) {
           fold_elem<T, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
         } else {
