@@ -104,6 +104,7 @@ __device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, fl
   } else {
     DissArgs<float> da{in.z_re, in.z_im, in.x_re, in.x_im, in.ld, in.n, in.dt, in.d,
                        in.leak, in.pi, in.cg, in.n_gather, in.aux, in.aux, in.trw};
+    da.self_mask = in.sparse.self_mask;
     da.n_csr = in.sparse.n_csr;
     da.csr_ptr = in.sparse.csr_ptr;
     da.csr_col = in.sparse.csr_col;

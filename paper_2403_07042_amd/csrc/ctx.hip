@@ -545,6 +545,16 @@ static qme_status finish_context(qme_ctx *c, int32_t precision, void *hip_stream
     HIP_OK(hipMalloc(&c->trw, sizeof(double) * n));
     HIP_OK(hipMemcpy(c->trw, trw.data(), sizeof(double) * n, hipMemcpyHostToDevice));
   }
+  // gather channels that map every state to itself (or out of the basis)
+  c->self_mask = 0;
+  for (int j = 0; j < c->jt.n_gather && j < 32; ++j) {
+    bool self = true;
+    for (int64_t u = 0; u < n && self; ++u) {
+      const int32_t w = c->jt.pi[size_t(j) * n + u];
+      self = w < 0 || w == u;
+    }
+    if (self) c->self_mask |= 1u << j;
+  }
   const size_t ng = size_t(std::max(1, c->jt.n_gather)) * n;
   HIP_OK(hipMalloc(&c->pi, sizeof(int32_t) * ng));
   HIP_OK(hipMalloc(&c->cg, sizeof(double) * ng));

@@ -56,6 +56,7 @@ struct qme_ctx {
   // the decoherence and trace passes' arguments for these tables
   template <typename T>
   void sparse_args(qme::DissArgs<T> &a) const {
+    a.self_mask = self_mask;
     a.n_csr = jt.n_csr;
     a.csr_ptr = csr_ptr;
     a.csr_col = csr_col;
@@ -71,6 +72,7 @@ struct qme_ctx {
   }
   // adjoint tables (owned)
   int32_t *tau = nullptr;     // [n_gather x n]
+  uint32_t self_mask = 0;     // DissArgs::self_mask of the gather channels
   double *ca = nullptr;
   int32_t *upi = nullptr;     // [n_arrival x n]
   double *uc = nullptr;

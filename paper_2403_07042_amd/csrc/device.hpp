@@ -200,6 +200,9 @@ struct DissArgs {
   // by many blocks at once, so the two pairs differ and alternate by step.
   int slot_in = 0, slot_out = 0;
   int fuse_trace = 0;
+  // bit j: gather channel j maps every state to itself or out of the basis
+  // (dephasing), so its term reads the element itself and needs no load
+  uint32_t self_mask = 0;
 };
 // the scalar indices of the sink and the step count in slot pair `slot`
 __host__ __device__ constexpr int sink_slot(int slot) { return slot ? 5 : 0; }

@@ -161,14 +161,19 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, doub
   const int64_t v0 = int64_t(bj) * TD + c0;
   const bool staged = p.n_gather > 0 && p.n_gather <= kGatherChunk;
   if (staged) {
+    // every load unconditional (indices clamped into the table, the value
+    // replaced after), so a thread's four loads are in flight together
     for (int e = tid; e < p.n_gather * TD; e += kDissThreads) {
       const int j = e / TD, i = e - (e / TD) * TD;
       const int64_t a = int64_t(bi) * TD + i, b = int64_t(bj) * TD + i;
       const int64_t base = int64_t(j) * n;
-      g->pu[j][i] = a < n ? p.pi[base + a] : -1;
-      g->cu[j][i] = a < n ? p.cg[base + a] : 0.0;
-      g->pv[j][i] = b < n ? p.pi[base + b] : -1;
-      g->cv[j][i] = b < n ? p.cg[base + b] : 0.0;
+      const int64_t ac = a < n ? a : n - 1, bc = b < n ? b : n - 1;
+      const int32_t pa = p.pi[base + ac], pb = p.pi[base + bc];
+      const double ca = p.cg[base + ac], cb = p.cg[base + bc];
+      g->pu[j][i] = a < n ? pa : -1;
+      g->cu[j][i] = a < n ? ca : 0.0;
+      g->pv[j][i] = b < n ? pb : -1;
+      g->cv[j][i] = b < n ? cb : 0.0;
     }
     __syncthreads();
   }
@@ -211,30 +216,42 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, doub
     for (int j0 = 0; j0 < p.n_gather; j0 += B) {
       T gr[B][4], gi[B][4];
       bool use[B][4];
+      // the gathered elements: every load unconditional (an element not
+      // needed reads Z[0][0]) and the values chosen after, so the 2 B x 4
+      // loads of a thread are in flight together instead of one round trip
+      // each behind the branches
+      bool self[B][4], low[B][4];
 #pragma unroll
       for (int jb = 0; jb < B; ++jb) {
         const bool ch = j0 + jb < p.n_gather;
+        // (a channel that maps every state to itself reads nothing)
+        const bool moves = ch && !((p.self_mask >> (j0 + jb)) & 1u);
         const int32_t pu = ch && row_ok ? g->pu[j0 + jb][r] : -1;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int32_t pv = ch && ok[i] ? g->pv[j0 + jb][c0 + i] : -1;
           use[jb][i] = pu >= 0 && pv >= 0;
+          self[jb][i] = pu == u && pv == v0 + i;          // the element itself
+          // element (pu, pv) of the Hermitian Z from its lower triangle
+          low[jb][i] = pu >= pv;
+          const int64_t o = !use[jb][i] || self[jb][i] ? 0
+                            : low[jb][i]               ? int64_t(pu) * ld + pv
+                                                       : int64_t(pv) * ld + pu;
           gr[jb][i] = gi[jb][i] = T(0);
-          if (use[jb][i]) {
-            if (pu == u && pv == v0 + i) {        // the element itself
-              gr[jb][i] = zr[i];
-              gi[jb][i] = zi[i];
-            } else {
-              // element (pu, pv) of the Hermitian Z from its lower triangle
-              const bool low = pu >= pv;
-              const int64_t o = low ? int64_t(pu) * ld + pv : int64_t(pv) * ld + pu;
-              gr[jb][i] = p.z_re[o];
-              const T im = p.z_im[o];
-              gi[jb][i] = low ? im : -im;
-            }
+          if (moves) {
+            gr[jb][i] = p.z_re[o];
+            gi[jb][i] = p.z_im[o];
           }
         }
       }
+#pragma unroll
+      for (int jb = 0; jb < B; ++jb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const T re = gr[jb][i], im = gi[jb][i];
+          gr[jb][i] = !use[jb][i] ? T(0) : self[jb][i] ? zr[i] : re;
+          gi[jb][i] = !use[jb][i] ? T(0) : self[jb][i] ? zi[i] : low[jb][i] ? im : -im;
+        }
 #pragma unroll
       for (int jb = 0; jb < B; ++jb) {
         if (j0 + jb >= p.n_gather) break;
