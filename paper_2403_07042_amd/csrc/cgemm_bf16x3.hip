@@ -14,6 +14,7 @@
 // Used for both products of a time step, in the same NT forms as the FP32
 // kernel (A rows and M rows stream contiguous k; see cgemm.hip).
 #include "cgemm_tile.hpp"
+#include "dissipate_tile.hpp"   // trace_body: the folded steps' trace in the first product
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -283,12 +284,27 @@ __device__ __forceinline__ void wide_coords(int t, int tr, int tc, int &bi, int 
 // CU, so a grid of twice the compute units runs in one round).  Per element
 // the k order, the six products and the three accumulators are those of
 // cgemm_bf16x3_kernel, and the epilogue is the FP32 tiles', so the two give
-// bitwise-identical results.
+// bitwise-identical results.  With CgemmArgs::tr_aux (folded steps) every
+// block first forms the previous step's trace as the trace pass does (block 0
+// stores the scalars) and applies its factor as alpha = beta.
 __global__ __launch_bounds__(kThreads3, 2) void cgemm_bf16x3_wide_kernel(CgemmArgs<float> p) {
   constexpr int BA = 128, BB = 64, KT = 32, LDK = KT;
   auto slot = [](int row, int c) { return 8 * (c ^ dma_swz(row)); };
   __shared__ __align__(16) __bf16 sA[6][BA * LDK];
   __shared__ __align__(16) __bf16 sB[6][BB * LDK];
+  __shared__ double s_tr[3][kThreads3 / 64];
+  bool scaled = p.scale != nullptr;
+  double sc = 1.0;
+  if (p.tr_aux) {
+    DissArgs<float> da{nullptr, nullptr, nullptr, nullptr, p.ld, p.tr_n, p.tr_dt, nullptr,
+                       p.tr_leak, nullptr, nullptr, 0, p.tr_aux, p.tr_aux, p.tr_w, p.tr_zdiag};
+    da.slot_in = p.tr_slot_in;
+    da.slot_out = p.tr_slot_out;
+    sc = trace_body<float, kThreads3>(da, s_tr[0], s_tr[1], s_tr[2], blockIdx.x == 0);
+    scaled = true;
+  } else if (p.scale) {
+    sc = *p.scale;
+  }
 
   const int64_t ld = p.ld;
   int bi, bj;
@@ -392,8 +408,6 @@ __global__ __launch_bounds__(kThreads3, 2) void cgemm_bf16x3_wide_kernel(CgemmAr
   }
 
   const bool has_x = p.beta != 0.0f;
-  const bool scaled = p.scale != nullptr;
-  const double sc = p.scale ? *p.scale : 1.0;
   const int64_t col = int64_t(bj) * BB + wn * 32 + li;
   float xr[2][16], xi[2][16];   // X loaded before any store (see epi_load_x)
 #pragma unroll
@@ -437,14 +451,16 @@ hipError_t launch_cgemm_bf16x3(const CgemmArgs<float> &a, const GemmOps &o, hipS
   if (o.wide) {
     // 128 x 64 tiles: the step's first product only, unsplit, unfolded
     if (a.ld % 128 != 0 || !a.a_split || o.lower || o.conj_a || !o.conj_b || a.split > 1 ||
-        a.fold_d || a.tr_aux || a.scale_set)
+        a.fold_d || a.scale_set || (a.tr_aux && a.scale))
       return hipErrorInvalidValue;
     const int blocks = int((a.ld / 128) * (a.ld / 64));
     if (blocks == 0) return hipSuccess;
     return launch_kernel(cgemm_bf16x3_wide_kernel, dim3(blocks), dim3(kThreads3), 0, s, a);
   }
-  // the folded epilogue exists for the step's lower-triangle product only
+  // the folded epilogue exists for the step's lower-triangle product only,
+  // the trace prologue for the 128 x 64 first product only
   if (a.fold_d && !(o.lower && a.m_split)) return hipErrorInvalidValue;
+  if (a.tr_aux) return hipErrorInvalidValue;
   if (a.a_split && a.m_split) return hipErrorInvalidValue;
   if (a.a_split || a.m_split) {
     // the two forward products of a step: T = rho + dU rho^H-form (dU

@@ -333,8 +333,8 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   T *area = split_area_of<T>(c, ws);
   const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
   const double dt = c->model.dt;
-  // FP32 first products in 64- or 128-tiles without a split form the
-  // previous step's trace themselves (every block sums the stored diagonal,
+  // FP32 first products in 64- or 128-tiles and BF16x3 ones in 128 x 64
+  // tiles, without a split, form the previous step's trace themselves (every block sums the stored diagonal,
   // block 0 stores the scalars), so the trace pass runs once per call, after
   // the last step; the sink and step count alternate between the scalar
   // pairs by step parity (as for the unfolded steps)
@@ -344,6 +344,12 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
       CgemmArgs<T> probe{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
       plan_product<T>(c, probe, c->tile1, false, area, nullptr, 0);
       fused_tr = probe.split <= 1;
+    }
+    // (and BF16x3 first products on 128 x 64 tiles)
+    if (c->precision == QME_BF16X3) {
+      CgemmArgs<T> probe{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};
+      plan_product<T>(c, probe, plan_tile1(c), false, area, nullptr, 0);
+      fused_tr = wide_first(c, probe);
     }
   }
   for (int64_t k = 0; k < n_steps; ++k) {
