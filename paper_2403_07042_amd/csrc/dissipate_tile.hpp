@@ -65,25 +65,40 @@ __device__ __forceinline__ double trace_body(const DissArgs<T> &p, double *s_tr,
     tr -= p.dt * x;
   }
   // u = tid + k NT in increasing k; the loads of G values of k are
-  // issued together (one batch at N = 2048), the sums keep that order
+  // issued together (one batch at N = 2048), the sums keep that order.
+  // Every load is unconditional (an index past n reads entry 0 and its
+  // value is replaced by 0 after), so no branch makes a load wait.
   constexpr int G = 8;
-  for (int64_t u0 = tid; u0 < p.n; u0 += int64_t(G) * NT) {
-    double z[G], wk[G], lk[G];
+  auto sums = [&](auto diag) {
+    for (int64_t u0 = tid; u0 < p.n; u0 += int64_t(G) * NT) {
+      double z[G], wk[G], lk[G];
 #pragma unroll
-    for (int gi = 0; gi < G; ++gi) {
-      const int64_t u = u0 + int64_t(gi) * NT;
-      const bool ok = u < p.n;
-      z[gi] = !ok ? 0.0 : p.zdiag ? p.zdiag[u] : double(p.z_re[u * p.ld + u]);
-      wk[gi] = ok ? p.trw[u] : 0.0;
-      lk[gi] = ok ? p.leak[u] : 0.0;
-    }
+      for (int gi = 0; gi < G; ++gi) {
+        const int64_t u = u0 + int64_t(gi) * NT;
+        const int64_t uc = u < p.n ? u : 0;
+        z[gi] = diag(uc);
+        wk[gi] = p.trw[uc];
+        lk[gi] = p.leak[uc];
+      }
 #pragma unroll
-    for (int gi = 0; gi < G; ++gi) {
-      tr += wk[gi] * z[gi];
-      lost += lk[gi] * z[gi];
-      rot += z[gi];
+      for (int gi = 0; gi < G; ++gi) {
+        const bool ok = u0 + int64_t(gi) * NT < p.n;
+        z[gi] = ok ? z[gi] : 0.0;
+        wk[gi] = ok ? wk[gi] : 0.0;
+        lk[gi] = ok ? lk[gi] : 0.0;
+      }
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        tr += wk[gi] * z[gi];
+        lost += lk[gi] * z[gi];
+        rot += z[gi];
+      }
     }
-  }
+  };
+  if (p.zdiag)
+    sums([&](int64_t u) { return p.zdiag[u]; });
+  else
+    sums([&](int64_t u) { return double(p.z_re[u * p.ld + u]); });
   // wave sums by butterfly (every lane ends with the same value), then the
   // NT / 64 wave sums in wave order
   for (int off = 32; off > 0; off >>= 1) {
