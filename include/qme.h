@@ -568,9 +568,12 @@ qme_status qme_set_fold(qme_ctx *ctx, int32_t enable);
  * the operand tiles from HBM straight into LDS (no register staging), 0
  * stages them through registers, -1 (default) takes the direct body for
  * launches with fewer than two blocks per compute unit, where the few
- * resident workgroups cannot hide the load latency by their number.  The two
- * bodies accumulate every output in the same order: results are bitwise
- * identical.  Other values: QME_E_ARG. */
+ * resident workgroups cannot hide the load latency by their number.  With a
+ * mode other than 0, 32-tile products of a state with ld <= 192 load every K
+ * tile of their row panels into LDS at once and are not split along k (mode
+ * 0: staged per K tile, split as qme_set_split says).  The bodies accumulate
+ * every output in the same order: results are bitwise identical (with the
+ * split off).  Other values: QME_E_ARG. */
 qme_status qme_set_direct_loads(qme_ctx *ctx, int32_t mode);
 
 /* Graph replay of qme_step (off by default): with enable = 1, a call of

@@ -87,6 +87,16 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
   }
 }
 
+// FP32 32-tiles of products with ld <= kPanelLd (never split): the whole
+// row panels in LDS at once (cgemm_s_panel), one workgroup per CU.
+template <int OPS, bool LOWER>
+__global__ __launch_bounds__(kThreads) void cgemm_f32_panel_kernel(CgemmArgs<float> p) {
+  __shared__ __align__(16) float smem[cgemm_panel_smem()];
+  int bi, bj;
+  tile_coords(blockIdx.x, int(p.ld / 32), LOWER, bi, bj);
+  cgemm_s_panel<OPS, LOWER>(p, bi, bj, smem);
+}
+
 template <int BM, int OPS, bool LOWER>
 // five waves per SIMD for the 32-tile NT forms (the step's products); the
 // forms reading B by rows need more registers and keep the default bound
@@ -327,6 +337,21 @@ constexpr bool f64_folds() {
   return 2 * BM * (BM + 1) + 2 * BM <= cgemm_f64_smem<BM, kConjB>();
 }
 
+static hipError_t cgemm_f32_panel_dispatch(const CgemmArgs<float> &a, int ops, bool lower,
+                                           hipStream_t s) {
+  switch (ops * 2 + (lower ? 1 : 0)) {
+    case 0: return launch(cgemm_f32_panel_kernel<0, false>, a, 32, false, s);
+    case 1: return launch(cgemm_f32_panel_kernel<0, true>, a, 32, true, s);
+    case 2: return launch(cgemm_f32_panel_kernel<1, false>, a, 32, false, s);
+    case 3: return launch(cgemm_f32_panel_kernel<1, true>, a, 32, true, s);
+    case 4: return launch(cgemm_f32_panel_kernel<2, false>, a, 32, false, s);
+    case 5: return launch(cgemm_f32_panel_kernel<2, true>, a, 32, true, s);
+    case 6: return launch(cgemm_f32_panel_kernel<3, false>, a, 32, false, s);
+    case 7: return launch(cgemm_f32_panel_kernel<3, true>, a, 32, true, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &args, int tile, const GemmOps &o, hipStream_t s) {
   if (args.ld % tile != 0) return hipErrorInvalidValue;
   // the trace inside the product: full 64- / 128-tile launches without a split
@@ -351,7 +376,13 @@ hipError_t launch_cgemm_f32(const CgemmArgs<float> &args, int tile, const GemmOp
   if (tile == 64)
     return direct ? cgemm_f32_direct_dispatch<64>(a, ops_of(o), o.lower, s)
                   : cgemm_f32_kernel_dispatch<64>(a, ops_of(o), o.lower, s);
-  if (tile == 32) return cgemm_f32_kernel_dispatch<32>(a, ops_of(o), o.lower, s);
+  if (tile == 32) {
+    // small products: whole panels straight into LDS, unless register
+    // staging is asked for (GemmOps::direct == 0)
+    if (a.ld <= kPanelLd && !o.b_rows && a.split <= 1 && o.direct != 0)
+      return cgemm_f32_panel_dispatch(a, ops_of(o), o.lower, s);
+    return cgemm_f32_kernel_dispatch<32>(a, ops_of(o), o.lower, s);
+  }
   return hipErrorInvalidValue;
 }
 

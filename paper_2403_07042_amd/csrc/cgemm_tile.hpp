@@ -642,6 +642,87 @@ __device__ __forceinline__ int s_row(int h, int r) {
   return sizeof(T) == 8 ? h + 4 * r : 4 * h + r;
 }
 
+// Writes a finished 16x16-MFMA tile (the layout of cgemm_s_tile): the raw
+// accumulator into a split partial, or C = alpha * acc + beta * X, or the
+// folded decoherence step (FITS: the LDS at smem holds its staging).
+template <typename T, int BM, int OPS, bool FOLD, int F, int WM, bool FITS>
+__device__ __forceinline__ void s_tile_epilogue(const CgemmArgs<T> &p, int bi, int bj, T *smem,
+                                                const T __attribute__((ext_vector_type(4))) (&cr)[F][F],
+                                                const T __attribute__((ext_vector_type(4))) (&ci)[F][F],
+                                                T *part) {
+  const int64_t ld = p.ld;
+  const int tid = thread_index();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, h = lane >> 4;
+
+  if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
+#pragma unroll
+    for (int a = 0; a < F; ++a)
+#pragma unroll
+      for (int b = 0; b < F; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (wm * WM + a * 16 + s_row<T>(h, r)) * BM + wn * WM + b * 16 + li;
+          part[o] = cr[a][b][r];
+          part[BM * BM + o] = ci[a][b][r];
+        }
+    return;
+  }
+  const bool has_x = p.beta != T(0);
+  constexpr bool kCanFold = FOLD && FITS;
+  const bool fold = kCanFold && p.fold_d != nullptr;
+  T (*f_re)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
+  T (*f_im)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem + BM * (BM + 1));
+  double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
+  const bool scaled = p.scale != nullptr;
+  const double sc = scaled ? *p.scale : 1.0;
+  if (fold) {
+    if (tid < 2 * BM) {
+      const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
+      f_d[tid] = u < p.fold_n ? p.fold_d[u] : 0.0;
+    }
+    __syncthreads();
+  }
+  T xr[F][F][4], xi[F][F][4];
+#pragma unroll
+  for (int a = 0; a < F; ++a)
+#pragma unroll
+    for (int b = 0; b < F; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = int64_t(bi) * BM + wm * WM + a * 16 + s_row<T>(h, r);
+        const int64_t col = int64_t(bj) * BM + wn * WM + b * 16 + li;
+        epi_load_x(p, has_x, row * ld + col, xr[a][b][r], xi[a][b][r]);
+      }
+#pragma unroll
+  for (int a = 0; a < F; ++a) {
+#pragma unroll
+    for (int b = 0; b < F; ++b) {
+      const int cl = wn * WM + b * 16 + li;
+      const int64_t col = int64_t(bj) * BM + cl;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wm * WM + a * 16 + s_row<T>(h, r);
+        const int64_t row = int64_t(bi) * BM + rl;
+        const int64_t o = row * ld + col;
+        T vr, vi;
+        epi_combine(p, has_x, scaled, sc, cr[a][b][r], ci[a][b][r], xr[a][b][r], xi[a][b][r], vr, vi);
+        if (fold) {
+          fold_elem<T, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
+        } else {
+          p.c_re[o] = vr;
+          p.c_im[o] = vi;
+        }
+      }
+    }
+  }
+  if (fold) {
+    __syncthreads();
+    fold_mirror<T, BM>(p, bi, bj, f_re, f_im);
+  }
+}
+
 template <typename T, int BM, int OPS, bool FOLD = false>
 __device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int bj, T *smem,
                                              int kb = 0, int ke = -1, T *part = nullptr) {
@@ -790,73 +871,118 @@ __device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int 
   for (int a = 0; a < F; ++a)
 #pragma unroll
     for (int b = 0; b < F; ++b) combine3<OPS>(p1[a][b], p2[a][b], p3[a][b], cr[a][b], ci[a][b]);
+  s_tile_epilogue<T, BM, OPS, FOLD, F, WM,
+                  2 * BM * (BM + 1) + 2 * BM * int(sizeof(double) / sizeof(T)) <=
+                      cgemm_s_smem<T, BM, OPS>()>(p, bi, bj, smem, cr, ci, part);
+}
 
-  if (part) {   // k-chunk of a split tile: raw accumulator, tile-local row-major
-#pragma unroll
-    for (int a = 0; a < F; ++a)
-#pragma unroll
-      for (int b = 0; b < F; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int o = (wm * WM + a * 16 + s_row<T>(h, r)) * BM + wn * WM + b * 16 + li;
-          part[o] = cr[a][b][r];
-          part[BM * BM + o] = ci[a][b][r];
-        }
-    return;
-  }
-  const bool has_x = p.beta != T(0);
-  constexpr bool kCanFold =
-      FOLD && 2 * BM * (BM + 1) + 2 * BM * int(sizeof(double) / sizeof(T)) <= cgemm_s_smem<T, BM, OPS>();
-  const bool fold = kCanFold && p.fold_d != nullptr;
-  T (*f_re)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
-  T (*f_im)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem + BM * (BM + 1));
-  double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
-  const bool scaled = p.scale != nullptr;
-  const double sc = scaled ? *p.scale : 1.0;
-  if (fold) {
-    if (tid < 2 * BM) {
-      const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
-      f_d[tid] = u < p.fold_n ? p.fold_d[u] : 0.0;
+// FP32 32-tiles of small products (ld <= kPanelLd): the tile's whole row
+// panels of A and M, every K tile, go straight into LDS at once
+// (global_load_lds_dwordx4, each wave instruction one contiguous 1 KB, lane L
+// at 16 L; the chunks placed as cgemm_s_tile places them), so the block waits
+// for memory once instead of once per K tile; the K tiles are then
+// multiplied with cgemm_s_tile's fragments and MFMA order and the tile
+// written by its epilogue, so the results are bitwise those of cgemm_s_tile
+// without a split.
+constexpr int cgemm_panel_smem() { return 4 * 32 * kPanelLd; }   // floats (96 KB)
+
+template <int OPS, bool FOLD>
+__device__ __forceinline__ void cgemm_s_panel(const CgemmArgs<float> &p, int bi, int bj,
+                                              float *smem) {
+  static_assert(!(OPS & kBRow), "whole-panel loads serve the NT forms");
+  using T = float;
+  constexpr int BM = 32, E = 4, KT = 32, LDK = KT, WM = 16, F = 1;
+  constexpr int PLANE = BM * LDK;       // floats of one operand plane of one K tile
+  constexpr int STAGE = 4 * PLANE;      // A re, A im, M re, M im
+  typedef T vec __attribute__((ext_vector_type(E)));
+  typedef T acc4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) void gvoid;
+  typedef __attribute__((address_space(3))) void lvoid;
+
+  const int64_t ld = p.ld;
+  const int nk = int(ld / KT);
+  const int tid = thread_index();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, h = lane >> 4;
+  {
+    // wave w fills rows 8w .. 8w + 7 of every plane and K tile: lane L at
+    // row 8w + L / 8, slot L % 8, which holds chunk (L % 8) ^ f64_swz(row)
+    const int row = 8 * wave + (lane >> 3);
+    const int chunk = (lane & 7) ^ f64_swz(row);
+    const int64_t ga = (int64_t(bi) * BM + row) * ld + E * chunk;
+    const int64_t gb = (int64_t(bj) * BM + row) * ld + E * chunk;
+    for (int kt = 0; kt < nk; ++kt) {
+      float *base = smem + kt * STAGE + 8 * wave * LDK;
+      const int64_t k0 = int64_t(kt) * KT;
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.a_re + ga + k0), (lvoid *)(base), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.a_im + ga + k0), (lvoid *)(base + PLANE), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.m_re + gb + k0), (lvoid *)(base + 2 * PLANE), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(p.m_im + gb + k0), (lvoid *)(base + 3 * PLANE), 16, 0, 0);
     }
-    __syncthreads();
   }
-  T xr[F][F][4], xi[F][F][4];
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  acc4 p1[F][F], p2[F][F], p3[F][F];
 #pragma unroll
   for (int a = 0; a < F; ++a)
 #pragma unroll
     for (int b = 0; b < F; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = int64_t(bi) * BM + wm * WM + a * 16 + s_row<T>(h, r);
-        const int64_t col = int64_t(bj) * BM + wn * WM + b * 16 + li;
-        epi_load_x(p, has_x, row * ld + col, xr[a][b][r], xi[a][b][r]);
-      }
+      for (int r = 0; r < 4; ++r) { p1[a][b][r] = T(0); p2[a][b][r] = T(0); p3[a][b][r] = T(0); }
+  auto mfma = [](T x, T y, acc4 acc) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc, 0, 0, 0); };
+
+  for (int kt = 0; kt < nk; ++kt) {
+    const T *sa_re = smem + kt * STAGE, *sa_im = sa_re + PLANE;
+    const T *sb_re = sa_re + 2 * PLANE, *sb_im = sa_re + 3 * PLANE;
 #pragma unroll
-  for (int a = 0; a < F; ++a) {
+    for (int hf = 0; hf < 2; ++hf) {
+      T ar[F][E], ai[F][E], br[F][E], bi_[F][E];
 #pragma unroll
-    for (int b = 0; b < F; ++b) {
-      const int cl = wn * WM + b * 16 + li;
-      const int64_t col = int64_t(bj) * BM + cl;
+      for (int f = 0; f < F; ++f) {
+        const int ra_ = wm * WM + f * 16 + li;
+        const int oa = ra_ * LDK + E * ((2 * h + hf) ^ f64_swz(ra_));
+        const vec x = *reinterpret_cast<const vec *>(&sa_re[oa]);
+        const vec y = *reinterpret_cast<const vec *>(&sa_im[oa]);
+        const int rb_ = wn * WM + f * 16 + li;
+        const int om = rb_ * LDK + E * ((2 * h + hf) ^ f64_swz(rb_));
+        const vec z = *reinterpret_cast<const vec *>(&sb_re[om]);
+        const vec w = *reinterpret_cast<const vec *>(&sb_im[om]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rl = wm * WM + a * 16 + s_row<T>(h, r);
-        const int64_t row = int64_t(bi) * BM + rl;
-        const int64_t o = row * ld + col;
-        T vr, vi;
-        epi_combine(p, has_x, scaled, sc, cr[a][b][r], ci[a][b][r], xr[a][b][r], xi[a][b][r], vr, vi);
-        if (fold) {
-          fold_elem<T, BM>(p, bi, bj, rl, cl, vr, vi, f_d[rl], f_d[BM + cl], f_re, f_im);
-        } else {
-          p.c_re[o] = vr;
-          p.c_im[o] = vi;
+        for (int e = 0; e < E; ++e) {
+          ar[f][e] = x[e];
+          ai[f][e] = y[e];
+          br[f][e] = z[e];
+          bi_[f][e] = w[e];
         }
       }
+      T as_[F][E], bs_[F][E];
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          as_[f][e] = opsum_a<OPS>(ar[f][e], ai[f][e]);
+          bs_[f][e] = opsum_b<OPS>(br[f][e], bi_[f][e]);
+        }
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+          for (int b = 0; b < F; ++b)
+            cmac3(p1[a][b], p2[a][b], p3[a][b], ar[a][e], ai[a][e], as_[a][e], br[b][e], bi_[b][e],
+                  bs_[b][e], mfma);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if (fold) {
-    __syncthreads();
-    fold_mirror<T, BM>(p, bi, bj, f_re, f_im);
-  }
+  __syncthreads();   // the panels are read before the epilogue may stage the fold there
+  acc4 cr[F][F], ci[F][F];
+#pragma unroll
+  for (int a = 0; a < F; ++a)
+#pragma unroll
+    for (int b = 0; b < F; ++b) combine3<OPS>(p1[a][b], p2[a][b], p3[a][b], cr[a][b], ci[a][b]);
+  s_tile_epilogue<T, BM, OPS, FOLD, F, WM, true>(p, bi, bj, smem, cr, ci, nullptr);
 }
 
 template <int BM, int OPS, bool FOLD = false>

@@ -197,6 +197,9 @@ template <typename T>
 static void plan_product(const qme_ctx *c, CgemmArgs<T> &g, int tile, bool lower, T *area,
                          T *tail_part, size_t tail_cap) {
   if (!c->tail_split) return;
+  // FP32 32-tile products this small load whole panels instead (cgemm_s_panel)
+  // unless register staging is asked for
+  if (c->precision == QME_FP32 && tile == 32 && c->ld <= kPanelLd && c->direct != 0) return;
   const int t = int(c->ld / tile);
   const int blocks = lower ? t * (t + 1) / 2 : t * t;
   if (area && small_split_applies(c)) {

@@ -58,6 +58,14 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem,
 // direct body when the launch has fewer blocks than 2 per compute unit
 // (`cus`), i.e. when resident workgroups cannot hide load latency by their
 // number.  Both bodies give bitwise-identical results.
+// FP32 32-tile products with ld up to this size load each tile's whole row
+// panels into LDS at once (cgemm_s_panel) and are not split along k (unless
+// GemmOps::direct == 0 asks for register staging).
+// Measured on MI355X: faster at ld = 128 (N = 128 lattice 54.6k -> 64.8k
+// steps/s) and 192 (N = 144: 46.0k -> 48.8k), slower at 256 (51.5k -> 47.3k:
+// 128 KB of LDS leaves one workgroup per CU for the whole panel load).
+constexpr int kPanelLd = 192;
+
 struct GemmOps {
   bool conj_a = false, conj_b = false, b_rows = false, lower = false;
   int direct = 0, cus = 0;

@@ -44,6 +44,39 @@ def test_tile_bodies_bitwise_equal(length, tiles, fold, split):
     assert np.abs(out[0][0] - rho0).max() > 1e-6          # the state moved
 
 
+@pytest.mark.parametrize("make,fold", [
+    (lambda: W.photon_lattice(8, 8, gamma=0.05), True),    # N = 128: folded steps
+    (lambda: W.photon_lattice(8, 8, gamma=0.05), False),
+    (W.tch_2x2, False),                                    # N = 144, ld = 192, gather channels
+    (lambda: W.photon_lattice(12, 8, gamma=0.05), True),   # N = 192
+])
+def test_whole_panel_body_bitwise_equal(make, fold):
+    """FP32 32-tile products with ld <= 192 load every K tile of their row
+    panels into LDS at once (direct modes 1 and -1) or stage them K tile by
+    K tile (mode 0, split off): the same accumulation, bitwise."""
+    wl = dict(make(), init={"kind": "haar", "seed": 5})
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, "fp32")
+    sol.set_tiles(32, 32)
+    sol.set_fold(fold)
+    sol.set_split(False)
+    assert sol.ld <= 192
+    out = {}
+    for mode in (0, 1, -1):
+        print(f"whole panels N={sol.n} fold={fold} direct={mode}", flush=True)
+        sol.set_direct_loads(mode)
+        sol.set_rho(rho0, sink=0.0625)
+        sol.step(9)
+        sol.step(4)
+        out[mode] = sol.get_rho()
+    sol.close()
+    for mode in (1, -1):
+        assert np.array_equal(out[mode][0], out[0][0])
+        assert out[mode][1] == out[0][1]
+    assert np.abs(out[0][0] - rho0).max() > 1e-6
+
+
 def test_adjoint_bitwise_equal():
     wl = dict(W.photon_lattice(16, 16, gamma=0.05), init={"kind": "haar", "seed": 4})
     occ = P.basis(wl)

@@ -13,6 +13,7 @@ from workloads import hydrogen_bond as hb
 from oracle import evolve as ev
 from oracle import selection as sel
 from general_models import export_general
+from workloads.collective import general_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -143,3 +144,40 @@ def test_general_model_errors():
     with pytest.raises(L.QmeError) as e:
         P.Solver(out_of_range, "fp32")
     assert "QME_E_ARG" in str(e.value)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_self_and_mixed_gather_channels_against_oracle(precision):
+    """Monomial channels that map every state to itself or out of the basis
+    (which the decoherence pass marks and reads no element for) next to
+    channels that move some states and keep others: a self channel, a
+    partial self channel (half the states leave the basis), a permutation
+    swapping two pairs and fixing the rest, and the photon leaks, in an order
+    that puts self and moving channels into the same batch of loads; N = 144
+    (ragged tiles, the trace formed inside the decoherence pass), 40 steps
+    against the oracle."""
+    base = W.tch_2x2(steps=40)
+    h = P.hamiltonian_coo(base)
+    n = len(P.basis(base))
+    rng = np.random.default_rng(17)
+    states = list(range(n))
+    coef_self = [float(x) for x in rng.uniform(0.2, 1.0, n)]
+    swap = list(range(n))
+    for a, b in ((3, 70), (11, 140)):
+        swap[a], swap[b] = b, a
+    half_dst = [w if w % 2 == 0 else -1 for w in states]
+    leak = export_general(base, h)["jumps"]
+    jumps = [leak[0], (0.004, states, states, coef_self),
+             (0.003, states, swap, [1.0] * n), (0.002, states, half_dst, [1.0] * n)] + leak[1:]
+    wl = dict(general_workload(base, n, h, jumps, name="self_and_mixed_channels"),
+              init={"kind": "haar", "seed": 23})
+    rho0 = W.initial_rho(wl, np.arange(n))
+    ref, ref_sink = ev.evolve(ev.GeneralSystem(wl), rho0, 40)
+    sol = P.Solver(wl, precision)
+    sol.set_rho(rho0)
+    sol.step(15)
+    sol.step(25)
+    got, sink = sol.get_rho()
+    sol.close()
+    assert np.abs(got - ref).max() < TOL[precision]
+    assert abs(sink - ref_sink) < (1e-12 if precision == "fp64" else 1e-7)

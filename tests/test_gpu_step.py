@@ -579,6 +579,8 @@ def small_split_expected(ld, tile, precision, cus):
     (first product split, lower-triangle product split)."""
     if precision == "bf16x3":
         tile = 64                    # a split BF16x3 product runs on 64-tiles
+    if precision == "fp32" and tile == 32 and ld <= 192:
+        return False, False          # whole-panel products, never split
     t = ld // tile
     kt = 32 if precision == "bf16x3" or (precision == "fp32" and tile == 32) else 16
 
