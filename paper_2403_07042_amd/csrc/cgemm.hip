@@ -88,13 +88,24 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_kernel(CgemmArgs<float> p)
 }
 
 // FP32 32-tiles of products with ld <= kPanelLd (never split): the whole
-// row panels in LDS at once (cgemm_s_panel), one workgroup per CU.
+// row panels in LDS at once (cgemm_s_panel), one workgroup per CU.  With
+// tr_aux (folded steps) every block forms the previous step's trace while
+// its panel loads are in flight, as the 64-tile first products do.
 template <int OPS, bool LOWER>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_panel_kernel(CgemmArgs<float> p) {
   __shared__ __align__(16) float smem[cgemm_panel_smem()];
+  __shared__ double s_tr[3][kThreads / 64];
   int bi, bj;
   tile_coords(blockIdx.x, int(p.ld / 32), LOWER, bi, bj);
-  cgemm_s_panel<OPS, LOWER>(p, bi, bj, smem);
+  cgemm_s_panel<OPS, LOWER>(p, bi, bj, smem, [&](CgemmArgs<float> &q) {
+    if (LOWER || !q.tr_aux) return;
+    DissArgs<float> da{nullptr, nullptr, nullptr, nullptr, q.ld, q.tr_n, q.tr_dt, nullptr,
+                       q.tr_leak, nullptr, nullptr, 0, q.tr_aux, q.tr_aux, q.tr_w, q.tr_zdiag};
+    da.slot_in = q.tr_slot_in;
+    da.slot_out = q.tr_slot_out;
+    q.scale_value = trace_body<float, kThreads>(da, s_tr[0], s_tr[1], s_tr[2], blockIdx.x == 0);
+    q.scale_set = 1;
+  });
 }
 
 template <int BM, int OPS, bool LOWER>
@@ -355,7 +366,9 @@ static hipError_t cgemm_f32_panel_dispatch(const CgemmArgs<float> &a, int ops, b
 hipError_t launch_cgemm_f32(const CgemmArgs<float> &args, int tile, const GemmOps &o, hipStream_t s) {
   if (args.ld % tile != 0) return hipErrorInvalidValue;
   // the trace inside the product: full 64- / 128-tile launches without a split
-  if (args.tr_aux && (o.lower || tile == 32 || args.split > 1 || args.scale || args.scale_set))
+  // and whole-panel 32-tile ones
+  const bool panel = tile == 32 && args.ld <= kPanelLd && !o.b_rows && args.split <= 1 && o.direct != 0;
+  if (args.tr_aux && (o.lower || (tile == 32 && !panel) || args.split > 1 || args.scale || args.scale_set))
     return hipErrorInvalidValue;
   // progress-ranked wave priority for launches resident in one round (four
   // workgroups per CU at most; larger launches overlap their rounds anyway)
@@ -379,8 +392,7 @@ hipError_t launch_cgemm_f32(const CgemmArgs<float> &args, int tile, const GemmOp
   if (tile == 32) {
     // small products: whole panels straight into LDS, unless register
     // staging is asked for (GemmOps::direct == 0)
-    if (a.ld <= kPanelLd && !o.b_rows && a.split <= 1 && o.direct != 0)
-      return cgemm_f32_panel_dispatch(a, ops_of(o), o.lower, s);
+    if (panel) return cgemm_f32_panel_dispatch(a, ops_of(o), o.lower, s);
     return cgemm_f32_kernel_dispatch<32>(a, ops_of(o), o.lower, s);
   }
   return hipErrorInvalidValue;

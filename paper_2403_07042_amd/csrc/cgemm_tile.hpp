@@ -675,8 +675,8 @@ __device__ __forceinline__ void s_tile_epilogue(const CgemmArgs<T> &p, int bi, i
   T (*f_re)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
   T (*f_im)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem + BM * (BM + 1));
   double *f_d = reinterpret_cast<double *>(smem + 2 * BM * (BM + 1));
-  const bool scaled = p.scale != nullptr;
-  const double sc = scaled ? *p.scale : 1.0;
+  const bool scaled = p.scale != nullptr || p.scale_set;
+  const double sc = p.scale ? *p.scale : p.scale_set ? p.scale_value : 1.0;
   if (fold) {
     if (tid < 2 * BM) {
       const int64_t u = tid < BM ? int64_t(bi) * BM + tid : int64_t(bj) * BM + tid - BM;
@@ -883,12 +883,14 @@ __device__ __forceinline__ void cgemm_s_tile(const CgemmArgs<T> &p, int bi, int 
 // for memory once instead of once per K tile; the K tiles are then
 // multiplied with cgemm_s_tile's fragments and MFMA order and the tile
 // written by its epilogue, so the results are bitwise those of cgemm_s_tile
-// without a split.
+// without a split.  `pre(p)` runs while the loads are in flight (the folded
+// steps' trace; it may set the epilogue's factor in its copy of the args).
 constexpr int cgemm_panel_smem() { return 4 * 32 * kPanelLd; }   // floats (96 KB)
 
-template <int OPS, bool FOLD>
-__device__ __forceinline__ void cgemm_s_panel(const CgemmArgs<float> &p, int bi, int bj,
-                                              float *smem) {
+template <int OPS, bool FOLD, typename Pre>
+__device__ __forceinline__ void cgemm_s_panel(const CgemmArgs<float> &args, int bi, int bj,
+                                              float *smem, Pre pre) {
+  CgemmArgs<float> p = args;
   static_assert(!(OPS & kBRow), "whole-panel loads serve the NT forms");
   using T = float;
   constexpr int BM = 32, E = 4, KT = 32, LDK = KT, WM = 16, F = 1;
@@ -921,6 +923,7 @@ __device__ __forceinline__ void cgemm_s_panel(const CgemmArgs<float> &p, int bi,
       __builtin_amdgcn_global_load_lds((gvoid *)(p.m_im + gb + k0), (lvoid *)(base + 3 * PLANE), 16, 0, 0);
     }
   }
+  pre(p);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 

@@ -336,8 +336,9 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
   T *area = split_area_of<T>(c, ws);
   const T *u_re = static_cast<const T *>(c->du_re), *u_im = static_cast<const T *>(c->du_im);
   const double dt = c->model.dt;
-  // FP32 first products in 64- or 128-tiles and BF16x3 ones in 128 x 64
-  // tiles, without a split, form the previous step's trace themselves (every block sums the stored diagonal,
+  // FP32 first products in 64- or 128-tiles or whole 32-tile panels and
+  // BF16x3 ones in 128 x 64 tiles, without a split, form the previous step's
+  // trace themselves (every block sums the stored diagonal,
   // block 0 stores the scalars), so the trace pass runs once per call, after
   // the last step; the sink and step count alternate between the scalar
   // pairs by step parity (as for the unfolded steps)
@@ -348,6 +349,9 @@ static hipError_t fold_steps(qme_ctx *c, void *state, int64_t n_steps, void *ws,
       plan_product<T>(c, probe, c->tile1, false, area, nullptr, 0);
       fused_tr = probe.split <= 1;
     }
+    // (and FP32 32-tile first products that load whole panels)
+    if (c->precision == QME_FP32 && c->tile1 == 32 && c->ld <= kPanelLd && c->direct != 0)
+      fused_tr = true;
     // (and BF16x3 first products on 128 x 64 tiles)
     if (c->precision == QME_BF16X3) {
       CgemmArgs<T> probe{u_re, u_im, x_re, x_im, x_re, x_im, y_re, y_im, c->ld, T(1), T(1)};

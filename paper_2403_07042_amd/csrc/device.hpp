@@ -105,12 +105,13 @@ struct CgemmArgs {
   double fold_dt = 0.0;
   int64_t fold_n = 0;
   double *zdiag = nullptr;
-  // Folded steps (FP32 64- and 128-tile and BF16x3 128 x 64 first products,
-  // no split): the previous step's trace formed by every block of the first
-  // product with the trace pass's arithmetic (DissArgs: the stored diagonal of Z, trace
-  // and leak weights, the state's scalars, the scalar slot pairs read and
-  // written); block 0 stores the step's scalars, and the factor it gives is
-  // the product's alpha = beta (in place of `scale`).
+  // Folded steps (FP32 64- and 128-tile and whole-panel 32-tile, and BF16x3
+  // 128 x 64 first products, no split): the previous step's trace formed by
+  // every block of the first product with the trace pass's arithmetic
+  // (DissArgs: the stored diagonal of Z, trace and leak weights, the state's
+  // scalars, the scalar slot pairs read and written); block 0 stores the
+  // step's scalars, and the factor it gives is the product's alpha = beta
+  // (in place of `scale`).
   const double *tr_zdiag = nullptr, *tr_w = nullptr, *tr_leak = nullptr;
   double *tr_aux = nullptr;
   int64_t tr_n = 0;

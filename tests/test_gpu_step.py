@@ -38,14 +38,17 @@ def gpu_run(wl, precision, checkpoints):
 
 def folded_trace_fused(sol, precision):
     """Whether folded steps form the trace inside the next first product:
-    FP32 64- or 128-tile first products and BF16x3 128 x 64 ones, not cut
-    along k (a small-launch split applies below two tiles per compute unit;
-    a BF16x3 split takes the 64-tiles)."""
+    FP32 64- or 128-tile first products, FP32 32-tile ones that load whole
+    panels (ld <= 192) and BF16x3 128 x 64 ones, not cut along k (a
+    small-launch split applies below two tiles per compute unit; a BF16x3
+    split takes the 64-tiles)."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     if precision == "bf16x3":
         return sol.tile1 == 128 and 2 * (sol.ld // 64) ** 2 > cus
-    if precision != "fp32" or sol.tile1 == 32:
+    if precision != "fp32":
         return False
+    if sol.tile1 == 32:
+        return sol.ld <= 192         # whole-panel 32-tile products
     return 2 * (sol.ld // sol.tile1) ** 2 > cus
 
 
@@ -234,7 +237,19 @@ def test_folded_trace_in_first_product_scalars(precision, tiles):
     64-tile first products keep the trace pass.  Over any
     split of 7 steps into calls the step count is 7, the sink agrees with one
     call's to rounding and the trace is 1 - sink."""
-    wl = dict(W.photon_lattice(gamma=0.05), init={"kind": "haar", "seed": 11})
+    folded_trace_scalars(dict(W.photon_lattice(gamma=0.05), init={"kind": "haar", "seed": 11}),
+                         precision, tiles)
+
+
+def test_whole_panel_folded_trace_scalars():
+    """The same at N = 128 with FP32 32-tiles, whose first products load
+    whole panels and form the previous step's trace while the loads are in
+    flight."""
+    folded_trace_scalars(dict(W.photon_lattice(8, 8, gamma=0.05), init={"kind": "haar", "seed": 11}),
+                         "fp32", (32, 32))
+
+
+def folded_trace_scalars(wl, precision, tiles):
     rho0 = W.initial_rho(wl, P.basis(wl))
     ref = None
     for split in ([7], [1, 2, 4], [3, 3, 1], [2, 5], [1, 1, 1, 1, 1, 1, 1]):
@@ -250,9 +265,9 @@ def test_folded_trace_in_first_product_scalars(precision, tiles):
         rho, sink = sol.get_rho()
         _, trace, _ = sol.observe()
         aux = _scalars(sol)
+        fused = folded_trace_fused(sol, precision)
         sol.close()
         assert counts[0] == 7 and counts[1] == 7 and counts[3] == 0
-        fused = (precision == "fp32" and tiles[0] != 32) or (precision == "bf16x3" and tiles[0] == 128)
         assert counts[2] == (len(split) if fused else 7)
         assert aux[3] == 7.0 and aux[0] == sink and sink > 0.125
         assert abs(trace - (1.0 - sink)) < 1e-6
