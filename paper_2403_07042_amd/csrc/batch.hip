@@ -366,8 +366,21 @@ static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 static qme_status build_tables(qme_batch *b) {
   const int nb = b->count;
   b->sparse = false;
+  // The trace formed by every block of the decoherence phase saves the trace
+  // phase's launch but repeats an instance's diagonal sums in each of its
+  // blocks: kept while the phase is one round of blocks (up to four per CU),
+  // where the launch costs more (measured on the 256-instance sweep, 11840
+  // blocks: a separate trace phase 1135 -> 1176 batched steps/s).
   b->fuse = true;
-  for (qme_ctx *c : b->ctxs) b->fuse = b->fuse && fuse_trace_applies(c);
+  int64_t blocks3 = 0;
+  int cus = 0;
+  for (qme_ctx *c : b->ctxs) {
+    b->fuse = b->fuse && fuse_trace_applies(c);
+    const int64_t td = (c->n + TD - 1) / TD;
+    blocks3 += td * (td + 1) / 2;
+    cus = std::max(cus, c->cus);
+  }
+  if (blocks3 > 4 * int64_t(std::max(cus, 1))) b->fuse = false;
   std::vector<int32_t> ord(nb);
   std::iota(ord.begin(), ord.end(), 0);
   if (b->lpt)
