@@ -76,15 +76,37 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
   for (int a = 0; a < kMaxArrival; ++a) gacc[a] = 0.0;
   const double dv = v < n ? p.d[v] : 0.0;
 
-  for (int rr = r0; rr < TD; rr += kAdjThreads / TD) {
+  // rows rr = r0 + 4 k; the element loads of G rows are issued together
+  // (unconditionally, an element outside the tile reading entry 0) ahead of
+  // their rows' stores, which could alias them as far as the compiler knows
+  constexpr int RSTEP = kAdjThreads / TD;
+  constexpr int G = 4;
+  static_assert(TD % (G * RSTEP) == 0, "row groups tile the adjoint tile");
+  for (int rq = r0; rq < TD; rq += G * RSTEP) {
+   T g_lre[G], g_lim[G], g_zre[G], g_zim[G];
+   double g_du[G];
+#pragma unroll
+   for (int gq = 0; gq < G; ++gq) {
+     const int64_t u = int64_t(bi) * TD + rq + gq * RSTEP;
+     const bool valid = u < n && v < n && !(diag_tile && v > u);
+     const int64_t o = valid ? u * ld + v : 0;
+     g_lre[gq] = p.l_re[o];
+     g_lim[gq] = p.l_im[o];
+     g_zre[gq] = p.z_re[o];
+     g_zim[gq] = p.z_im[o];
+     g_du[gq] = p.d[valid ? u : 0];
+   }
+#pragma unroll
+   for (int gq = 0; gq < G; ++gq) {
+    const int rr = rq + gq * RSTEP;
     const int64_t u = int64_t(bi) * TD + rr;
     const bool valid = u < n && v < n && !(diag_tile && v > u);
     double e = 0.0;
     if (valid) {
       const int64_t o = u * ld + v;
-      const double lr = double(p.l_re[o]), li = double(p.l_im[o]);
+      const double lr = double(g_lre[gq]), li = double(g_lim[gq]);
       if (first) {
-        const double f = 1.0 - 0.5 * dt * (p.d[u] + dv);
+        const double f = 1.0 - 0.5 * dt * (g_du[gq] + dv);
         double mr = f * lr, mi = f * li;
         for (int j = 0; j < p.n_gather; ++j) {
           const int32_t tu = p.tau[int64_t(j) * n + u];
@@ -150,7 +172,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
           s_im[rr][c] = T(mi);
         }
         // e(u, v) = Re(Z[u,v] lam[v,u]) = Re(Z[u,v] conj(lam[u,v]))
-        const double zr = double(p.z_re[o]), zi = double(p.z_im[o]);
+        const double zr = double(g_zre[gq]), zi = double(g_zim[gq]);
         e = zr * lr + zi * li;
         if (u != v) colacc += e;
       }
@@ -171,6 +193,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_dissipate_kernel(AdjArgs<T> p
       const double rs = wave_sum(e);
       if (c == 0 && u < n) p.rowbuf[int64_t(bj) * n + u] = rs;
     }
+   }
   }
   if (first) {
     s_col[r0][c] = colacc;
@@ -283,9 +306,25 @@ __global__ void q_reduce_kernel(const double *rowbuf, const double *colbuf, int6
   const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (u >= n) return;
   const int tu = int(u / kAdjTile);
+  // the same sums in the same order, the loads of G terms issued together
+  constexpr int G = 8;
   double acc = 0.0;
-  for (int b = 0; b <= tu; ++b) acc += rowbuf[int64_t(b) * n + u];
-  for (int b = tu; b < tiles; ++b) acc += colbuf[int64_t(b) * n + u];
+  for (int b0 = 0; b0 <= tu; b0 += G) {
+    double x[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) x[g] = rowbuf[int64_t(b0 + g <= tu ? b0 + g : 0) * n + u];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (b0 + g <= tu) acc += x[g];
+  }
+  for (int b0 = tu; b0 < tiles; b0 += G) {
+    double x[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) x[g] = colbuf[int64_t(b0 + g < tiles ? b0 + g : 0) * n + u];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (b0 + g < tiles) acc += x[g];
+  }
   q[u] = acc;
 }
 
@@ -427,7 +466,7 @@ hipError_t launch_sparse_gamma_reduce(const double *part, int blocks, int n_csr,
 hipError_t launch_q_reduce(const double *rowbuf, const double *colbuf, int64_t n, double *q,
                            hipStream_t s) {
   const int tiles = int((n + kAdjTile - 1) / kAdjTile);
-  hipLaunchKernelGGL(q_reduce_kernel, dim3(int((n + 255) / 256)), dim3(256), 0, s, rowbuf,
+  hipLaunchKernelGGL(q_reduce_kernel, dim3(int((n + 63) / 64)), dim3(64), 0, s, rowbuf,
                      colbuf, n, tiles, q);
   return hipGetLastError();
 }
