@@ -135,7 +135,8 @@ __device__ __forceinline__ void batch_item(const BatchInstance &in, int tile, fl
                                                                    st + 2 * (kBatchThreads / 64),
                                                                    tile == 0)
                                 : in.aux[4];
-      dissipate_tile<float, SPARSE>(da, tile, scale, sr, si, reinterpret_cast<GatherLds *>(gp));
+      dissipate_tile<float, SPARSE>(da, tile, [scale]() { return scale; }, sr, si,
+                                    reinterpret_cast<GatherLds *>(gp));
     }
   }
 }

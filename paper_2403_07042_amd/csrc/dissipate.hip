@@ -29,21 +29,21 @@ __global__ __launch_bounds__(kTraceThreads) void trace_kernel(DissArgs<T> p) {
 }
 
 // FUSE: every block forms the trace sums itself (the same reduction as
-// trace_kernel, so the factor is bitwise the same) and block 0 stores the
-// step's scalars; otherwise the factor comes from the trace pass.
+// trace_kernel, so the factor is bitwise the same; its loads overlap the
+// tile's own) and block 0 stores the step's scalars; otherwise the factor
+// comes from the trace pass.
 template <typename T, bool SPARSE, bool FUSE>
 __global__ __launch_bounds__(kDissThreads) void dissipate_kernel(DissArgs<T> p) {
   __shared__ T s_re[TD][TD + 1];
   __shared__ T s_im[TD][TD + 1];
   __shared__ GatherLds g;
-  double scale;
-  if constexpr (FUSE) {
-    __shared__ double s_t[3][kDissThreads / 64];
-    scale = trace_body<T, kDissThreads>(p, s_t[0], s_t[1], s_t[2], blockIdx.x == 0);
-  } else {
-    scale = p.aux_out[4];
-  }
-  dissipate_tile<T, SPARSE>(p, blockIdx.x, scale, s_re, s_im, &g);
+  __shared__ double s_t[3][kDissThreads / 64];
+  dissipate_tile<T, SPARSE, FUSE>(p, blockIdx.x, [&]() {
+    if constexpr (FUSE)
+      return trace_body<T, kDissThreads>(p, s_t[0], s_t[1], s_t[2], blockIdx.x == 0);
+    else
+      return p.aux_out[4];
+  }, s_re, s_im, &g);
 }
 
 __global__ void scalars_home_kernel(double *aux) {

@@ -156,9 +156,13 @@ struct GatherLds {
 // elements are loaded for two channels at a time before they are used, and
 // a channel that maps the element onto itself (dephasing) reuses its value.
 // Each element's arithmetic is that of the file comment, in channel order.
-// scale: the step's renormalisation factor.
-template <typename T, bool SPARSE = false>
-__device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, double scale,
+// scale_of(): the step's renormalisation factor, called by every thread.
+// EARLY: call it once the tile's own elements and gather tables are in
+// flight (when it forms the trace, its loads then overlap theirs); otherwise
+// first (the values held across the call cost registers, which a factor that
+// is only read need not pay).
+template <typename T, bool SPARSE = false, bool EARLY = false, typename ScaleOf>
+__device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, ScaleOf scale_of,
                                                T (*s_re)[TD + 1], T (*s_im)[TD + 1],
                                                GatherLds *g) {
   typedef T vec4 __attribute__((ext_vector_type(4)));
@@ -175,22 +179,42 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, doub
   const int64_t u = int64_t(bi) * TD + r;
   const int64_t v0 = int64_t(bj) * TD + c0;
   const bool staged = p.n_gather > 0 && p.n_gather <= kGatherChunk;
-  if (staged) {
-    // every load unconditional (indices clamped into the table, the value
-    // replaced after), so a thread's four loads are in flight together
-    for (int e = tid; e < p.n_gather * TD; e += kDissThreads) {
-      const int j = e / TD, i = e - (e / TD) * TD;
-      const int64_t a = int64_t(bi) * TD + i, b = int64_t(bj) * TD + i;
-      const int64_t base = int64_t(j) * n;
-      const int64_t ac = a < n ? a : n - 1, bc = b < n ? b : n - 1;
-      const int32_t pa = p.pi[base + ac], pb = p.pi[base + bc];
-      const double ca = p.cg[base + ac], cb = p.cg[base + bc];
-      g->pu[j][i] = a < n ? pa : -1;
-      g->cu[j][i] = a < n ? ca : 0.0;
-      g->pv[j][i] = b < n ? pb : -1;
-      g->cv[j][i] = b < n ? cb : 0.0;
+  double scale = 0.0;
+  // the gather tables (every load unconditional: indices clamped into the
+  // table, the value replaced after)
+  static_assert(kGatherChunk * TD <= kDissThreads, "one table entry per thread");
+  const bool stager = staged && tid < p.n_gather * TD;
+  const int sj = tid / TD, si = tid - (tid / TD) * TD;
+  const int64_t ta = int64_t(bi) * TD + si, tb = int64_t(bj) * TD + si;
+  int32_t pa = -1, pb = -1;
+  double ca = 0.0, cb = 0.0;
+  if constexpr (EARLY) {
+    // one entry per thread, held in registers across the factor
+    if (stager) {
+      const int64_t base = int64_t(sj) * n;
+      const int64_t ac = ta < n ? ta : n - 1, bc = tb < n ? tb : n - 1;
+      pa = p.pi[base + ac];
+      pb = p.pi[base + bc];
+      ca = p.cg[base + ac];
+      cb = p.cg[base + bc];
     }
-    __syncthreads();
+  } else {
+    scale = scale_of();
+    if (staged) {
+      for (int e = tid; e < p.n_gather * TD; e += kDissThreads) {
+        const int j = e / TD, i = e - (e / TD) * TD;
+        const int64_t a = int64_t(bi) * TD + i, b = int64_t(bj) * TD + i;
+        const int64_t base = int64_t(j) * n;
+        const int64_t ac = a < n ? a : n - 1, bc = b < n ? b : n - 1;
+        const int32_t la = p.pi[base + ac], lb = p.pi[base + bc];
+        const double da = p.cg[base + ac], db = p.cg[base + bc];
+        g->pu[j][i] = a < n ? la : -1;
+        g->cu[j][i] = a < n ? da : 0.0;
+        g->pv[j][i] = b < n ? lb : -1;
+        g->cv[j][i] = b < n ? db : 0.0;
+      }
+      __syncthreads();
+    }
   }
 
   // the four elements, the decay factors
@@ -223,6 +247,17 @@ __device__ __forceinline__ void dissipate_tile(const DissArgs<T> &p, int t, doub
     const double f = 1.0 - 0.5 * dt * ((ok[i] ? du : 0.0) + dv);
     xr[i] = f * (ok[i] ? double(zr[i]) : 0.0);
     xi[i] = f * (ok[i] ? double(zi[i]) : 0.0);
+  }
+
+  if constexpr (EARLY) {
+    scale = scale_of();
+    if (stager) {
+      g->pu[sj][si] = ta < n ? pa : -1;
+      g->cu[sj][si] = ta < n ? ca : 0.0;
+      g->pv[sj][si] = tb < n ? pb : -1;
+      g->cv[sj][si] = tb < n ? cb : 0.0;
+    }
+    if (staged) __syncthreads();
   }
 
   // monomial channels (gather form)
