@@ -122,29 +122,58 @@ __global__ __launch_bounds__(kThreads, (BM == 32 && !(OPS & kBRow)) ? 5 : 1) voi
 }
 
 // C = alpha * sum_s part[tile, s] + beta * X over the split tiles: one
-// 64-thread block per (split tile, 64 * V elements).  The chunk loads are
-// issued in groups of 8 ahead of the additions, which run in chunk (k) order.
+// 64-thread block per (split tile, 64 * V elements).  The chunks are loaded
+// in groups of 16 (one group for the split counts the planner makes) and X
+// with the first group, so a block waits for one memory round trip before
+// the additions, which run in chunk (k) order.
 template <typename T, int BM, bool LOWER>
 __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
   constexpr int V = 16 / sizeof(T);
   constexpr int PER_TILE = BM * BM / (64 * V);
-  constexpr int G = 8;
+  constexpr int G = 16;
   typedef T vec __attribute__((ext_vector_type(V)));
   const int tl = blockIdx.x / PER_TILE;
   const int e = (blockIdx.x % PER_TILE) * 64 * V + threadIdx.x * V;
   int bi, bj;
   tile_coords(p.full + tl, int(p.ld / BM), LOWER, bi, bj);
-  vec sr = vec(T(0)), si = vec(T(0));
+  const int64_t o = (int64_t(bi) * BM + e / BM) * p.ld + int64_t(bj) * BM + e % BM;
+  const bool has_x = p.beta != T(0);
   const T *src = p.part + size_t(tl) * p.split * 2 * BM * BM + e;
-  for (int c0 = 0; c0 < p.split; c0 += G) {
-    vec lr[G], li[G];
+  vec lr[G], li[G];
+  auto load_group = [&](int c0) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      if (c0 + g < p.split) {
-        lr[g] = *reinterpret_cast<const vec *>(src + size_t(c0 + g) * 2 * BM * BM);
-        li[g] = *reinterpret_cast<const vec *>(src + size_t(c0 + g) * 2 * BM * BM + BM * BM);
-      }
+      // every load unconditional (a chunk past the last re-reads it; its
+      // value is not added), so they are in flight together
+      const int c = c0 + g < p.split ? c0 + g : p.split - 1;
+      lr[g] = *reinterpret_cast<const vec *>(src + size_t(c) * 2 * BM * BM);
+      li[g] = *reinterpret_cast<const vec *>(src + size_t(c) * 2 * BM * BM + BM * BM);
     }
+  };
+  load_group(0);
+  // X behind the first group (one wait covers both), before any store (see
+  // epi_load_x)
+  T xr[V], xi[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) epi_load_x(p, has_x, o + v, xr[v], xi[v]);
+  // the folded step's decay rates of the row and the V columns, loaded with
+  // them too (indices clamped, the values chosen at use)
+  const int rl = e / BM;
+  const int64_t row = int64_t(bi) * BM + rl;
+  double fu = 0.0, fv[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) fv[v] = 0.0;
+  if (p.fold_d && p.fold_n > 0) {
+    const int64_t last = p.fold_n - 1;
+    fu = p.fold_d[row < last ? row : last];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int64_t col = int64_t(bj) * BM + e % BM + v;
+      fv[v] = p.fold_d[col < last ? col : last];
+    }
+  }
+  vec sr = vec(T(0)), si = vec(T(0));
+  for (int c0 = 0;;) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (c0 + g < p.split) {
@@ -152,14 +181,12 @@ __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
         si += li[g];
       }
     }
+    c0 += G;
+    if (c0 >= p.split) break;
+    load_group(c0);
   }
-  const int64_t o = (int64_t(bi) * BM + e / BM) * p.ld + int64_t(bj) * BM + e % BM;
-  const bool has_x = p.beta != T(0);
   const bool scaled = p.scale != nullptr;
   const double sc = scaled ? *p.scale : 1.0;
-  T xr[V], xi[V];   // X loaded before any store (see epi_load_x)
-#pragma unroll
-  for (int v = 0; v < V; ++v) epi_load_x(p, has_x, o + v, xr[v], xi[v]);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     T vr, vi;
@@ -170,12 +197,12 @@ __global__ __launch_bounds__(64) void split_reduce_kernel(CgemmArgs<T> p) {
       continue;
     }
     // folded decoherence step (as fold_elem), mirror written directly
-    const int rl = e / BM, cl = e % BM + v;
+    const int cl = e % BM + v;
     if (bi == bj && cl > rl) continue;
-    const int64_t row = int64_t(bi) * BM + rl, col = int64_t(bj) * BM + cl;
+    const int64_t col = int64_t(bj) * BM + cl;
     const double zr = double(vr), zi = double(vi);
-    const double du = row < p.fold_n ? p.fold_d[row] : 0.0;
-    const double dv = col < p.fold_n ? p.fold_d[col] : 0.0;
+    const double du = row < p.fold_n ? fu : 0.0;
+    const double dv = col < p.fold_n ? fv[v] : 0.0;
     const double f = 1.0 - 0.5 * p.fold_dt * (du + dv);
     double xr = f * zr, xi = f * zi;
     if (row == col) {
