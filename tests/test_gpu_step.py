@@ -392,6 +392,47 @@ def test_tail_split_of_the_lower_product(precision, tol):
     assert abs(sa - sb) < 1e-12
 
 
+@pytest.mark.parametrize("precision,tol,tiles", [("fp32", 1e-5, (64, 64)), ("bf16x3", 1e-5, (64, 64)),
+                                                ("fp64", 1e-12, (64, 64))])
+def test_tail_split_in_two_reduce_groups(precision, tol, tiles):
+    """N = 2862 lattice (ld = 2880, 45 tile rows of 64, folded steps): the
+    lower-triangle product has 1035 tiles, 11 past the last full wave of 256
+    compute units, cut into 23 k-chunks each, so the reduce pass sums its
+    chunks in two groups (16, then the rest) and applies the folded
+    decoherence step and mirror.  Split and unsplit steps from a dense pure
+    state differ only by the regrouped k sums."""
+    wl = dict(W.photon_lattice(27, 53, gamma=0.05), init={"kind": "haar", "seed": 9})
+    occ = P.basis(wl)
+    rho0 = W.initial_rho(wl, occ)
+    sol = P.Solver(wl, precision)
+    sol.set_tiles(*tiles)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    t = sol.ld // 64
+    tail = (t * (t + 1) // 2) % cus
+    kt = 32 if precision == "bf16x3" else 16
+    chunks = min(cus // tail, sol.ld // kt) if tail else 0
+    if chunks <= 16:
+        sol.close()
+        pytest.skip(f"{cus} compute units: {chunks} chunks per tail tile, one reduce group")
+    outs = {}
+    for split in (False, True):
+        sol.set_split(split)
+        sol.set_rho(rho0)
+        print(f"two-group tail split N={sol.n} {precision} chunks={chunks} split={split}", flush=True)
+        sol.step(2)
+        sol.step(1)
+        rho, sink = sol.get_rho()
+        _, trace, _ = sol.observe()
+        outs[split] = (rho, sink, trace)
+    sol.close()
+    (a, sa, ta), (b, sb, tb) = outs[False], outs[True]
+    assert not np.array_equal(a, b)          # the split really ran
+    assert np.abs(a - b).max() < tol * np.abs(a).max()
+    assert abs(sa - sb) < 1e-12
+    assert np.array_equal(b, b.conj().T)     # the mirror written by the reduce pass
+    assert abs(tb - (1.0 - sb)) < TRACE_TOL[precision]
+
+
 @pytest.mark.parametrize("precision,tol,tiles", [("fp64", 1e-12, None), ("fp32", 1e-5, None),
                                                 ("fp64", 1e-12, (64, 64)),
                                                 ("bf16x3", 1e-5, None)])
